@@ -1,0 +1,727 @@
+/*
+ * CPU oracle for the double-grid lattice-regularized diffusion Monte Carlo
+ * (LRDMC) projection step of Nakano, Maezono & Sorella, arXiv:1909.01589.
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU
+ * baseline of the benchmark load this file.  It shares no code, header or
+ * table with the HIP library.
+ *
+ * Plain, slow, FP64.  Each quantity is computed from its definition:
+ *   - Psi(x) = det A_up * det A_dn * exp(J), determinants by LU with partial
+ *     pivoting, J summed over all pairs;
+ *   - every move ratio Psi(x')/Psi(x) recomputes the moved spin's
+ *     determinant from scratch and the whole Jastrow factor (no
+ *     Sherman-Morrison, no incremental updates);
+ *   - the local energy uses the textbook analytic derivatives;
+ *   - cumulative sums are sequential, left to right.
+ *
+ * Method passages (paper numbering):
+ *   main text Eq. (1): Laplacian split into a small-spacing part weighted by
+ *     p and a large-spacing part weighted by 1-p;
+ *   main text Eq. (3): Gaussian switch p(r) around the nearest heavy nucleus;
+ *   "Application to large systems": R_c over the heaviest nuclei only.
+ * The rest (stencil, regularized potential, fixed-node rule, continuous-time
+ * projection, reconfiguration) is the standard LRDMC the paper cites
+ * (Casula, Filippi & Sorella 2005), read as listed in the design notes.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int32_t n_nuc;
+    const double *Z;          /* [n_nuc] */
+    const double *R;          /* [n_nuc][3] */
+    int32_t n_up, n_dn;
+    int32_t n_shell;
+    const int32_t *shell_nuc; /* [n_shell] */
+    const int32_t *shell_l;   /* [n_shell], 0..2 */
+    const double *shell_alpha;/* [n_shell] */
+    int32_t n_orb;
+    const double *mo;         /* [K][n_orb] */
+    double b_ee, b_en;
+} orc_system;
+
+typedef struct {
+    double a, a_prime, r_c, z_heavy, tau;
+    uint64_t seed;
+    int32_t rotate;
+    int32_t pad;
+} orc_params;
+
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ESINGULAR = -2, ORC_ENONFINITE = -3, ORC_ENOMEM = -4 };
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11), from its definition. */
+
+static void philox_round(uint64_t c[4], const uint64_t k[2])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    unsigned __int128 p0 = (unsigned __int128)M0 * c[0];
+    unsigned __int128 p1 = (unsigned __int128)M1 * c[2];
+    uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+    uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+    uint64_t n0 = hi1 ^ c[1] ^ k[0];
+    uint64_t n1 = lo1;
+    uint64_t n2 = hi0 ^ c[3] ^ k[1];
+    uint64_t n3 = lo0;
+    c[0] = n0; c[1] = n1; c[2] = n2; c[3] = n3;
+}
+
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    uint64_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint64_t k[2] = {key[0], key[1]};
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k[0] += 0x9E3779B97F4A7C15ULL;
+            k[1] += 0xBB67AE8584CAA73BULL;
+        }
+        philox_round(c, k);
+    }
+    for (int i = 0; i < 4; ++i) out[i] = c[i];
+}
+
+/* Uniform in (0,1): top 53 bits, centred in their interval. */
+double orc_u01(uint64_t x)
+{
+    return ((double)(x >> 11) + 0.5) * 0x1.0p-53;
+}
+
+/* Four uniforms for counter (slot, generation, iteration, purpose). */
+void orc_draw(uint64_t seed, uint64_t slot, uint64_t gen, uint64_t iter,
+              uint64_t purpose, double u[4])
+{
+    uint64_t ctr[4] = {slot, gen, iter, purpose}, key[2] = {seed, 0}, o[4];
+    orc_philox4x64_10(ctr, key, o);
+    for (int i = 0; i < 4; ++i) u[i] = orc_u01(o[i]);
+}
+
+/* Uniform random rotation from three uniforms (Shoemake, Graphics Gems III,
+ * "Uniform random rotations").  Rm is row-major; its columns are the three
+ * lattice axes e_1, e_2, e_3. */
+void orc_rotation(const double u[3], double Rm[9])
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    double r1 = sqrt(1.0 - u[0]), r2 = sqrt(u[0]);
+    double t1 = two_pi * u[1], t2 = two_pi * u[2];
+    double x = sin(t1) * r1, y = cos(t1) * r1, z = sin(t2) * r2, w = cos(t2) * r2;
+    Rm[0] = 1.0 - 2.0 * (y * y + z * z);
+    Rm[1] = 2.0 * (x * y - w * z);
+    Rm[2] = 2.0 * (x * z + w * y);
+    Rm[3] = 2.0 * (x * y + w * z);
+    Rm[4] = 1.0 - 2.0 * (x * x + z * z);
+    Rm[5] = 2.0 * (y * z - w * x);
+    Rm[6] = 2.0 * (x * z - w * y);
+    Rm[7] = 2.0 * (y * z + w * x);
+    Rm[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Basis and orbitals                                                         */
+
+int orc_nbasis(const orc_system *s)
+{
+    int K = 0;
+    for (int q = 0; q < s->n_shell; ++q) K += 2 * s->shell_l[q] + 1;
+    return K;
+}
+
+/* Polynomial parts of one shell at displacement d: values P[c], gradients
+ * dP[c][3] and Laplacians lP[c].  l=2 uses the five real harmonic forms
+ * xy, yz, zx, x^2-y^2, 2z^2-x^2-y^2. */
+static int shell_poly(int l, const double d[3], double *P, double (*dP)[3], double *lP)
+{
+    double x = d[0], y = d[1], z = d[2];
+    if (l == 0) {
+        P[0] = 1.0; dP[0][0] = dP[0][1] = dP[0][2] = 0.0; lP[0] = 0.0;
+        return 1;
+    }
+    if (l == 1) {
+        for (int c = 0; c < 3; ++c) {
+            P[c] = d[c];
+            dP[c][0] = dP[c][1] = dP[c][2] = 0.0;
+            dP[c][c] = 1.0;
+            lP[c] = 0.0;
+        }
+        return 3;
+    }
+    /* l == 2 */
+    P[0] = x * y;  dP[0][0] = y;   dP[0][1] = x;  dP[0][2] = 0;   lP[0] = 0.0;
+    P[1] = y * z;  dP[1][0] = 0;   dP[1][1] = z;  dP[1][2] = y;   lP[1] = 0.0;
+    P[2] = z * x;  dP[2][0] = z;   dP[2][1] = 0;  dP[2][2] = x;   lP[2] = 0.0;
+    P[3] = x * x - y * y;
+    dP[3][0] = 2 * x; dP[3][1] = -2 * y; dP[3][2] = 0;  lP[3] = 2.0 - 2.0;
+    P[4] = 2 * z * z - x * x - y * y;
+    dP[4][0] = -2 * x; dP[4][1] = -2 * y; dP[4][2] = 4 * z; lP[4] = 4.0 - 2.0 - 2.0;
+    return 5;
+}
+
+/* g(r) = P(d) e^{-alpha d^2}; grad g = (grad P - 2 alpha d P) e;
+ * lap g = (lap P - 4 alpha d.grad P + (4 alpha^2 d^2 - 6 alpha) P) e. */
+void orc_basis(const orc_system *s, const double r[3], double *val, double *grad, double *lap)
+{
+    int mu = 0;
+    for (int q = 0; q < s->n_shell; ++q) {
+        const double *Rn = s->R + 3 * s->shell_nuc[q];
+        double d[3] = {r[0] - Rn[0], r[1] - Rn[1], r[2] - Rn[2]};
+        double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        double al = s->shell_alpha[q];
+        double e = exp(-al * d2);
+        double P[5], dP[5][3], lP[5];
+        int nc = shell_poly(s->shell_l[q], d, P, dP, lP);
+        for (int c = 0; c < nc; ++c, ++mu) {
+            double ddotgP = d[0] * dP[c][0] + d[1] * dP[c][1] + d[2] * dP[c][2];
+            if (val) val[mu] = P[c] * e;
+            if (grad)
+                for (int k = 0; k < 3; ++k) grad[3 * mu + k] = (dP[c][k] - 2.0 * al * d[k] * P[c]) * e;
+            if (lap)
+                lap[mu] = (lP[c] - 4.0 * al * ddotgP + (4.0 * al * al * d2 - 6.0 * al) * P[c]) * e;
+        }
+    }
+}
+
+/* phi_j(r) = sum_mu C[mu][j] g_mu(r) for j < n; optional gradients and
+ * Laplacians. */
+static void orbitals_at(const orc_system *s, const double r[3], int n,
+                        double *phi, double *dphi, double *lphi, double *work)
+{
+    int K = orc_nbasis(s);
+    double *g = work, *gg = work + K, *lg = work + 4 * K;
+    orc_basis(s, r, g, dphi ? gg : NULL, lphi ? lg : NULL);
+    for (int j = 0; j < n; ++j) {
+        double v = 0, gx = 0, gy = 0, gz = 0, l = 0;
+        for (int mu = 0; mu < K; ++mu) {
+            double c = s->mo[(size_t)mu * s->n_orb + j];
+            v += c * g[mu];
+            if (dphi) { gx += c * gg[3 * mu]; gy += c * gg[3 * mu + 1]; gz += c * gg[3 * mu + 2]; }
+            if (lphi) l += c * lg[mu];
+        }
+        phi[j] = v;
+        if (dphi) { dphi[3 * j] = gx; dphi[3 * j + 1] = gy; dphi[3 * j + 2] = gz; }
+        if (lphi) lphi[j] = l;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense linear algebra: LU with partial pivoting (row interchanges).        */
+
+/* In place; returns log|det|, sets *sign (0 if singular). */
+static double lu_logdet(double *A, int n, int *sign)
+{
+    int sg = 1;
+    double la = 0.0;
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        double best = fabs(A[c * n + c]);
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(A[r * n + c]) > best) { best = fabs(A[r * n + c]); p = r; }
+        if (!(best > 0.0)) { *sign = 0; return -INFINITY; }
+        if (p != c) {
+            for (int k = 0; k < n; ++k) { double t = A[c * n + k]; A[c * n + k] = A[p * n + k]; A[p * n + k] = t; }
+            sg = -sg;
+        }
+        double piv = A[c * n + c];
+        if (piv < 0) sg = -sg;
+        la += log(fabs(piv));
+        for (int r = c + 1; r < n; ++r) {
+            double f = A[r * n + c] / piv;
+            A[r * n + c] = f;
+            for (int k = c + 1; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+        }
+    }
+    *sign = sg;
+    return la;
+}
+
+/* Inverse by LU: solves A X = I column by column.  Returns 0 or -2. */
+static int lu_inverse(const double *A, int n, double *X, double *work, int *perm)
+{
+    double *L = work;
+    memcpy(L, A, sizeof(double) * n * n);
+    for (int i = 0; i < n; ++i) perm[i] = i;
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        double best = fabs(L[c * n + c]);
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(L[r * n + c]) > best) { best = fabs(L[r * n + c]); p = r; }
+        if (!(best > 0.0) || !isfinite(best)) return ORC_ESINGULAR;
+        if (p != c) {
+            for (int k = 0; k < n; ++k) { double t = L[c * n + k]; L[c * n + k] = L[p * n + k]; L[p * n + k] = t; }
+            int t = perm[c]; perm[c] = perm[p]; perm[p] = t;
+        }
+        for (int r = c + 1; r < n; ++r) {
+            double f = L[r * n + c] / L[c * n + c];
+            L[r * n + c] = f;
+            for (int k = c + 1; k < n; ++k) L[r * n + k] -= f * L[c * n + k];
+        }
+    }
+    for (int col = 0; col < n; ++col) {
+        /* b = P e_col */
+        double *x = X; /* solve into column col of X (row-major X[row][col]) */
+        double y[64];
+        for (int r = 0; r < n; ++r) y[r] = (perm[r] == col) ? 1.0 : 0.0;
+        for (int r = 0; r < n; ++r)
+            for (int k = 0; k < r; ++k) y[r] -= L[r * n + k] * y[k];
+        for (int r = n - 1; r >= 0; --r) {
+            double v = y[r];
+            for (int k = r + 1; k < n; ++k) v -= L[r * n + k] * x[k * n + col];
+            x[r * n + col] = v / L[r * n + r];
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pade Jastrow: J = sum_{i<j} c_ij r/(1+b_ee r) - sum_{i,I} Z_I r/(1+b_en r),
+ * c = 1/2 antiparallel, 1/4 parallel (exact cusps).                          */
+
+static int spin_of(const orc_system *s, int i) { return i < s->n_up ? 0 : 1; }
+
+static double dist(const double *a, const double *b)
+{
+    double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+    return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+double orc_jastrow(const orc_system *s, const double *pos)
+{
+    int N = s->n_up + s->n_dn;
+    double J = 0.0;
+    for (int i = 0; i < N; ++i) {
+        for (int j = i + 1; j < N; ++j) {
+            double c = (spin_of(s, i) == spin_of(s, j)) ? 0.25 : 0.5;
+            double r = dist(pos + 3 * i, pos + 3 * j);
+            J += c * r / (1.0 + s->b_ee * r);
+        }
+        for (int I = 0; I < s->n_nuc; ++I) {
+            double r = dist(pos + 3 * i, s->R + 3 * I);
+            J -= s->Z[I] * r / (1.0 + s->b_en * r);
+        }
+    }
+    return J;
+}
+
+/* grad_i J and lap_i J. */
+static void jastrow_derivs(const orc_system *s, const double *pos, int i, double g[3], double *lap)
+{
+    int N = s->n_up + s->n_dn;
+    g[0] = g[1] = g[2] = 0.0;
+    double L = 0.0;
+    for (int j = 0; j < N; ++j) {
+        if (j == i) continue;
+        double c = (spin_of(s, i) == spin_of(s, j)) ? 0.25 : 0.5;
+        double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1], pos[3 * i + 2] - pos[3 * j + 2]};
+        double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double q = 1.0 + s->b_ee * r;
+        double up = c / (q * q);                 /* u'(r)  */
+        double upp = -2.0 * c * s->b_ee / (q * q * q); /* u''(r) */
+        for (int k = 0; k < 3; ++k) g[k] += up * d[k] / r;
+        L += upp + 2.0 * up / r;
+    }
+    for (int I = 0; I < s->n_nuc; ++I) {
+        double d[3] = {pos[3 * i] - s->R[3 * I], pos[3 * i + 1] - s->R[3 * I + 1], pos[3 * i + 2] - s->R[3 * I + 2]};
+        double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double q = 1.0 + s->b_en * r;
+        double Z = s->Z[I];
+        double up = -Z / (q * q);
+        double upp = 2.0 * Z * s->b_en / (q * q * q);
+        for (int k = 0; k < 3; ++k) g[k] += up * d[k] / r;
+        L += upp + 2.0 * up / r;
+    }
+    *lap = L;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Wave function                                                              */
+
+static int nspin(const orc_system *s, int sg) { return sg == 0 ? s->n_up : s->n_dn; }
+static int first_of(const orc_system *s, int sg) { return sg == 0 ? 0 : s->n_up; }
+
+/* Slater matrix of one spin: A[i][j] = phi_j(r_i), i, j < n_sigma. */
+static void slater_matrix(const orc_system *s, const double *pos, int sg, double *A, double *work)
+{
+    int n = nspin(s, sg), i0 = first_of(s, sg);
+    for (int i = 0; i < n; ++i) orbitals_at(s, pos + 3 * (i0 + i), n, A + i * n, NULL, NULL, work);
+}
+
+/* 5K doubles for orbitals_at, then room for one n_sigma x n_sigma matrix. */
+static double *scratch(const orc_system *s)
+{
+    int K = orc_nbasis(s), N = s->n_up + s->n_dn;
+    return (double *)malloc(sizeof(double) * ((size_t)5 * K + (size_t)N * N + 1));
+}
+
+/* log|Psi| and sign(Psi). */
+int orc_log_psi(const orc_system *s, const double *pos, double *logabs, int *sign)
+{
+    int N = s->n_up + s->n_dn;
+    double *w = scratch(s);
+    double *A = w + 5 * orc_nbasis(s);
+    if (!w) return ORC_ENOMEM;
+    double la = 0.0;
+    int sg_total = 1;
+    for (int sg = 0; sg < 2; ++sg) {
+        int n = nspin(s, sg);
+        if (n == 0) continue;
+        slater_matrix(s, pos, sg, A, w);
+        int sgn;
+        la += lu_logdet(A, n, &sgn);
+        sg_total *= sgn;
+    }
+    la += orc_jastrow(s, pos);
+    (void)N;
+    free(w);
+    *logabs = la;
+    *sign = sg_total;
+    return sg_total == 0 ? ORC_ESINGULAR : ORC_OK;
+}
+
+/* Coulomb potential: e-e, e-n and n-n terms. */
+double orc_potential(const orc_system *s, const double *pos)
+{
+    int N = s->n_up + s->n_dn;
+    double V = 0.0;
+    for (int i = 0; i < N; ++i) {
+        for (int j = i + 1; j < N; ++j) V += 1.0 / dist(pos + 3 * i, pos + 3 * j);
+        for (int I = 0; I < s->n_nuc; ++I) V -= s->Z[I] / dist(pos + 3 * i, s->R + 3 * I);
+    }
+    for (int I = 0; I < s->n_nuc; ++I)
+        for (int J = I + 1; J < s->n_nuc; ++J) V += s->Z[I] * s->Z[J] / dist(s->R + 3 * I, s->R + 3 * J);
+    return V;
+}
+
+/* Analytic local energy E_L = -1/2 sum_i lap_i Psi / Psi + V.
+ * lap_i Psi/Psi = lap_i D/D + 2 grad_i D/D . grad_i J + lap_i J + |grad_i J|^2,
+ * grad_i D/D = sum_j grad phi_j(r_i) Ainv[j][i], lap likewise.
+ * Outputs: e_l, lap_psi (sum_i lap_i Psi/Psi), v (potential). */
+int orc_local_energy(const orc_system *s, const double *pos, double *e_l, double *lap_psi, double *v)
+{
+    int K = orc_nbasis(s), nmax = s->n_up > s->n_dn ? s->n_up : s->n_dn;
+    if (nmax > 64) return ORC_EINVAL;
+    size_t n2 = (size_t)nmax * nmax;
+    double *w = (double *)malloc(sizeof(double) * (5 * (size_t)K + 7 * n2 + 1));
+    if (!w) return ORC_ENOMEM;
+    double *A = w + 5 * K;   /* [n][n]    phi_j(r_i)      */
+    double *Ai = A + n2;     /* [n][n]    inverse         */
+    double *LUw = Ai + n2;   /* [n][n]    LU workspace    */
+    double *dA = LUw + n2;   /* [n][n][3] grad phi_j(r_i) */
+    double *lA = dA + 3 * n2;/* [n][n]    lap phi_j(r_i)  */
+    int perm[64];
+    double total = 0.0;
+    int rc = ORC_OK;
+    for (int sg = 0; sg < 2 && rc == ORC_OK; ++sg) {
+        int n = nspin(s, sg), i0 = first_of(s, sg);
+        if (n == 0) continue;
+        for (int i = 0; i < n; ++i)
+            orbitals_at(s, pos + 3 * (i0 + i), n, A + i * n, dA + 3 * i * n, lA + i * n, w);
+        rc = lu_inverse(A, n, Ai, LUw, perm);
+        if (rc) break;
+        for (int i = 0; i < n; ++i) {
+            double gD[3] = {0, 0, 0}, lD = 0.0;
+            for (int j = 0; j < n; ++j) {
+                double inv = Ai[j * n + i];
+                for (int k = 0; k < 3; ++k) gD[k] += dA[3 * (i * n + j) + k] * inv;
+                lD += lA[i * n + j] * inv;
+            }
+            double gJ[3], lJ;
+            jastrow_derivs(s, pos, i0 + i, gJ, &lJ);
+            total += lD + 2.0 * (gD[0] * gJ[0] + gD[1] * gJ[1] + gD[2] * gJ[2]) + lJ
+                     + gJ[0] * gJ[0] + gJ[1] * gJ[1] + gJ[2] * gJ[2];
+        }
+    }
+    free(w);
+    if (rc) return rc;
+    double V = orc_potential(s, pos);
+    if (lap_psi) *lap_psi = total;
+    if (v) *v = V;
+    *e_l = -0.5 * total + V;
+    return isfinite(*e_l) ? ORC_OK : ORC_ENONFINITE;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Lattice moves (main text Eq. (1) and Eq. (3))                              */
+
+/* Switch p at point x: Gaussian of the distance to the nearest nucleus with
+ * Z_I >= z_heavy (lowest index wins a tie). */
+double orc_p_switch(const orc_system *s, const orc_params *p, const double x[3])
+{
+    int best = -1;
+    double bd2 = 0.0;
+    for (int I = 0; I < s->n_nuc; ++I) {
+        if (s->Z[I] < p->z_heavy) continue;
+        double dx = x[0] - s->R[3 * I], dy = x[1] - s->R[3 * I + 1], dz = x[2] - s->R[3 * I + 2];
+        double d2 = dx * dx + dy * dy + dz * dz;
+        if (best < 0 || d2 < bd2) { best = I; bd2 = d2; }
+    }
+    if (best < 0) return 0.0;
+    return exp(-bd2 / (2.0 * p->r_c * p->r_c));
+}
+
+/* Move m = 12 i + 6 g + dir of electron i: grid g (0: spacing a weighted by
+ * p, 1: spacing a' weighted by 1-p), axis dir/2, sign + for even dir.
+ * New position r' = r_i + sign h e_axis; p is taken at the midpoint
+ * r_i + sign (h/2) e_axis; coefficient k = p/a^2 or (1-p)/a'^2. */
+void orc_move(const orc_system *s, const orc_params *p, const double *pos, const double Rm[9],
+              int m, double rp[3], double *k)
+{
+    int i = m / 12, g = (m / 6) % 2, dir = m % 6, ax = dir / 2;
+    double sgn = (dir % 2 == 0) ? 1.0 : -1.0;
+    double h = (g == 0) ? p->a : p->a_prime;
+    double e[3] = {Rm[ax], Rm[3 + ax], Rm[6 + ax]};
+    double mid[3];
+    for (int c = 0; c < 3; ++c) {
+        rp[c] = pos[3 * i + c] + sgn * h * e[c];
+        mid[c] = pos[3 * i + c] + sgn * (0.5 * h) * e[c];
+    }
+    double pv = orc_p_switch(s, p, mid);
+    *k = (g == 0) ? pv / (p->a * p->a) : (1.0 - pv) / (p->a_prime * p->a_prime);
+}
+
+/* Psi(x')/Psi(x) for x' = x with electron i at rp: the moved spin's
+ * determinant recomputed by LU, the whole Jastrow recomputed. */
+static int ratio_full(const orc_system *s, const double *pos, int i, const double rp[3],
+                      const double *A_cur, double logdet_cur, int sign_cur, double J_cur,
+                      double *pos_tmp, double *A_tmp, double *work, double *out)
+{
+    int sg = spin_of(s, i), n = nspin(s, sg), i0 = first_of(s, sg);
+    memcpy(A_tmp, A_cur, sizeof(double) * n * n);
+    orbitals_at(s, rp, n, A_tmp + (i - i0) * n, NULL, NULL, work);
+    int sgn;
+    double ld = lu_logdet(A_tmp, n, &sgn);
+    int N = s->n_up + s->n_dn;
+    memcpy(pos_tmp, pos, sizeof(double) * 3 * N);
+    pos_tmp[3 * i] = rp[0]; pos_tmp[3 * i + 1] = rp[1]; pos_tmp[3 * i + 2] = rp[2];
+    double Jn = orc_jastrow(s, pos_tmp);
+    if (sgn == 0) { *out = 0.0; return ORC_OK; }
+    *out = (double)(sgn * sign_cur) * exp((ld - logdet_cur) + (Jn - J_cur));
+    return ORC_OK;
+}
+
+/* Table of all M = 12N moves at fixed x: ratios rho[m] and coefficients k[m].
+ * diag (optional, 10 doubles):
+ *   [0] E_L analytic          [1] e_L lattice-assembled
+ *   [2] L^a = sum k (rho-1)   [3] sum_i lap_i Psi/Psi
+ *   [4] V^a                   [5] V_sf
+ *   [6] Delta = sum T         [7] V
+ *   [8] sum k                 [9] unused
+ * V^a = V + (L^a - lap Psi/Psi)/2; V_sf = -1/2 sum_{rho<0} k rho;
+ * T = k max(rho,0)/2; e_L = sum k/2 + V^a + V_sf - Delta. */
+int orc_eval_moves(const orc_system *s, const orc_params *p, const double *pos, const double Rm[9],
+                   double *rho, double *kout, double *diag)
+{
+    int N = s->n_up + s->n_dn, K = orc_nbasis(s), M = 12 * N;
+    int nmax = s->n_up > s->n_dn ? s->n_up : s->n_dn;
+    size_t n2 = (size_t)nmax * nmax;
+    double *w = (double *)malloc(sizeof(double) * (5 * (size_t)K + 3 * n2 + 3 * (size_t)N + 1));
+    if (!w) return ORC_ENOMEM;
+    double *A[2] = {w + 5 * K, w + 5 * K + n2};  /* Slater matrices of x */
+    double *Atmp = A[1] + n2;                     /* moved-spin matrix    */
+    double *pos_tmp = Atmp + n2;                  /* x'                   */
+    double ld[2] = {0, 0};
+    int sgn[2] = {1, 1};
+    int rc = ORC_OK;
+    for (int sg = 0; sg < 2; ++sg) {
+        int n = nspin(s, sg);
+        if (n == 0) continue;
+        slater_matrix(s, pos, sg, A[sg], w);
+        memcpy(Atmp, A[sg], sizeof(double) * n * n);
+        ld[sg] = lu_logdet(Atmp, n, &sgn[sg]);
+        if (sgn[sg] == 0) rc = ORC_ESINGULAR;
+    }
+    if (rc) { free(w); return rc; }
+    double J = orc_jastrow(s, pos);
+    double sumk = 0, La = 0, Vsf = 0, Delta = 0;
+    for (int m = 0; m < M; ++m) {
+        double rp[3], k;
+        int i = m / 12, sg = spin_of(s, i);
+        orc_move(s, p, pos, Rm, m, rp, &k);
+        double r;
+        ratio_full(s, pos, i, rp, A[sg], ld[sg], sgn[sg], J, pos_tmp, Atmp, w, &r);
+        rho[m] = r;
+        kout[m] = k;
+        sumk += k;
+        La += k * (r - 1.0);
+        if (r < 0) Vsf += -0.5 * k * r;
+        Delta += 0.5 * k * (r > 0 ? r : 0.0);
+    }
+    free(w);
+    double EL, lap, V;
+    rc = orc_local_energy(s, pos, &EL, &lap, &V);
+    if (diag) {
+        double Va = V + 0.5 * (La - lap);
+        diag[0] = EL;
+        diag[1] = 0.5 * sumk + Va + Vsf - Delta;
+        diag[2] = La;
+        diag[3] = lap;
+        diag[4] = Va;
+        diag[5] = Vsf;
+        diag[6] = Delta;
+        diag[7] = V;
+        diag[8] = sumk;
+        diag[9] = 0.0;
+    }
+    return rc;
+}
+
+/* Heat-bath choice: first m with C_m > u2 * Delta, C the sequential
+ * left-to-right cumulative sum of T and Delta = C_{M-1}.  If rounding leaves
+ * no such m, the last m with T_m > 0.  Returns -1 when Delta == 0. */
+int orc_select(const double *T, int M, double u2)
+{
+    double D = 0.0;
+    for (int m = 0; m < M; ++m) D += T[m];
+    if (!(D > 0.0)) return -1;
+    double thr = u2 * D, C = 0.0;
+    for (int m = 0; m < M; ++m) {
+        C += T[m];
+        if (C > thr) return m;
+    }
+    for (int m = M - 1; m >= 0; --m)
+        if (T[m] > 0.0) return m;
+    return -1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Continuous-time projection of one walker over one generation.              */
+/* Holding time tau_d = -ln(u1)/Delta(x); weight factor exp(-tau_d e_L(x));
+ * move chosen with probability T_m/Delta.  E_T = 0.  A tie tau_d == tau_left
+ * counts as staying; Delta == 0 stays for the remaining time.
+ * Random numbers: iteration t of generation gen of slot s draws the
+ * rotation from counter (s, gen, t, 1) and (u1, u2) from (s, gen, t, 0).
+ * pos is updated in place; log_w starts at 0. */
+int orc_generation(const orc_system *s, const orc_params *p, uint64_t slot, uint64_t gen,
+                   double *pos, double *log_w, double *e_l, int64_t *n_moves)
+{
+    int N = s->n_up + s->n_dn, M = 12 * N;
+    double *rho = (double *)malloc(sizeof(double) * 3 * M);
+    if (!rho) return ORC_ENOMEM;
+    double *k = rho + M, *T = k + M;
+    double tl = p->tau, lw = 0.0, EL, lap, V;
+    int64_t moves = 0;
+    int rc = orc_local_energy(s, pos, &EL, &lap, &V);
+    for (uint64_t it = 0; rc == ORC_OK; ++it) {
+        double Rm[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, u[4];
+        if (p->rotate) {
+            orc_draw(p->seed, slot, gen, it, 1, u);
+            orc_rotation(u, Rm);
+        }
+        rc = orc_eval_moves(s, p, pos, Rm, rho, k, NULL);
+        if (rc) break;
+        double D = 0.0;
+        for (int m = 0; m < M; ++m) {
+            T[m] = 0.5 * k[m] * (rho[m] > 0 ? rho[m] : 0.0);
+            D += T[m];
+        }
+        orc_draw(p->seed, slot, gen, it, 0, u);
+        if (!(D > 0.0)) { lw -= tl * EL; break; }
+        double td = -log(u[0]) / D;
+        if (td >= tl) { lw -= tl * EL; break; }
+        lw -= td * EL;
+        tl -= td;
+        int ms = orc_select(T, M, u[1]);
+        double rp[3], kk;
+        orc_move(s, p, pos, Rm, ms, rp, &kk);
+        int i = ms / 12;
+        pos[3 * i] = rp[0]; pos[3 * i + 1] = rp[1]; pos[3 * i + 2] = rp[2];
+        ++moves;
+        rc = orc_local_energy(s, pos, &EL, &lap, &V);
+    }
+    free(rho);
+    if (rc == ORC_OK && !(isfinite(lw) && isfinite(EL))) rc = ORC_ENONFINITE;
+    *log_w = lw;
+    *e_l = EL;
+    *n_moves = moves;
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Reconfiguration at fixed population (systematic resampling).              */
+/* w_j = exp(log_w_j - max); Ws = sum w; ebar = sum w e / Ws;
+ * log_wbar = log(Ws/W) + max; t_s = (s + xi) * (Ws/W);
+ * idx_s = first j with CW_j > t_s (CW sequential), clamped to W-1. */
+int orc_reconfigure(const double *log_w, const double *e_l, int W, double xi,
+                    int32_t *idx, double *log_wbar, double *ebar)
+{
+    if (W < 1) return ORC_EINVAL;
+    double mx = log_w[0];
+    for (int j = 1; j < W; ++j) if (log_w[j] > mx) mx = log_w[j];
+    double *CW = (double *)malloc(sizeof(double) * W);
+    if (!CW) return ORC_ENOMEM;
+    double Ws = 0.0, ew = 0.0;
+    for (int j = 0; j < W; ++j) {
+        double w = exp(log_w[j] - mx);
+        Ws += w;
+        CW[j] = Ws;
+        if (e_l) ew += w * e_l[j];
+    }
+    if (ebar) *ebar = e_l ? ew / Ws : 0.0;
+    if (log_wbar) *log_wbar = log(Ws / (double)W) + mx;
+    double q = Ws / (double)W;
+    for (int s_ = 0; s_ < W; ++s_) {
+        double t = ((double)s_ + xi) * q;
+        int j = 0;
+        while (j < W - 1 && !(CW[j] > t)) ++j;
+        idx[s_] = j;
+    }
+    free(CW);
+    return isfinite(Ws) && Ws > 0 ? ORC_OK : ORC_ENONFINITE;
+}
+
+double orc_xi(uint64_t seed, uint64_t gen)
+{
+    double u[4];
+    orc_draw(seed, ~0ULL, gen, 0, 3, u);
+    return u[0];
+}
+
+/* Whole projection: n_gen generations of W walkers, each followed by a
+ * reconfiguration.  pos [W][N][3] in/out.  Records per generation:
+ * log_wbar, ebar, total moves; idx [n_gen][W] if non-NULL.  The per-walker
+ * state before each reconfiguration is written to walker_out (W x (3N+3):
+ * positions, log_w, e_L, moves) for the last generation if non-NULL. */
+int orc_run(const orc_system *s, const orc_params *p, int W, double *pos, uint64_t gen0, int n_gen,
+            double *log_wbar, double *ebar, int64_t *n_moves, int32_t *idx_all, int nthreads)
+{
+    int N = s->n_up + s->n_dn;
+    double *lw = (double *)malloc(sizeof(double) * 2 * W);
+    int64_t *mv = (int64_t *)malloc(sizeof(int64_t) * W);
+    int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * W);
+    double *tmp = (double *)malloc(sizeof(double) * 3 * N * (size_t)W);
+    if (!lw || !mv || !idx || !tmp) { free(lw); free(mv); free(idx); free(tmp); return ORC_ENOMEM; }
+    double *el = lw + W;
+    int rc = ORC_OK;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    for (int g = 0; g < n_gen && rc == ORC_OK; ++g) {
+        uint64_t gen = gen0 + (uint64_t)g;
+        int err = ORC_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int w = 0; w < W; ++w) {
+            int r = orc_generation(s, p, (uint64_t)w, gen, pos + 3 * N * (size_t)w, &lw[w], &el[w], &mv[w]);
+            if (r != ORC_OK) {
+#pragma omp critical
+                err = r;
+            }
+        }
+        if (err) { rc = err; break; }
+        int64_t tot = 0;
+        for (int w = 0; w < W; ++w) tot += mv[w];
+        n_moves[g] = tot;
+        rc = orc_reconfigure(lw, el, W, orc_xi(p->seed, gen), idx, &log_wbar[g], &ebar[g]);
+        if (rc) break;
+        if (idx_all) memcpy(idx_all + (size_t)g * W, idx, sizeof(int32_t) * W);
+        for (int w = 0; w < W; ++w)
+            memcpy(tmp + 3 * N * (size_t)w, pos + 3 * N * (size_t)idx[w], sizeof(double) * 3 * N);
+        memcpy(pos, tmp, sizeof(double) * 3 * N * (size_t)W);
+    }
+    free(lw); free(mv); free(idx); free(tmp);
+    return rc;
+}
