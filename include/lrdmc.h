@@ -1,0 +1,197 @@
+/*
+ * lrdmc.h -- C ABI of the double-grid lattice-regularized diffusion Monte
+ * Carlo (LRDMC) projection library for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Nakano, Maezono & Sorella, "Speeding up the ab initio diffusion
+ * Monte Carlo by a smart lattice regularization", arXiv:1909.01589.
+ *   - main text Eq. (1): the kinetic Laplacian is split into a small-spacing
+ *     part (a, weighted by p) and a large-spacing part (a', weighted by 1-p);
+ *   - main text Eq. (3): p(r) = exp(-|r - R_c|^2 / 2 r_c^2), R_c the nearest
+ *     nucleus; for molecules only the heaviest nuclei count ("Application
+ *     to large systems");
+ *   - main text Eq. (6)-(7) and supplement Eq. (S-13): the choice of r_c and
+ *     a'/a (lrdmc_spacing).
+ * The projection itself (finite-difference stencil, regularized potential,
+ * fixed-node rule, continuous-time moves, fixed-population reconfiguration)
+ * is the lattice-regularized DMC the paper builds on (its refs. Casula,
+ * Filippi & Sorella 2005; Becca & Sorella 2017).
+ *
+ * Conventions
+ *   - All floating point is FP64.  Arrays are row-major and C-contiguous.
+ *   - Host pointers: the system and parameter descriptions of lrdmc_create
+ *     (deep-copied; the caller may free them on return) and the outputs of
+ *     lrdmc_spacing.  Every other array argument is a DEVICE pointer on the
+ *     current HIP device (for instance the data pointer of a torch tensor);
+ *     the caller owns it.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Entry points
+ *     that take a stream enqueue their work on it and return after
+ *     synchronizing it, so that errors found by the kernels are reported by
+ *     the call that caused them.
+ *   - Return value 0 on success, else a negative LRDMC_E* code; the message
+ *     of the last failure of a context (with the walker index for per-walker
+ *     failures) is returned by lrdmc_last_error.  After a non-zero return no
+ *     output is promised to be complete.
+ *   - Electron order: the n_up spin-up electrons first, then n_dn spin-down.
+ *     A walker is pos[N][3], N = n_up + n_dn; W walkers are pos[W][N][3].
+ *   - Moves: electron i has M/N = 12 lattice moves, index m = 12 i + 6 g + d,
+ *     g = 0 for spacing a (weight p/a^2), g = 1 for a' (weight (1-p)/a'^2),
+ *     d = 2 axis + (0 for +, 1 for -).  p is evaluated at the midpoint of the
+ *     move.  With rotate != 0 the three axes are the columns of a uniform
+ *     random rotation drawn for every move.
+ *   - Random numbers: Philox4x64-10 with key (seed, 0) and counter
+ *     (slot, generation, iteration, purpose); purpose 0 gives (u1, u2) of a
+ *     move, 1 the rotation, 3 the resampling offset at slot 2^64-1.
+ *
+ * Thread safety: a context may be used by one host thread at a time.
+ */
+#ifndef LRDMC_H
+#define LRDMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LRDMC_OK          0
+#define LRDMC_EINVAL     -1  /* bad sizes or parameters                        */
+#define LRDMC_ESINGULAR  -2  /* a Slater matrix is singular or non-finite      */
+#define LRDMC_ENONFINITE -3  /* NaN/Inf in an energy, a weight or a position   */
+#define LRDMC_ENOMEM     -4  /* host or device allocation failed               */
+#define LRDMC_EDEVICE    -5  /* HIP runtime error                              */
+
+/* Number of per-walker diagnostics written by lrdmc_eval_moves. */
+#define LRDMC_NDIAG 9
+
+typedef struct lrdmc_ctx lrdmc_ctx;
+
+/* Trial function Psi = det A_up det A_dn exp(J).
+ * Basis: shell q is an uncontracted, unnormalized Gaussian
+ * P_l(d) exp(-alpha_q |d|^2), d = r - R[shell_nuc[q]], l = shell_l[q] in
+ * {0,1,2} giving 1, 3 or 5 functions (p: x, y, z; d: xy, yz, zx, x^2-y^2,
+ * 2z^2-x^2-y^2); K = sum of (2l+1).  Orbitals phi_j = sum_mu mo[mu][j] g_mu,
+ * mo is [K][n_orb] and shared by both spins; the spin-sigma determinant uses
+ * orbitals 0..n_sigma-1.  Jastrow (Pade):
+ * J = sum_{i<j} c_ij r_ij/(1 + b_ee r_ij) - sum_{i,I} Z_I r_iI/(1 + b_en r_iI),
+ * c_ij = 1/2 for opposite spins and 1/4 for equal spins (exact cusps). */
+typedef struct {
+    int32_t n_nuc;
+    const double *Z;            /* [n_nuc] nuclear charges                   */
+    const double *R;            /* [n_nuc][3] positions (bohr)               */
+    int32_t n_up, n_dn;
+    int32_t n_shell;
+    const int32_t *shell_nuc;   /* [n_shell]                                 */
+    const int32_t *shell_l;     /* [n_shell]                                 */
+    const double *shell_alpha;  /* [n_shell]                                 */
+    int32_t n_orb;
+    const double *mo;           /* [K][n_orb]                                */
+    double b_ee, b_en;
+} lrdmc_system;
+
+/* Lattice and projection parameters.
+ * a: small (core) spacing; a_prime: large spacing, a_prime >= a;
+ * r_c: width of the switch p (main text Eq. (3)); nuclei with Z >= z_heavy
+ * define R_c; tau: projection time per generation (1/Ha); seed: Philox key;
+ * rotate: random lattice orientation per move (0 = fixed x, y, z axes). */
+typedef struct {
+    double a, a_prime, r_c, z_heavy, tau;
+    uint64_t seed;
+    int32_t rotate;
+    int32_t reserved;           /* must be 0                                 */
+} lrdmc_params;
+
+/* Host-side parameter choice of the paper for heaviest charge Z and small
+ * spacing a: r_c(a,Z) = beta (kappa alpha^-2 + 1)/(alpha^-2 + 1) Z^(-5/7),
+ * alpha = 1/(a Z) (supplement Eq. (S-13)); N_core(r_c) from a Slater-rule
+ * atomic density (main text Eq. (7)); a' = a sqrt((Z - N_core)/N_core)
+ * (main text Eq. (6)).  The paper uses beta = 0.75, kappa = 2.5.
+ * Outputs are host pointers; n_core may be NULL.
+ * Errors: LRDMC_EINVAL for Z < 1, Z > 86, a <= 0, beta <= 0 or kappa <= 0. */
+int lrdmc_spacing(double Z, double a, double beta, double kappa,
+                  double *r_c, double *a_prime, double *n_core);
+
+/* Create a context for n_walkers walkers on the current HIP device.
+ * Deep-copies sys and prm to the device and allocates the walker state.
+ * Errors: LRDMC_EINVAL (n_walkers < 1; n_up < 1; n_dn < 0; max(n_up, n_dn)
+ * > 32; N > 64; n_orb < max(n_up, n_dn); K > 512; n_nuc < 1 or > 64; l
+ * outside 0..2; alpha < 0; a <= 0; a_prime < a; r_c <= 0; tau <= 0; no
+ * nucleus with Z >= z_heavy; reserved != 0), LRDMC_ENOMEM, LRDMC_EDEVICE. */
+int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm,
+                 int32_t n_walkers, lrdmc_ctx **out);
+
+/* Load walker positions pos[W][N][3] (device) and set the generation counter
+ * that keys the random numbers of the next projection.  Clears any pending
+ * reconfiguration.  Errors: LRDMC_EINVAL (NULL pointers). */
+int lrdmc_set_walkers(lrdmc_ctx *ctx, const double *pos, uint64_t generation, void *stream);
+
+/* One generation of projection (no reconfiguration): every walker slot s
+ * starts with log w = 0 and projection time tau and, in continuous time,
+ * waits tau_d = -ln(u1)/Delta(x), multiplies its weight by exp(-tau_d e_L(x))
+ * and moves along lattice move m with probability T_m/Delta(x), until the
+ * time is used up.  Delta(x) = sum_m T_m, T_m = k_m max(rho_m, 0)/2,
+ * rho_m = Psi(x'_m)/Psi(x) (fixed node: moves with rho_m <= 0 are dropped).
+ * If a reconfiguration is pending, slot s starts from the copy it selected.
+ * Errors: LRDMC_ESINGULAR, LRDMC_ENONFINITE (with the slot index),
+ * LRDMC_EDEVICE. */
+int lrdmc_project(lrdmc_ctx *ctx, void *stream);
+
+/* Fixed-population reconfiguration after a projection (systematic
+ * resampling with one offset xi drawn from the counter stream):
+ * w_j = exp(log w_j - max), t_s = (s + xi) sum(w)/W, idx_s = first j with
+ * cumulative weight > t_s.  Writes the generation record at the device
+ * pointers (each may be NULL): log_wbar = log(mean w) (including the max),
+ * ebar = sum w_j e_L,j / sum w_j, n_moves = total moves of the generation;
+ * idx (device, [W] int32, may be NULL).  Advances the generation counter.
+ * Errors: LRDMC_EINVAL (no projection since the last reconfiguration),
+ * LRDMC_ENONFINITE, LRDMC_EDEVICE. */
+int lrdmc_branch(lrdmc_ctx *ctx, void *stream, double *log_wbar, double *ebar,
+                 int64_t *n_moves, int32_t *idx);
+
+/* n_gen x (lrdmc_project + lrdmc_branch) without host synchronization in
+ * between.  Device outputs (each may be NULL): log_wbar[n_gen], ebar[n_gen],
+ * n_moves[n_gen], idx[n_gen][W]. */
+int lrdmc_run(lrdmc_ctx *ctx, int32_t n_gen, void *stream, double *log_wbar,
+              double *ebar, int64_t *n_moves, int32_t *idx);
+
+/* Copy the walker state to device buffers (each may be NULL): pos[W][N][3],
+ * log_w[W], e_loc[W] (analytic local energy), n_moves[W] (moves of the last
+ * projection).  After a reconfiguration, slot s holds the copy it selected,
+ * with log_w = 0 and n_moves = 0. */
+int lrdmc_get_walkers(lrdmc_ctx *ctx, double *pos, double *log_w, double *e_loc,
+                      int32_t *n_moves, void *stream);
+
+/* Evaluate the move table at frozen positions pos[W][N][3] without moving:
+ * rho[W][M] = Psi(x'_m)/Psi(x), k[W][M] = hopping coefficient of move m,
+ * M = 12 N, and diag[W][LRDMC_NDIAG] =
+ *   {E_L analytic, e_L lattice-assembled, L^a = sum_m k_m (rho_m - 1),
+ *    sum_i lap_i Psi/Psi, V^a, V_sf, Delta, V, sum_m k_m},
+ * with V^a = V + (L^a - lap Psi/Psi)/2, V_sf = -1/2 sum_{rho<0} k rho and
+ * e_L = sum k/2 + V^a + V_sf - Delta.  The axes are those of iteration 0 of
+ * the current generation (identity if rotate == 0).  Any output may be NULL.
+ * Errors: LRDMC_ESINGULAR, LRDMC_ENONFINITE, LRDMC_EDEVICE. */
+int lrdmc_eval_moves(lrdmc_ctx *ctx, const double *pos, double *rho, double *k,
+                     double *diag, void *stream);
+
+/* Stateless reconfiguration of W walkers with given offset xi in (0,1):
+ * log_w[W], e_loc[W] (device) -> idx[W] (device int32) and stats[2] (device:
+ * log_wbar, ebar; may be NULL).  Allocates a W-double scratch buffer on the
+ * stream.  Errors: LRDMC_EINVAL (W < 1, xi outside (0,1)), LRDMC_ENONFINITE,
+ * LRDMC_ENOMEM, LRDMC_EDEVICE. */
+int lrdmc_reconfigure(const double *log_w, const double *e_loc, int32_t W, double xi,
+                      int32_t *idx, double *stats, void *stream);
+
+/* Generation counter of the next projection. */
+uint64_t lrdmc_generation(const lrdmc_ctx *ctx);
+
+/* Message of the last failure of ctx (or of the last failing call without a
+ * context when ctx is NULL).  Valid until the next call on ctx. */
+const char *lrdmc_last_error(const lrdmc_ctx *ctx);
+
+/* Free the context and its device memory.  NULL is allowed. */
+void lrdmc_destroy(lrdmc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LRDMC_H */

@@ -1,0 +1,276 @@
+"""Thin Python binding of liblrdmc.so (include/lrdmc.h) for MI355X.
+
+Argument marshalling only: every step of the projection runs in the HIP
+kernels of the library.  torch supplies device memory (cuda tensors on ROCm)
+and the stream handle.  There is no CPU fallback: if the library is not built
+or no GPU is present, the calls raise.
+
+Module-level functions carry the C names (lrdmc_create, lrdmc_project, ...);
+the class ``LRDMC`` bundles a context with the system it was made for.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+import torch  # imported before the library so that both share one HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblrdmc.so")
+
+LRDMC_NDIAG = 9
+DIAG_NAMES = ("e_l", "e_lattice", "lap_lattice", "lap_exact", "v_a", "v_sf", "delta", "v", "sum_k")
+
+ERRORS = {-1: "EINVAL", -2: "ESINGULAR", -3: "ENONFINITE", -4: "ENOMEM", -5: "EDEVICE"}
+
+
+class LRDMCError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class lrdmc_system(C.Structure):
+    _fields_ = [
+        ("n_nuc", C.c_int32), ("Z", C.c_void_p), ("R", C.c_void_p),
+        ("n_up", C.c_int32), ("n_dn", C.c_int32),
+        ("n_shell", C.c_int32), ("shell_nuc", C.c_void_p), ("shell_l", C.c_void_p),
+        ("shell_alpha", C.c_void_p),
+        ("n_orb", C.c_int32), ("mo", C.c_void_p),
+        ("b_ee", C.c_double), ("b_en", C.c_double),
+    ]
+
+
+class lrdmc_params(C.Structure):
+    _fields_ = [
+        ("a", C.c_double), ("a_prime", C.c_double), ("r_c", C.c_double),
+        ("z_heavy", C.c_double), ("tau", C.c_double),
+        ("seed", C.c_uint64), ("rotate", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+_lib = None
+EXPORTS = ("lrdmc_spacing", "lrdmc_create", "lrdmc_set_walkers", "lrdmc_project", "lrdmc_branch",
+           "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure",
+           "lrdmc_generation", "lrdmc_last_error", "lrdmc_destroy")
+
+
+def load():
+    """Load liblrdmc.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    P, I32, I64, U64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
+    lib.lrdmc_spacing.argtypes = [D, D, D, D, P, P, P]
+    lib.lrdmc_create.argtypes = [P, P, I32, P]
+    lib.lrdmc_set_walkers.argtypes = [P, P, U64, P]
+    lib.lrdmc_project.argtypes = [P, P]
+    lib.lrdmc_branch.argtypes = [P, P, P, P, P, P]
+    lib.lrdmc_run.argtypes = [P, I32, P, P, P, P, P]
+    lib.lrdmc_get_walkers.argtypes = [P, P, P, P, P, P]
+    lib.lrdmc_eval_moves.argtypes = [P, P, P, P, P, P]
+    lib.lrdmc_reconfigure.argtypes = [P, P, I32, D, P, P, P]
+    lib.lrdmc_generation.argtypes = [P]
+    lib.lrdmc_generation.restype = U64
+    lib.lrdmc_last_error.argtypes = [P]
+    lib.lrdmc_last_error.restype = C.c_char_p
+    lib.lrdmc_destroy.argtypes = [P]
+    lib.lrdmc_destroy.restype = None
+    for name in ("lrdmc_spacing", "lrdmc_create", "lrdmc_set_walkers", "lrdmc_project", "lrdmc_branch",
+                 "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, ctx=None):
+    if rc != 0:
+        msg = load().lrdmc_last_error(ctx).decode()
+        raise LRDMCError(rc, msg)
+
+
+def _dptr(t: Optional[torch.Tensor], dtype=None) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{dtype} tensor expected, got {t.dtype}")
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+# -- the C entry points -------------------------------------------------------
+
+def lrdmc_spacing(Z: float, a: float, beta: float = 0.75, kappa: float = 2.5) -> Tuple[float, float, float]:
+    rc, ap, nc = C.c_double(), C.c_double(), C.c_double()
+    _check(load().lrdmc_spacing(float(Z), float(a), float(beta), float(kappa),
+                                C.byref(rc), C.byref(ap), C.byref(nc)))
+    return rc.value, ap.value, nc.value
+
+
+def _pack_system(system):
+    keep = [np.ascontiguousarray(system.Z, dtype=np.float64),
+            np.ascontiguousarray(system.R, dtype=np.float64).reshape(-1),
+            np.ascontiguousarray(system.shell_nuc, dtype=np.int32),
+            np.ascontiguousarray(system.shell_l, dtype=np.int32),
+            np.ascontiguousarray(system.shell_alpha, dtype=np.float64),
+            np.ascontiguousarray(system.mo, dtype=np.float64)]
+    s = lrdmc_system(len(keep[0]), keep[0].ctypes.data, keep[1].ctypes.data, int(system.n_up),
+                     int(system.n_dn), len(keep[2]), keep[2].ctypes.data, keep[3].ctypes.data,
+                     keep[4].ctypes.data, int(keep[5].shape[1]), keep[5].ctypes.data,
+                     float(system.b_ee), float(system.b_en))
+    return s, keep
+
+
+def lrdmc_create(system, a: float, a_prime: float, r_c: float, tau: float, n_walkers: int,
+                 z_heavy: Optional[float] = None, seed: int = 0, rotate: int = 1) -> int:
+    s, keep = _pack_system(system)
+    zh = float(np.max(system.Z)) if z_heavy is None else float(z_heavy)
+    p = lrdmc_params(a, a_prime, r_c, zh, tau, seed, rotate, 0)
+    ctx = C.c_void_p()
+    _check(load().lrdmc_create(C.byref(s), C.byref(p), int(n_walkers), C.byref(ctx)))
+    del keep
+    return ctx.value
+
+
+def lrdmc_set_walkers(ctx, pos: torch.Tensor, generation: int = 0, stream=None):
+    _check(load().lrdmc_set_walkers(ctx, _dptr(pos, torch.float64), int(generation), _stream(stream)), ctx)
+
+
+def lrdmc_project(ctx, stream=None):
+    _check(load().lrdmc_project(ctx, _stream(stream)), ctx)
+
+
+def lrdmc_branch(ctx, log_wbar=None, ebar=None, n_moves=None, idx=None, stream=None):
+    _check(load().lrdmc_branch(ctx, _stream(stream), _dptr(log_wbar, torch.float64),
+                               _dptr(ebar, torch.float64), _dptr(n_moves, torch.int64),
+                               _dptr(idx, torch.int32)), ctx)
+
+
+def lrdmc_run(ctx, n_gen: int, log_wbar=None, ebar=None, n_moves=None, idx=None, stream=None):
+    _check(load().lrdmc_run(ctx, int(n_gen), _stream(stream), _dptr(log_wbar, torch.float64),
+                            _dptr(ebar, torch.float64), _dptr(n_moves, torch.int64),
+                            _dptr(idx, torch.int32)), ctx)
+
+
+def lrdmc_get_walkers(ctx, pos=None, log_w=None, e_loc=None, n_moves=None, stream=None):
+    _check(load().lrdmc_get_walkers(ctx, _dptr(pos, torch.float64), _dptr(log_w, torch.float64),
+                                    _dptr(e_loc, torch.float64), _dptr(n_moves, torch.int32),
+                                    _stream(stream)), ctx)
+
+
+def lrdmc_eval_moves(ctx, pos, rho=None, k=None, diag=None, stream=None):
+    _check(load().lrdmc_eval_moves(ctx, _dptr(pos, torch.float64), _dptr(rho, torch.float64),
+                                   _dptr(k, torch.float64), _dptr(diag, torch.float64),
+                                   _stream(stream)), ctx)
+
+
+def lrdmc_reconfigure(log_w, e_loc, xi: float, idx, stats=None, stream=None):
+    _check(load().lrdmc_reconfigure(_dptr(log_w, torch.float64), _dptr(e_loc, torch.float64),
+                                    int(log_w.shape[0]), float(xi), _dptr(idx, torch.int32),
+                                    _dptr(stats, torch.float64), _stream(stream)))
+
+
+def lrdmc_generation(ctx) -> int:
+    return int(load().lrdmc_generation(ctx))
+
+
+def lrdmc_last_error(ctx=None) -> str:
+    return load().lrdmc_last_error(ctx).decode()
+
+
+def lrdmc_destroy(ctx):
+    if ctx:
+        load().lrdmc_destroy(ctx)
+
+
+# -- convenience object -----------------------------------------------------
+
+class LRDMC:
+    """A context bound to one system and walker count, with torch buffers."""
+
+    def __init__(self, system, a: float, a_prime: float, r_c: float, tau: float, n_walkers: int,
+                 z_heavy: Optional[float] = None, seed: int = 0, rotate: int = 1,
+                 device: str = "cuda:0"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the LRDMC projection runs only on the HIP device")
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        torch.cuda.set_device(self.device)
+        self.system = system
+        self.W = int(n_walkers)
+        self.N = system.n_elec
+        self.M = 12 * self.N
+        self.ctx = lrdmc_create(system, a, a_prime, r_c, tau, n_walkers, z_heavy, seed, rotate)
+
+    def close(self):
+        if self.ctx:
+            lrdmc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _f64(self, *shape):
+        return torch.empty(*shape, dtype=torch.float64, device=self.device)
+
+    def set_walkers(self, pos, generation: int = 0):
+        t = torch.as_tensor(pos, dtype=torch.float64).to(self.device).contiguous()
+        if tuple(t.shape) != (self.W, self.N, 3):
+            raise ValueError(f"positions must be [{self.W}, {self.N}, 3]")
+        lrdmc_set_walkers(self.ctx, t, generation)
+
+    @property
+    def generation(self) -> int:
+        return lrdmc_generation(self.ctx)
+
+    def project(self):
+        lrdmc_project(self.ctx)
+
+    def branch(self):
+        lwb, eb = self._f64(1), self._f64(1)
+        nm = torch.empty(1, dtype=torch.int64, device=self.device)
+        idx = torch.empty(self.W, dtype=torch.int32, device=self.device)
+        lrdmc_branch(self.ctx, lwb, eb, nm, idx)
+        return dict(log_wbar=float(lwb.item()), ebar=float(eb.item()), n_moves=int(nm.item()), idx=idx)
+
+    def run(self, n_gen: int, want_idx: bool = False, out=None):
+        if out is None:
+            out = dict(log_wbar=self._f64(n_gen), ebar=self._f64(n_gen),
+                       n_moves=torch.empty(n_gen, dtype=torch.int64, device=self.device),
+                       idx=(torch.empty(n_gen, self.W, dtype=torch.int32, device=self.device)
+                            if want_idx else None))
+        lrdmc_run(self.ctx, n_gen, out["log_wbar"], out["ebar"], out["n_moves"], out["idx"])
+        return out
+
+    def get_walkers(self):
+        pos = self._f64(self.W, self.N, 3)
+        lw, el = self._f64(self.W), self._f64(self.W)
+        nm = torch.empty(self.W, dtype=torch.int32, device=self.device)
+        lrdmc_get_walkers(self.ctx, pos, lw, el, nm)
+        return dict(pos=pos, log_w=lw, e_l=el, n_moves=nm)
+
+    def eval_moves(self, pos):
+        t = torch.as_tensor(pos, dtype=torch.float64).to(self.device).contiguous()
+        if tuple(t.shape) != (self.W, self.N, 3):
+            raise ValueError(f"positions must be [{self.W}, {self.N}, 3]")
+        rho, k = self._f64(self.W, self.M), self._f64(self.W, self.M)
+        diag = self._f64(self.W, LRDMC_NDIAG)
+        lrdmc_eval_moves(self.ctx, t, rho, k, diag)
+        return rho, k, diag
