@@ -1,0 +1,191 @@
+#!/usr/bin/env python
+"""Benchmark of the double-grid LRDMC projection on one MI355X.
+
+One step = one generation: a continuous-time projection of every walker over
+projection time tau (all moves: table of 12N lattice moves, heat-bath choice,
+Sherman-Morrison update) followed by the fixed-population reconfiguration.
+The timed region runs `--steps` generations through lrdmc_run with the
+walkers resident in HBM, bracketed by device synchronizations.
+
+Workload (default): Ar-like atom, Z = 18 (9 up, 9 down), K = 64 even-tempered
+s/p/d Gaussians 0.05 * 2.5^k with a seeded orthonormal MO matrix, Pade
+Jastrow b = 1, small spacing a = 0.1 bohr with r_c(a, Z) and a' from the
+paper's rule, 4096 walkers.  The a = 0.2 bohr spacing of the same workload is
+timed as a second line inside the same JSON object.
+
+Prints one JSON line.  Multi-GPU runs are not part of this build.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector peak (vendor figure)
+METRIC = "LRDMC electron-moves/s"
+
+
+def _traffic_record(workload: str):
+    """HBM bytes per projection launch measured with rocprofv3 counters, if
+    they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_project_kernel.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_1909_01589_amd", "csrc", "lrdmc.hip"), "rb").read()
+    if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    ent = rec.get("workloads", {}).get(workload)
+    return None if ent is None else float(ent["bytes_per_launch"])
+
+
+def cpu_baseline(system, a, ap, rc, tau, seed, pos, gen0, seconds):
+    """The CPU oracle, as it stands, on a bounded sample of the workload:
+    chunks of 64 walkers of the equilibrated population, one generation each,
+    until `seconds` of wall time have passed."""
+    import oracle
+    oracle.build(force=False)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    o = oracle.Oracle(system, a, ap, rc, tau=tau, seed=seed)
+    W = pos.shape[0]
+    moves, chunks = 0, 0
+    t0 = time.perf_counter()
+    while True:
+        lo = (chunks * 64) % W
+        r = o.run(pos[lo:lo + 64], 1, gen0=gen0 + chunks, want_idx=False, nthreads=threads)
+        moves += int(r["n_moves"].sum())
+        chunks += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": moves / dt, "unit": "electron-moves/s", "cores": threads, "kind": "oracle",
+            "sample": f"{chunks} x (64 walkers x 1 generation) of the equilibrated population, "
+                      f"{moves} moves in {dt:.1f} s"}
+
+
+def run_workload(name, steps, warmup, want_cpu, cpu_seconds):
+    import torch
+    from paper_1909_01589_amd import inputs, stats, workcount
+    from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_set_timing, lrdmc_spacing, lrdmc_timing
+
+    cfg = inputs.get_config(name)
+    s = cfg.system
+    rc, ap, nc = lrdmc_spacing(s.z_max, cfg.a)
+    W = cfg.walkers
+    gpu = LRDMC(s, cfg.a, ap, rc, cfg.tau, W, seed=cfg.seed, rotate=cfg.rotate)
+    gpu.set_walkers(inputs.initial_walkers(s, W, cfg.seed), 0)
+    if warmup:
+        gpu.run(warmup)
+    torch.cuda.synchronize()
+    lrdmc_set_timing(gpu.ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = gpu.run(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    proj_ms, proj_n, br_ms, br_n = lrdmc_timing(gpu.ctx)
+    lrdmc_set_timing(gpu.ctx, False)
+    wall = t1 - t0
+    n_moves = out["n_moves"].cpu().numpy()
+    moves = int(n_moves.sum())
+    lwb = out["log_wbar"].cpu().numpy()
+    eb = out["ebar"].cpu().numpy()
+    E, sig = stats.estimate(lwb, eb, p=None)
+
+    shp = workcount.shape_of(s)
+    ops = workcount.projection_ops(shp, W, moves) if proj_n else 0.0
+    avg_ms = proj_ms / max(proj_n, 1)
+    ops_per_launch = ops / max(proj_n, 1)
+    achieved = ops_per_launch / (avg_ms * 1e-3) / 1e12 if proj_n else 0.0
+    traffic = _traffic_record(name)
+    res = {
+        "value": moves / wall, "ms_per_step": 1e3 * wall / steps, "moves": moves, "wall_s": wall,
+        "moves_per_walker_gen": moves / (W * steps),
+        "projection_time_per_s": W * cfg.tau * steps / wall,
+        "E_Ha": E, "sigma_E_Ha": sig,
+        "time_to_sigma_1mHa_s": wall * (sig / 1e-3) ** 2 if np.isfinite(sig) else None,
+        "a": cfg.a, "a_prime": ap, "r_c": rc, "n_core": nc, "tau": cfg.tau, "walkers": W,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+                     "kernel": "project_kernel", "avg_launch_ms": avg_ms,
+                     "ops_per_launch": ops_per_launch,
+                     "reconfigure_avg_ms": br_ms / max(br_n, 1)},
+    }
+    if want_cpu:
+        pos = gpu.get_walkers()["pos"].cpu().numpy()
+        res["cpu_baseline"] = cpu_baseline(s, cfg.a, ap, rc, cfg.tau, cfg.seed, pos, 10_000_000, cpu_seconds)
+    gpu.close()
+    return cfg, res
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000, help="timed generations")
+    ap.add_argument("--warmup", type=int, default=100, help="untimed generations before timing")
+    ap.add_argument("--workload", default="ar_a0.1")
+    ap.add_argument("--second", default="ar_a0.2", help="second workload line ('' to skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on exactly one GPU; --gpus must be 1 "
+              "(multi-GPU sharding of the walker population is described in DESIGN.md, not built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+
+    cfg, main_res = run_workload(args.workload, args.steps, args.warmup, not args.no_cpu_baseline,
+                                 args.cpu_seconds)
+    second = None
+    if args.second:
+        _, second = run_workload(args.second, args.steps, args.warmup, False, 0.0)
+
+    s = cfg.system
+    line = {
+        "metric": METRIC, "value": main_res["value"], "unit": "electron-moves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {
+            "workload": f"{cfg.name}: Ar-like atom Z=18 (9 up, 9 down), K={s.n_basis} even-tempered "
+                        f"s/p/d Gaussians 0.05*2.5^k, seeded orthonormal MOs, Pade Jastrow b=1, "
+                        f"a={cfg.a} bohr, a'={main_res['a_prime']:.5f}, r_c={main_res['r_c']:.5f}, "
+                        f"{cfg.walkers} walkers, tau={cfg.tau} per generation",
+            "walkers": cfg.walkers, "electrons": s.n_elec, "basis": s.n_basis,
+            "a": cfg.a, "a_prime": main_res["a_prime"], "r_c": main_res["r_c"], "tau": cfg.tau,
+        },
+        "roofline": main_res["roofline"],
+        "moves_per_walker_gen": main_res["moves_per_walker_gen"],
+        "projection_time_per_s": main_res["projection_time_per_s"],
+        "E_Ha": main_res["E_Ha"], "sigma_E_Ha": main_res["sigma_E_Ha"],
+        "time_to_sigma_1mHa_s": main_res["time_to_sigma_1mHa_s"],
+    }
+    if "cpu_baseline" in main_res:
+        line["cpu_baseline"] = main_res["cpu_baseline"]
+    if second is not None:
+        line["second_workload"] = {
+            "workload": args.second, "value": second["value"], "ms_per_step": second["ms_per_step"],
+            "a": second["a"], "a_prime": second["a_prime"], "tau": second["tau"],
+            "moves_per_walker_gen": second["moves_per_walker_gen"],
+            "roofline_frac": second["roofline"]["frac"],
+            "time_to_sigma_1mHa_s": second["time_to_sigma_1mHa_s"],
+        }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -180,6 +180,15 @@ int lrdmc_eval_moves(lrdmc_ctx *ctx, const double *pos, double *rho, double *k,
 int lrdmc_reconfigure(const double *log_w, const double *e_loc, int32_t W, double xi,
                       int32_t *idx, double *stats, void *stream);
 
+/* Kernel timing with HIP events recorded on the launch stream around every
+ * projection and reconfiguration kernel of lrdmc_project, lrdmc_branch and
+ * lrdmc_run.  enable != 0 clears the totals and starts accumulating, 0 stops.
+ * lrdmc_timing writes (host) out[4] = {projection kernel ms, projection
+ * launches, reconfiguration kernel ms, reconfiguration launches}.
+ * Errors: LRDMC_EINVAL (NULL), LRDMC_EDEVICE. */
+int lrdmc_set_timing(lrdmc_ctx *ctx, int32_t enable);
+int lrdmc_timing(const lrdmc_ctx *ctx, double *out);
+
 /* Generation counter of the next projection. */
 uint64_t lrdmc_generation(const lrdmc_ctx *ctx);
 

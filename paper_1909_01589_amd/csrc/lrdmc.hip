@@ -41,7 +41,10 @@ constexpr int kMaxIter = 1 << 22;  // moves per walker and generation
 // Internal kernel error codes (err[0]); err[1] holds the slot.
 enum { kErrSingular = 1, kErrNonFinite = 2, kErrIterCap = 3 };
 
-// Offsets (in doubles) of the per-walker LDS arrays.
+// Offsets (in doubles) of the per-walker LDS arrays.  The region starting at
+// U is used twice: during the generation start it holds the Gauss-Jordan
+// workspace and a batch of basis blocks, during the move loop the heat-bath
+// weights and the accepted-move temporaries.
 struct Layout {
     int pos;    // [N][3]            positions
     int Y;      // [N][Kp]           Y[i][mu] = sum_j C[mu][j] Ainv_sigma(i)[j][i_sigma]
@@ -50,18 +53,24 @@ struct Layout {
     int gD;     // [N][4]            grad D/D (3) and lap D/D of electron i
     int gJ;     // [N][4]            grad J (3) and lap J of electron i
     int Jo;     // [N]               Jastrow terms that contain electron i
-    int Vi;     // [N]               sum_{j>i} 1/r_ij - sum_I Z_I/r_iI
+    int C;      // [K][ns]           MO coefficients of the occupied orbitals, or -1 (read from HBM)
+    int red;    // [64]              reduction scratch
+    int sc;     // [32]              block scalars
+    int rng;    // [16][12]          rotations and (u1, u2) of the next sixteen iterations
+    int acc;    // [4][6]            per-wavefront partial sums of the moved electron's Jastrow
+    // move-loop view of U
     int T;      // [M]               heat-bath weights of the moves
     int bv;     // [5][K]            basis value, gradient, Laplacian at one point
     int vrow;   // [5][ns]           orbital value, gradient, Laplacian at one point
     int wrow;   // [ns]              w_i = phi(r_new) . Ainv[:, i]
     int colk;   // [ns]              column k of Ainv before the update
     int Yk;     // [Kp]              row k of Y before the update
+    // generation-start view of U
     int G;      // [2][ns][2ns]      Gauss-Jordan workspace
     int piv;    // [2][2][2ns]       pivot row and row c copies
     int fac;    // [2][ns]           elimination factors
-    int red;    // [64]              reduction scratch
-    int sc;     // [32]              block scalars
+    int bvb;    // [EB][5][K]        basis blocks of a batch of electrons
+    int EB;     // electrons per batch
     int total;
 };
 
@@ -73,8 +82,11 @@ struct KArgs {
     const int *grp_nuc;            // [n_grp]
     const double *grp_alpha;       // [n_grp]
     const int *grp_off;            // [n_grp][3] first basis index of the s, p, d shell, -1 if none
+    int n_chain;
+    const int *chain;              // [n_chain][3]: first group, length, step code (see basis_dot)
     const double *mo;              // [K][n_orb]
     double b_ee, b_en, v_nn;
+    int c_lds;                     // 1: occupied MO block staged in LDS
     // lattice
     double a, ap, inv_a2, inv_ap2, inv_2rc2, tau;
     uint64_t seed;
@@ -94,12 +106,7 @@ struct KArgs {
 };
 
 // Block scalar slots.
-enum {
-    SC_R = 0,        // 9 rotation entries
-    SC_U1 = 9, SC_U2 = 10, SC_DELTA = 11, SC_EL = 12, SC_TL = 13, SC_LW = 14,
-    SC_RP = 15,      // 3 entries: accepted position
-    SC_LAP = 18, SC_V = 19
-};
+enum { SC_EL = 0, SC_V = 1 };
 
 __device__ __forceinline__ void report(int *err, int code, int slot)
 {
@@ -158,50 +165,47 @@ __device__ void basis_group_full(const KArgs &A, int g, const double r[3], doubl
     }
 }
 
+// sqrt of e in [0, 1] through the refined reciprocal square root; values
+// below 1e-300 (whose powers vanish anyway) map to 0.
+__device__ __forceinline__ double sqrt_unit(double e);
+
 // sum_mu g_mu(r) y[mu]: the determinant ratio of moving an electron whose
-// orbital-projected inverse row is y to r.
+// orbital-projected inverse row is y to r.  Groups come in chains on one
+// nucleus with exponents alpha_{q+1} = beta alpha_q; for beta = 2, 2.5 and 3
+// the exponential of the next group is a power of the current one
+// (e^2, e^2 sqrt(e), e^3), so a chain costs one exp; other chains (code 0)
+// take one exp per group.
 __device__ __forceinline__ double basis_dot(const KArgs &A, const double r[3], const double *y)
 {
     double acc = 0.0;
-    for (int g = 0; g < A.n_grp; ++g) {
-        const double *Rn = A.Rnuc + 3 * A.grp_nuc[g];
+    for (int ch = 0; ch < A.n_chain; ++ch) {
+        const int g0 = A.chain[3 * ch], len = A.chain[3 * ch + 1], code = A.chain[3 * ch + 2];
+        const double *Rn = A.Rnuc + 3 * A.grp_nuc[g0];
         const double dx = r[0] - Rn[0], dy = r[1] - Rn[1], dz = r[2] - Rn[2];
         const double d2 = dx * dx + dy * dy + dz * dz;
-        const double e = exp(-A.grp_alpha[g] * d2);
-        const int *off = A.grp_off + 3 * g;
-        double poly = 0.0;
-        if (off[0] >= 0) poly += y[off[0]];
-        if (off[1] >= 0) {
-            const double *yp = y + off[1];
-            poly += dx * yp[0] + dy * yp[1] + dz * yp[2];
+        const double pd[5] = {dx * dy, dy * dz, dz * dx, dx * dx - dy * dy, 2.0 * dz * dz - dx * dx - dy * dy};
+        double e = exp(-A.grp_alpha[g0] * d2);
+        for (int q = 0; q < len; ++q) {
+            const int g = g0 + q;
+            const int *off = A.grp_off + 3 * g;
+            double poly = 0.0;
+            if (off[0] >= 0) poly += y[off[0]];
+            if (off[1] >= 0) {
+                const double *yp = y + off[1];
+                poly += dx * yp[0] + dy * yp[1] + dz * yp[2];
+            }
+            if (off[2] >= 0) {
+                const double *yd = y + off[2];
+                poly += pd[0] * yd[0] + pd[1] * yd[1] + pd[2] * yd[2] + pd[3] * yd[3] + pd[4] * yd[4];
+            }
+            acc += e * poly;
+            if (q + 1 < len) {
+                if (code == 3) e = e * e * e;
+                else if (code == 2) e = (e * e) * sqrt_unit(e);
+                else if (code == 1) e = e * e;
+                else e = exp(-A.grp_alpha[g + 1] * d2);
+            }
         }
-        if (off[2] >= 0) {
-            const double *yd = y + off[2];
-            poly += dx * dy * yd[0] + dy * dz * yd[1] + dz * dx * yd[2] + (dx * dx - dy * dy) * yd[3] +
-                    (2.0 * dz * dz - dx * dx - dy * dy) * yd[4];
-        }
-        acc += e * poly;
-    }
-    return acc;
-}
-
-// Jastrow terms containing electron i when it sits at r (others fixed).
-__device__ __forceinline__ double jastrow_point(const KArgs &A, const double *pos, int i, const double r[3])
-{
-    const int si = spin_of(A, i);
-    double acc = 0.0;
-    for (int j = 0; j < A.N; ++j) {
-        if (j == i) continue;
-        const double dx = r[0] - pos[3 * j], dy = r[1] - pos[3 * j + 1], dz = r[2] - pos[3 * j + 2];
-        const double rr = sqrt(dx * dx + dy * dy + dz * dz);
-        const double c = (spin_of(A, j) == si) ? 0.25 : 0.5;
-        acc += c * rr / (1.0 + A.b_ee * rr);
-    }
-    for (int I = 0; I < A.n_nuc; ++I) {
-        const double *R = A.Rnuc + 3 * I;
-        const double dx = r[0] - R[0], dy = r[1] - R[1], dz = r[2] - R[2];
-        const double rr = sqrt(dx * dx + dy * dy + dz * dz);
-        acc -= A.Znuc[I] * rr / (1.0 + A.b_en * rr);
     }
     return acc;
 }
@@ -238,89 +242,207 @@ __device__ __forceinline__ double move_geometry(const KArgs &A, const double *po
 
 // -- per-walker state ------------------------------------------------------
 
-// Orbital rows (value, gradient, Laplacian of phi_j, j < n) at a point whose
-// basis block is in bv; threads over (component, orbital).
-__device__ __forceinline__ void orbital_rows(const KArgs &A, const double *bv, int n, double *vrow)
+// Occupied MO block: C[mu][j] at Cm[mu * ldc + j].
+struct MoView {
+    const double *p;
+    int ld;
+};
+
+__device__ __forceinline__ MoView mo_view(const KArgs &A, const double *lds)
 {
-    const int K = A.K, no = A.n_orb, ns = A.ns;
-    for (int t = threadIdx.x; t < 5 * n; t += blockDim.x) {
-        const int c = t / n, j = t - c * n;
-        const double *b = bv + c * K;
+    if (A.c_lds) return {lds + A.L.C, A.ns};
+    return {A.mo, A.n_orb};
+}
+
+// out(e, c, j) = sum_mu b[e][c][mu] C[mu][j] for ne basis blocks b[e][5][K],
+// c < 5, j < n.  Each output is split over P adjacent lanes (a power of two,
+// at most 16) that sum slices of mu and combine with lane shuffles, so the
+// loads of one output are independent and the chains short.
+template <typename Store>
+__device__ __forceinline__ void orb_contract(const KArgs &A, const double *b, int ne, int n, MoView C,
+                                             Store store)
+{
+    const int K = A.K, NT = blockDim.x, nout = ne * 5 * n;
+    int P = 1;
+    while (P < 16 && nout * P * 2 <= NT) P <<= 1;
+    const int S = (K + P - 1) / P;
+    for (int base = 0; base < nout * P; base += NT) {
+        const int t = base + threadIdx.x, o = t / P, part = t - o * P;
         double acc0 = 0.0, acc1 = 0.0;
-        int mu = 0;
-        for (; mu + 1 < K; mu += 2) {
-            acc0 += b[mu] * A.mo[mu * no + j];
-            acc1 += b[mu + 1] * A.mo[(mu + 1) * no + j];
+        int e = 0, c = 0, j = 0;
+        if (o < nout) {
+            e = o / (5 * n);
+            const int r = o - e * 5 * n;
+            c = r / n;
+            j = r - c * n;
+            const double *bb = b + (e * 5 + c) * K;
+            const int mu1 = min(K, (part + 1) * S);
+            int mu = part * S;
+            for (; mu + 1 < mu1; mu += 2) {
+                acc0 += bb[mu] * C.p[mu * C.ld + j];
+                acc1 += bb[mu + 1] * C.p[(mu + 1) * C.ld + j];
+            }
+            if (mu < mu1) acc0 += bb[mu] * C.p[mu * C.ld + j];
         }
-        if (mu < K) acc0 += b[mu] * A.mo[mu * no + j];
-        vrow[c * ns + j] = acc0 + acc1;
+        double acc = acc0 + acc1;
+        for (int off = P >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (o < nout && part == 0) store(e, c, j, acc);
     }
 }
 
-// Jastrow gradient/Laplacian, own sum and potential share of every electron.
-// Segments of `seg` lanes (a power of two within a wavefront) per electron.
-__device__ void jastrow_all(const KArgs &A, const double *pos, double *gJ, double *Jo, double *Vi)
+// -- Pade pair terms -----------------------------------------------------------
+// u(r) = c r / (1 + b r) = c / (1/r + b).  With y = 1/r and inv = 1/(y + b):
+// u = c inv, q = 1/(1 + b r) = y inv, u' = c q^2, u'' = -2 c b q^3.
+
+// Reciprocal: hardware estimate refined by two Newton-Raphson steps
+// x <- x (2 - a x), written as fused multiply-adds.
+__device__ __forceinline__ double rcp_nr(double a)
 {
+    double x = __builtin_amdgcn_rcp(a);
+    double e = fma(-a, x, 1.0);
+    x = fma(x, e, x);
+    e = fma(-a, x, 1.0);
+    return fma(x, e, x);
+}
+
+// Reciprocal square root: hardware estimate refined by two Newton-Raphson
+// steps y <- y (3 - a y^2) / 2.
+__device__ __forceinline__ double rsqrt_nr(double a)
+{
+    double y = __builtin_amdgcn_rsq(a);
+    const double h = 0.5 * a;
+    double e = fma(-h * y, y, 0.5);
+    y = fma(y, e, y);
+    e = fma(-h * y, y, 0.5);
+    return fma(y, e, y);
+}
+
+__device__ __forceinline__ double sqrt_unit(double e)
+{
+    return e > 1e-300 ? e * rsqrt_nr(e) : 0.0;
+}
+
+// u(r) for the move table: one Newton-Raphson step on each hardware estimate
+// (relative error about 3e-14), enough for the ratio exp(dJ).
+__device__ __forceinline__ double pade_u(double c, double b, double d2)
+{
+    double y = __builtin_amdgcn_rsq(d2);
+    y = fma(y, fma(-0.5 * d2 * y, y, 0.5), y);
+    const double a = y + b;
+    double x = __builtin_amdgcn_rcp(a);
+    x = fma(x, fma(-a, x, 1.0), x);
+    return c * x;
+}
+
+struct PairD {
+    double u;    // u(r)
+    double f;    // u'(r) / r
+    double lap;  // u''(r) + 2 u'(r) / r
+    double y;    // 1 / r
+};
+
+__device__ __forceinline__ PairD pade_d(double c, double b, double d2)
+{
+    const double y = rsqrt_nr(d2);
+    const double inv = rcp_nr(y + b);
+    const double q = y * inv;
+    const double cq2 = c * q * q;
+    PairD p;
+    p.u = c * inv;
+    p.f = cq2 * y;
+    p.lap = -2.0 * b * cq2 * q + 2.0 * p.f;
+    p.y = y;
+    return p;
+}
+
+// Jastrow terms containing electron i when it sits at r (others fixed).
+__device__ __forceinline__ double jastrow_point(const KArgs &A, const double *pos, int i, const double r[3])
+{
+    const int si = spin_of(A, i);
+    double acc = 0.0;
+    for (int j = 0; j < A.N; ++j) {
+        if (j == i) continue;
+        const double dx = r[0] - pos[3 * j], dy = r[1] - pos[3 * j + 1], dz = r[2] - pos[3 * j + 2];
+        acc += pade_u((spin_of(A, j) == si) ? 0.25 : 0.5, A.b_ee, dx * dx + dy * dy + dz * dz);
+    }
+    for (int I = 0; I < A.n_nuc; ++I) {
+        const double *R = A.Rnuc + 3 * I;
+        const double dx = r[0] - R[0], dy = r[1] - R[1], dz = r[2] - R[2];
+        acc += pade_u(-A.Znuc[I], A.b_en, dx * dx + dy * dy + dz * dz);
+    }
+    return acc;
+}
+
+// Displaced position of move m.
+__device__ __forceinline__ void move_position(const KArgs &A, const double *pos, const double *Rm, int m,
+                                              double rp[3])
+{
+    const int i = m / 12, g = (m / 6) & 1, dir = m % 6, ax = dir >> 1;
+    const double h = g ? A.ap : A.a;
+    const double t = (dir & 1) ? -h : h;
+    for (int c = 0; c < 3; ++c) rp[c] = pos[3 * i + c] + t * Rm[3 * c + ax];
+}
+
+// Jastrow gradient/Laplacian and own sum of every electron; returns the total
+// potential to every thread.  Segments of `seg` lanes per electron.
+__device__ double jastrow_setup(const KArgs &A, double *lds)
+{
+    const Layout &L = A.L;
+    const double *pos = lds + L.pos;
+    double *gJ = lds + L.gJ, *Jo = lds + L.Jo;
     const int N = A.N;
     int seg = 64;
     while (seg > 1 && seg * N > (int)blockDim.x) seg >>= 1;
     const int per_pass = blockDim.x / seg;
+    double vsum = 0.0;
     for (int base = 0; base < N; base += per_pass) {
         const int i = base + threadIdx.x / seg, sub = threadIdx.x % seg;
-        double g0 = 0, g1 = 0, g2 = 0, lap = 0, jo = 0, v = 0;
+        double g0 = 0, g1 = 0, g2 = 0, lap = 0, jo = 0;
         if (i < N) {
             const int si = spin_of(A, i);
             const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
             for (int j = sub; j < N + A.n_nuc; j += seg) {
                 if (j == i) continue;
-                double dx, dy, dz, c, b, Zn = 0.0;
-                const bool ee = j < N;
-                if (ee) {
+                double dx, dy, dz, c, b;
+                if (j < N) {
                     dx = xi - pos[3 * j]; dy = yi - pos[3 * j + 1]; dz = zi - pos[3 * j + 2];
                     c = (spin_of(A, j) == si) ? 0.25 : 0.5;
                     b = A.b_ee;
                 } else {
                     const double *R = A.Rnuc + 3 * (j - N);
                     dx = xi - R[0]; dy = yi - R[1]; dz = zi - R[2];
-                    Zn = A.Znuc[j - N];
-                    c = -Zn;
+                    c = -A.Znuc[j - N];
                     b = A.b_en;
                 }
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                const double r = sqrt(r2);
-                const double ir = 1.0 / r;
-                const double q = 1.0 / (1.0 + b * r);
-                const double up = c * q * q;             // u'(r)
-                const double upp = -2.0 * c * b * q * q * q;  // u''(r)
-                const double f = up * ir;
-                g0 += f * dx; g1 += f * dy; g2 += f * dz;
-                lap += upp + 2.0 * f;
-                jo += c * r * q;
-                if (ee) { if (j > i) v += ir; }
-                else v -= Zn * ir;
+                const PairD pr = pade_d(c, b, dx * dx + dy * dy + dz * dz);
+                g0 += pr.f * dx; g1 += pr.f * dy; g2 += pr.f * dz;
+                lap += pr.lap;
+                jo += pr.u;
+                if (j >= N) vsum += c * pr.y;        // -Z_I / r_iI
+                else if (j > i) vsum += pr.y;        // 1 / r_ij, each pair once
             }
         }
         for (int off = seg >> 1; off > 0; off >>= 1) {
             g0 += __shfl_xor(g0, off, 64); g1 += __shfl_xor(g1, off, 64); g2 += __shfl_xor(g2, off, 64);
-            lap += __shfl_xor(lap, off, 64); jo += __shfl_xor(jo, off, 64); v += __shfl_xor(v, off, 64);
+            lap += __shfl_xor(lap, off, 64); jo += __shfl_xor(jo, off, 64);
         }
         if (i < N && sub == 0) {
             gJ[4 * i] = g0; gJ[4 * i + 1] = g1; gJ[4 * i + 2] = g2; gJ[4 * i + 3] = lap;
             Jo[i] = jo;
-            Vi[i] = v;
         }
     }
+    double v[1] = {vsum};
+    block_sum<1>(v, lds + L.red);
+    return v[0] + A.v_nn;
 }
 
-// grad D/D and lap D/D for the electrons of spin sg (sg < 0: both spins).
-__device__ __forceinline__ void det_derivs(const KArgs &A, const double *Ainv, const double *dphi,
-                                           double *gD, int sg)
+// grad D/D and lap D/D of every electron from its derivative rows and Ainv.
+__device__ __forceinline__ void det_derivs_all(const KArgs &A, const double *Ainv, const double *dphi,
+                                               double *gD)
 {
     const int ns = A.ns;
-    const int i0 = sg == 1 ? A.n_up : 0;
-    const int i1 = sg == 0 ? A.n_up : A.N;
-    for (int t = threadIdx.x; t < 4 * (i1 - i0); t += blockDim.x) {
-        const int i = i0 + t / 4, c = t & 3;
+    for (int t = threadIdx.x; t < 4 * A.N; t += blockDim.x) {
+        const int i = t >> 2, c = t & 3;
         const int s = spin_of(A, i), n = s ? A.n_dn : A.n_up, il = s ? i - A.n_up : i;
         const double *inv = Ainv + s * ns * ns;
         const double *dp = dphi + (i * 4 + c) * ns;
@@ -330,56 +452,45 @@ __device__ __forceinline__ void det_derivs(const KArgs &A, const double *Ainv, c
     }
 }
 
-// Local energy from the per-electron pieces; every thread gets the result.
-__device__ __forceinline__ void local_energy(const KArgs &A, double *lds, double *out_el, double *out_lap,
-                                             double *out_v)
+__device__ __forceinline__ double psi_lap_term(const double *d, const double *j)
 {
-    const Layout &L = A.L;
-    const double *gD = lds + L.gD, *gJ = lds + L.gJ, *Vi = lds + L.Vi;
-    double v[2] = {0.0, 0.0};
-    for (int i = threadIdx.x; i < A.N; i += blockDim.x) {
-        const double *d = gD + 4 * i, *j = gJ + 4 * i;
-        v[0] += d[3] + 2.0 * (d[0] * j[0] + d[1] * j[1] + d[2] * j[2]) + j[3] + j[0] * j[0] + j[1] * j[1] +
-                j[2] * j[2];
-        v[1] += Vi[i];
-    }
-    block_sum<2>(v, lds + L.red);
-    const double V = v[1] + A.v_nn;
-    *out_lap = v[0];
-    *out_v = V;
-    *out_el = -0.5 * v[0] + V;
+    return d[3] + 2.0 * (d[0] * j[0] + d[1] * j[1] + d[2] * j[2]) + j[3] + j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
 }
 
 // Generation start: Slater matrices and derivative rows of every electron,
 // Gauss-Jordan inversion with partial pivoting, Y = C Ainv, determinant and
-// Jastrow derivatives, local energy.  Returns an error code (uniform).
-__device__ int walker_setup(const KArgs &A, double *lds, int *sflag)
+// Jastrow derivatives, local energy.  Returns an error code (uniform);
+// EL, LAP (sum_i lap_i Psi/Psi) and V reach every thread.
+__device__ int walker_setup(const KArgs &A, double *lds, int *sflag, double &EL, double &LAP, double &V)
 {
     const Layout &L = A.L;
     const int N = A.N, ns = A.ns, K = A.K, Kp = A.Kp, tid = threadIdx.x, NT = blockDim.x;
-    double *pos = lds + L.pos, *bv = lds + L.bv, *vrow = lds + L.vrow, *G = lds + L.G;
+    double *pos = lds + L.pos, *G = lds + L.G, *bvb = lds + L.bvb;
     double *dphi = lds + L.dphi, *Ainv = lds + L.Ainv;
     const int two = 2 * ns;
+    const MoView Cv = mo_view(A, lds);
 
     // right halves = identity
     for (int t = tid; t < 2 * ns * two; t += NT) {
-        const int s = t / (ns * two), r = (t / two) % ns, c = t % two;
+        const int r = (t / two) % ns, c = t % two;
         if (c >= ns) G[t] = (c - ns == r) ? 1.0 : 0.0;
     }
-    for (int i = 0; i < N; ++i) {
-        const int s = spin_of(A, i), n = s ? A.n_dn : A.n_up, il = s ? i - A.n_up : i;
-        const double r[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
-        for (int g = tid; g < A.n_grp; g += NT) basis_group_full(A, g, r, bv);
-        __syncthreads();
-        orbital_rows(A, bv, n, vrow);
-        __syncthreads();
-        for (int t = tid; t < 5 * n; t += NT) {
-            const int c = t / n, j = t - c * n;
-            if (c == 0) G[(s * ns + il) * two + j] = vrow[j];
-            else dphi[(i * 4 + c - 1) * ns + j] = vrow[c * ns + j];
+    for (int e0 = 0; e0 < N; e0 += L.EB) {
+        const int ne = min(L.EB, N - e0);
+        for (int t = tid; t < ne * A.n_grp; t += NT) {
+            const int e = t / A.n_grp, g = t - e * A.n_grp, i = e0 + e;
+            const double r[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+            basis_group_full(A, g, r, bvb + e * 5 * K);
         }
+        __syncthreads();
+        orb_contract(A, bvb, ne, ns, Cv, [&](int e, int c, int j, double v) {
+            const int i = e0 + e, s = spin_of(A, i), n = s ? A.n_dn : A.n_up, il = s ? i - A.n_up : i;
+            if (j >= n) return;
+            if (c == 0) G[(s * ns + il) * two + j] = v;
+            else dphi[(i * 4 + c - 1) * ns + j] = v;
+        });
+        __syncthreads();
     }
-    __syncthreads();
 
     // Gauss-Jordan on [A | I] for both spins at once.
     double *prow = lds + L.piv;   // [2][2][two]: pivot row, row c
@@ -401,7 +512,6 @@ __device__ int walker_setup(const KArgs &A, double *lds, int *sflag)
         __syncthreads();
         if (sflag[2] == -2 || sflag[3] == -2) return kErrSingular;
         for (int t = tid; t < 2 * two + 2 * ns; t += NT) {
-            // copies: t < 2*two -> pivot row / row c entries; else factors
             if (t < 2 * two) {
                 const int s = t / two, col = t % two, p = sflag[2 + s];
                 if (p >= 0) {
@@ -445,39 +555,58 @@ __device__ int walker_setup(const KArgs &A, double *lds, int *sflag)
         const int s = spin_of(A, i), n = s ? A.n_dn : A.n_up, il = s ? i - A.n_up : i;
         const double *inv = Ainv + s * ns * ns;
         double acc = 0.0;
-        for (int j = 0; j < n; ++j) acc += A.mo[mu * A.n_orb + j] * inv[j * ns + il];
+        for (int j = 0; j < n; ++j) acc += Cv.p[mu * Cv.ld + j] * inv[j * ns + il];
         Y[i * Kp + mu] = acc;
     }
-    det_derivs(A, Ainv, dphi, lds + L.gD, -1);
-    jastrow_all(A, pos, lds + L.gJ, lds + L.Jo, lds + L.Vi);
-    __syncthreads();
-    double el, lap, V;
-    local_energy(A, lds, &el, &lap, &V);
-    if (tid == 0) {
-        lds[L.sc + SC_EL] = el;
-        lds[L.sc + SC_LAP] = lap;
-        lds[L.sc + SC_V] = V;
-    }
-    __syncthreads();
-    return isfinite(el) ? 0 : kErrNonFinite;
+    det_derivs_all(A, Ainv, dphi, lds + L.gD);
+    V = jastrow_setup(A, lds);          // ends with workgroup barriers
+    double v[1] = {0.0};
+    for (int i = tid; i < N; i += NT) v[0] += psi_lap_term(lds + L.gD + 4 * i, lds + L.gJ + 4 * i);
+    block_sum<1>(v, lds + L.red);
+    LAP = v[0];
+    EL = -0.5 * LAP + V;
+    return isfinite(EL) ? 0 : kErrNonFinite;
 }
 
-// Heat-bath weights of every move at the current configuration (S1-S6).
-// Optionally stores rho and k, and accumulates sum k, L^a and V_sf.
-__device__ __forceinline__ void move_table(const KArgs &A, double *lds, const double *Rm, double *rho_g,
-                                           double *k_g, double acc[3], bool diag)
+// Random numbers of iterations it .. it+15 (rotation and u1, u2), computed by
+// sixteen lanes at once into rng[16][12].
+__device__ __forceinline__ void refill_rng(const KArgs &A, double *rng, int slot, int it)
+{
+    if (threadIdx.x < 16) {
+        const int q = threadIdx.x;
+        double Rm[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, u[4];
+        if (A.rotate) {
+            draw4(A.seed, slot, A.gen, (uint64_t)(it + q), 1, u);
+            rotation(u, Rm);
+        }
+        double *o = rng + 12 * q;
+        for (int c = 0; c < 9; ++c) o[c] = Rm[c];
+        draw4(A.seed, slot, A.gen, (uint64_t)(it + q), 0, u);
+        o[9] = u[0];
+        o[10] = u[1];
+    }
+}
+
+// Heat-bath weights of the moves m in [c0, c1) (S1-S6); returns their sum.
+// With diag, stores rho and k and accumulates sum k, L^a and V_sf.
+__device__ __forceinline__ double move_table(const KArgs &A, double *lds, const double *Rm, int c0, int c1,
+                                             int *last, double *rho_g, double *k_g, double acc[3], bool diag)
 {
     const Layout &L = A.L;
     const double *pos = lds + L.pos, *Y = lds + L.Y, *Jo = lds + L.Jo;
     double *T = lds + L.T;
-    for (int m = threadIdx.x; m < A.M; m += blockDim.x) {
+    double part = 0.0;
+    for (int m = c0; m < c1; ++m) {
         const int i = m / 12;
         double rp[3];
         const double k = move_geometry(A, pos, Rm, m, rp);
         const double rd = basis_dot(A, rp, Y + i * A.Kp);
         const double dJ = jastrow_point(A, pos, i, rp) - Jo[i];
         const double rho = rd * exp(dJ);
-        T[m] = 0.5 * k * (rho > 0.0 ? rho : 0.0);
+        const double t = 0.5 * k * (rho > 0.0 ? rho : 0.0);
+        T[m] = t;
+        part += t;
+        if (t > 0.0) *last = m;
         if (diag) {
             if (rho_g) rho_g[m] = rho;
             if (k_g) k_g[m] = k;
@@ -486,39 +615,64 @@ __device__ __forceinline__ void move_table(const KArgs &A, double *lds, const do
             if (rho < 0.0) acc[2] += -0.5 * k * rho;
         }
     }
+    return part;
 }
 
-// Sherman-Morrison update after electron k moved to lds[SC_RP].
-__device__ void accept_move(const KArgs &A, double *lds, int k)
+// Sherman-Morrison update after electron k moved from rold to rnew (S8).
+// Updates Ainv, Y, the derivative rows, the determinant and Jastrow
+// derivatives, the Jastrow own sums and the potential; EL and V are
+// returned to every thread.
+__device__ void accept_move(const KArgs &A, double *lds, int k, const double rold[3], const double rnew[3],
+                            double &EL, double &V)
 {
     const Layout &L = A.L;
-    const int ns = A.ns, K = A.K, Kp = A.Kp, tid = threadIdx.x, NT = blockDim.x;
+    const int N = A.N, ns = A.ns, K = A.K, Kp = A.Kp, tid = threadIdx.x, NT = blockDim.x;
+    const int lane = tid & 63, wv = tid >> 6, nw = NT >> 6;
     const int s = spin_of(A, k), n = s ? A.n_dn : A.n_up, kl = s ? k - A.n_up : k, i0 = s ? A.n_up : 0;
     double *pos = lds + L.pos, *bv = lds + L.bv, *vrow = lds + L.vrow, *wrow = lds + L.wrow;
     double *colk = lds + L.colk, *Yk = lds + L.Yk, *Y = lds + L.Y, *dphi = lds + L.dphi;
+    double *gD = lds + L.gD, *gJ = lds + L.gJ, *Jo = lds + L.Jo, *accw = lds + L.acc;
     double *inv = lds + L.Ainv + s * ns * ns;
-    const double rp[3] = {lds[L.sc + SC_RP], lds[L.sc + SC_RP + 1], lds[L.sc + SC_RP + 2]};
+    const MoView Cv = mo_view(A, lds);
 
-    for (int g = tid; g < A.n_grp; g += NT) basis_group_full(A, g, rp, bv);
+    // A1: basis block at the new position
+    for (int g = tid; g < A.n_grp; g += NT) basis_group_full(A, g, rnew, bv);
     __syncthreads();
-    orbital_rows(A, bv, n, vrow);
-    __syncthreads();
-    // w_i = phi(r') . Ainv[:, i]; save column k of Ainv and row k of Y
-    for (int t = tid; t < n + n + K; t += NT) {
-        if (t < n) {
-            double acc = 0.0;
-            for (int j = 0; j < n; ++j) acc += vrow[j] * inv[j * ns + t];
-            wrow[t] = acc;
-        } else if (t < 2 * n) {
-            const int j = t - n;
-            colk[j] = inv[j * ns + kl];
-        } else {
-            const int mu = t - 2 * n;
-            Yk[mu] = Y[k * Kp + mu];
+
+    // A2: new orbital row with derivatives (vrow), w_i = g(r_new) . Y_i, and
+    // copies of column k of Ainv and row k of Y.
+    orb_contract(A, bv, 1, n, Cv, [&](int, int c, int j, double v) { vrow[c * ns + j] = v; });
+    {
+        int P = 1;
+        while (P < 16 && n * P * 2 <= NT) P <<= 1;
+        const int S = (K + P - 1) / P;
+        for (int base = 0; base < n * P; base += NT) {
+            const int t = base + tid, o = t / P, part = t - o * P;
+            double a0 = 0.0, a1 = 0.0;
+            if (o < n) {
+                const double *yr = Y + (i0 + o) * Kp;
+                const int mu1 = min(K, (part + 1) * S);
+                int mu = part * S;
+                for (; mu + 1 < mu1; mu += 2) {
+                    a0 += bv[mu] * yr[mu];
+                    a1 += bv[mu + 1] * yr[mu + 1];
+                }
+                if (mu < mu1) a0 += bv[mu] * yr[mu];
+            }
+            double acc = a0 + a1;
+            for (int off = P >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            if (o < n && part == 0) wrow[o] = acc;
         }
     }
+    for (int t = tid; t < n + K; t += NT) {
+        if (t < n) colk[t] = inv[t * ns + kl];
+        else Yk[t - n] = Y[k * Kp + t - n];
+    }
     __syncthreads();
+
     const double irho = 1.0 / wrow[kl];
+    // A3: rank-1 updates of Ainv and of the spin's rows of Y; new derivative
+    // row and position of electron k.
     for (int t = tid; t < n * n + n * K + 4 * n + 3; t += NT) {
         if (t < n * n) {
             const int j = t / n, i = t - j * n;
@@ -533,68 +687,171 @@ __device__ void accept_move(const KArgs &A, double *lds, int k)
             dphi[(k * 4 + c) * ns + j] = vrow[(c + 1) * ns + j];
         } else {
             const int c = t - n * n - n * K - 4 * n;
-            pos[3 * k + c] = rp[c];
+            pos[3 * k + c] = rnew[c];
+        }
+    }
+    // A4a: thread i < N updates electron i.  For i != k: the Jastrow pair with
+    // k (new minus old) and, for the moved spin, grad/lap D/D through
+    // Ainv' = Ainv - colk (w - e_k)^T / rho.  For i == k: grad/lap D/D from
+    // the new derivative row and Ainv'[:, k] = colk / rho.
+    double dv = 0.0;
+    if (tid < N) {
+        const int i = tid;
+        if (i != k) {
+            const double c = (spin_of(A, i) == s) ? 0.25 : 0.5;
+            const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+            const double ax = xi - rnew[0], ay = yi - rnew[1], az = zi - rnew[2];
+            const double bx = xi - rold[0], by = yi - rold[1], bz = zi - rold[2];
+            const PairD pn = pade_d(c, A.b_ee, ax * ax + ay * ay + az * az);
+            const PairD po = pade_d(c, A.b_ee, bx * bx + by * by + bz * bz);
+            gJ[4 * i] += pn.f * ax - po.f * bx;
+            gJ[4 * i + 1] += pn.f * ay - po.f * by;
+            gJ[4 * i + 2] += pn.f * az - po.f * bz;
+            gJ[4 * i + 3] += pn.lap - po.lap;
+            Jo[i] += pn.u - po.u;
+            dv = pn.y - po.y;
+            if (spin_of(A, i) == s) {
+                const int il = i - i0;
+                const double f = wrow[il] * irho;
+                for (int c4 = 0; c4 < 4; ++c4) {
+                    const double *dp = dphi + (i * 4 + c4) * ns;
+                    double acc = 0.0;
+                    for (int j = 0; j < n; ++j) acc += dp[j] * colk[j];
+                    gD[4 * i + c4] -= f * acc;
+                }
+            }
+        } else {
+            for (int c4 = 0; c4 < 4; ++c4) {
+                double acc = 0.0;
+                for (int j = 0; j < n; ++j) acc += vrow[(c4 + 1) * ns + j] * colk[j];
+                gD[4 * k + c4] = acc * irho;
+            }
+        }
+    }
+    // A4b: Jastrow gradient, Laplacian and own sum of electron k at r_new,
+    // and the electron-nucleus change of the potential; partners spread over
+    // the wavefronts after the first (or thread k alone for one wavefront).
+    {
+        const int sk = s;
+        auto partner = [&](int p, double o[6]) {
+            double dx, dy, dz, c, b;
+            if (p < N) {
+                dx = rnew[0] - pos[3 * p]; dy = rnew[1] - pos[3 * p + 1]; dz = rnew[2] - pos[3 * p + 2];
+                c = (spin_of(A, p) == sk) ? 0.25 : 0.5;
+                b = A.b_ee;
+            } else {
+                const double *R = A.Rnuc + 3 * (p - N);
+                dx = rnew[0] - R[0]; dy = rnew[1] - R[1]; dz = rnew[2] - R[2];
+                c = -A.Znuc[p - N];
+                b = A.b_en;
+            }
+            const PairD pr = pade_d(c, b, dx * dx + dy * dy + dz * dz);
+            o[0] += pr.f * dx; o[1] += pr.f * dy; o[2] += pr.f * dz;
+            o[3] += pr.lap;
+            o[4] += pr.u;
+            if (p >= N) {
+                const double *R = A.Rnuc + 3 * (p - N);
+                const double ex = rold[0] - R[0], ey = rold[1] - R[1], ez = rold[2] - R[2];
+                o[5] += c * (pr.y - rsqrt_nr(ex * ex + ey * ey + ez * ez));
+            }
+        };
+        const int np = N + A.n_nuc;
+        if (nw == 1) {
+            if (tid == k) {
+                double o[6] = {0, 0, 0, 0, 0, 0};
+                for (int p = 0; p < np; ++p)
+                    if (p != k) partner(p, o);
+                for (int q = 0; q < 6; ++q) accw[q] = o[q];
+            }
+        } else if (wv >= 1) {
+            double o[6] = {0, 0, 0, 0, 0, 0};
+            for (int p = tid - 64; p < np; p += NT - 64)
+                if (p != k) partner(p, o);
+            for (int q = 0; q < 6; ++q) o[q] = wave_sum(o[q]);
+            if (lane == 0)
+                for (int q = 0; q < 6; ++q) accw[6 * wv + q] = o[q];
         }
     }
     __syncthreads();
-    det_derivs(A, lds + L.Ainv, dphi, lds + L.gD, s);
-    jastrow_all(A, pos, lds + L.gJ, lds + L.Jo, lds + L.Vi);
+
+    // A5: electron k's Jastrow values, the Laplacian terms and the potential
+    // change, reduced over the first wavefront.
+    if (wv == 0) {
+        double term = 0.0, dvn = 0.0;
+        if (tid < N) {
+            if (tid == k) {
+                double o[6] = {0, 0, 0, 0, 0, 0};
+                const int w0 = nw == 1 ? 0 : 1;
+                for (int w = w0; w < max(nw, 1); ++w)
+                    for (int q = 0; q < 6; ++q) o[q] += accw[6 * w + q];
+                gJ[4 * k] = o[0]; gJ[4 * k + 1] = o[1]; gJ[4 * k + 2] = o[2]; gJ[4 * k + 3] = o[3];
+                Jo[k] = o[4];
+                dvn = o[5];
+            }
+            term = psi_lap_term(gD + 4 * tid, gJ + 4 * tid);
+        }
+        term = wave_sum(term);
+        const double dvt = wave_sum(dv + dvn);
+        if (tid == 0) {
+            const double Vn = V + dvt;
+            lds[L.sc + SC_V] = Vn;
+            lds[L.sc + SC_EL] = -0.5 * term + Vn;
+        }
+    }
     __syncthreads();
-    double el, lap, V;
-    local_energy(A, lds, &el, &lap, &V);
-    if (tid == 0) lds[L.sc + SC_EL] = el;
-    __syncthreads();
+    V = lds[L.sc + SC_V];
+    EL = lds[L.sc + SC_EL];
 }
 
 // One workgroup per walker slot: a generation of continuous-time projection,
 // or (eval != 0) the move table at frozen positions.
-__global__ void __launch_bounds__(kMaxThreads) project_kernel(KArgs A)
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) project_kernel(KArgs A)
 {
     extern __shared__ double lds[];
-    __shared__ int sflag[8];  // 0: action, 1: m*, 2-3: pivots, 4: last m with T>0, 5: stop
+    __shared__ int sflag[8];  // 1: m*, 2-3: pivots, 4: last m with T>0, 5: stop
     const Layout &L = A.L;
     const int tid = threadIdx.x, NT = blockDim.x, slot = blockIdx.x, N = A.N, M = A.M;
-    double *pos = lds + L.pos, *sc = lds + L.sc, *T = lds + L.T;
+    const int lane = tid & 63, wv = tid >> 6, nw = NT >> 6;
+    double *pos = lds + L.pos, *T = lds + L.T, *rng = lds + L.rng, *red = lds + L.red;
 
     const int src = A.idx_in ? A.idx_in[slot] : slot;
     for (int t = tid; t < 3 * N; t += NT) pos[t] = A.pos_in[(size_t)src * 3 * N + t];
+    if (A.c_lds)
+        for (int t = tid; t < A.K * A.ns; t += NT) {
+            const int mu = t / A.ns, j = t - mu * A.ns;
+            lds[L.C + t] = A.mo[mu * A.n_orb + j];
+        }
     if (tid == 0) sflag[5] = (A.err[0] != 0);
+    refill_rng(A, rng, slot, 0);
     __syncthreads();
     if (sflag[5]) return;
 
-    int rc = walker_setup(A, lds, sflag);
+    double EL, LAP, V;
+    int rc = walker_setup(A, lds, sflag, EL, LAP, V);
     if (rc) {
         if (tid == 0) report(A.err, rc, slot);
         return;
     }
 
+    // contiguous chunk of moves per thread
+    const int chunk = (M + NT - 1) / NT;
+    const int c0 = min(M, tid * chunk), c1 = min(M, c0 + chunk);
+
     if (A.eval) {
-        if (tid == 0) {
-            double Rm[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
-            if (A.rotate) {
-                double u[4];
-                draw4(A.seed, slot, A.gen, 0, 1, u);
-                rotation(u, Rm);
-            }
-            for (int q = 0; q < 9; ++q) sc[SC_R + q] = Rm[q];
-        }
-        __syncthreads();
         double acc[3] = {0.0, 0.0, 0.0};
-        move_table(A, lds, sc + SC_R, A.rho_out ? A.rho_out + (size_t)slot * M : nullptr,
-                   A.k_out ? A.k_out + (size_t)slot * M : nullptr, acc, true);
-        __syncthreads();
-        double dl = 0.0;
-        for (int m = tid; m < M; m += NT) dl += T[m];
-        double v[4] = {acc[0], acc[1], acc[2], dl};
-        block_sum<4>(v, lds + L.red);
+        int last = -1;
+        const double part = move_table(A, lds, rng, c0, c1, &last,
+                                       A.rho_out ? A.rho_out + (size_t)slot * M : nullptr,
+                                       A.k_out ? A.k_out + (size_t)slot * M : nullptr, acc, true);
+        double v[4] = {acc[0], acc[1], acc[2], part};
+        block_sum<4>(v, red);
         if (tid == 0 && A.diag_out) {
             double *d = A.diag_out + (size_t)slot * LRDMC_NDIAG;
-            const double el = sc[SC_EL], lap = sc[SC_LAP], V = sc[SC_V];
-            const double Va = V + 0.5 * (v[1] - lap);
-            d[0] = el;
+            const double Va = V + 0.5 * (v[1] - LAP);
+            d[0] = EL;
             d[1] = 0.5 * v[0] + Va + v[2] - v[3];
             d[2] = v[1];
-            d[3] = lap;
+            d[3] = LAP;
             d[4] = Va;
             d[5] = v[2];
             d[6] = v[3];
@@ -604,42 +861,64 @@ __global__ void __launch_bounds__(kMaxThreads) project_kernel(KArgs A)
         return;
     }
 
-    if (tid == 0) {
-        sc[SC_TL] = A.tau;
-        sc[SC_LW] = 0.0;
-    }
+    double tl = A.tau, lw = 0.0;
     int moves = 0;
-    const int chunk = (M + NT - 1) / NT;
-    const int c0 = min(M, tid * chunk), c1 = min(M, c0 + chunk);
     for (int it = 0;; ++it) {
+        if (it > 0 && (it & 15) == 0) {
+            refill_rng(A, rng, slot, it);
+            __syncthreads();
+        }
+        const double *R = rng + 12 * (it & 15);
         if (tid == 0) {
-            double Rm[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, u[4];
-            if (A.rotate) {
-                draw4(A.seed, slot, A.gen, (uint64_t)it, 1, u);
-                rotation(u, Rm);
-            }
-            for (int q = 0; q < 9; ++q) sc[SC_R + q] = Rm[q];
-            draw4(A.seed, slot, A.gen, (uint64_t)it, 0, u);
-            sc[SC_U1] = u[0];
-            sc[SC_U2] = u[1];
             sflag[1] = M;
             sflag[4] = -1;
         }
-        __syncthreads();
-        double dummy[3];
-        move_table(A, lds, sc + SC_R, nullptr, nullptr, dummy, false);
-        __syncthreads();
-        // Delta = sum T and the first m with C_m > u2 Delta (workgroup scan)
-        double part = 0.0;
         int last = -1;
-        for (int m = c0; m < c1; ++m) {
-            part += T[m];
-            if (T[m] > 0.0) last = m;
+        double dummy[3];
+        const double part = move_table(A, lds, R, c0, c1, &last, nullptr, nullptr, dummy, false);
+
+        // Delta = sum T and the first m with C_m > u2 Delta (scan over threads)
+        double x = part;
+        for (int off = 1; off < 64; off <<= 1) {
+            const double y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
         }
-        double Delta;
-        const double pre = block_exclusive_scan(part, lds + L.red, &Delta);
-        const double thr = sc[SC_U2] * Delta;
-        if (pre <= thr) {
+        double excl = __shfl_up(x, 1, 64);
+        if (lane == 0) excl = 0.0;
+        if (lane == 63) red[wv] = x;
+        __syncthreads();
+        double pre = excl, Delta = 0.0;
+        for (int w = 0; w < nw; ++w) {
+            const double r = red[w];
+            if (w < wv) pre += r;
+            Delta += r;
+        }
+        // every thread takes the same decision
+        int action = 0;  // 0 stop, 1 move, 2 error
+        double thr = 0.0;
+        if (!(Delta > 0.0)) {
+            lw -= tl * EL;
+        } else if (!isfinite(Delta)) {
+            action = 2;
+        } else {
+            const double td = -log(R[9]) / Delta;
+            if (td >= tl) {
+                lw -= tl * EL;
+            } else {
+                lw -= td * EL;
+                tl -= td;
+                action = it + 1 >= kMaxIter ? 3 : 1;
+                thr = R[10] * Delta;
+            }
+        }
+        if (action != 1) {
+            if (action >= 2) {
+                if (tid == 0) report(A.err, action == 2 ? kErrNonFinite : kErrIterCap, slot);
+                return;
+            }
+            break;
+        }
+        if (pre <= thr && c1 > c0) {
             double C = pre;
             for (int m = c0; m < c1; ++m) {
                 C += T[m];
@@ -651,60 +930,27 @@ __global__ void __launch_bounds__(kMaxThreads) project_kernel(KArgs A)
         }
         if (last >= 0) atomicMax(&sflag[4], last);
         __syncthreads();
-        if (tid == 0) {
-            const double EL = sc[SC_EL];
-            int action = 0;  // 0 stop, 1 move, 2 error
-            if (!(Delta > 0.0)) {
-                sc[SC_LW] -= sc[SC_TL] * EL;
-            } else if (!isfinite(Delta)) {
-                action = 2;
-            } else {
-                const double td = -log(sc[SC_U1]) / Delta;
-                if (td >= sc[SC_TL]) {
-                    sc[SC_LW] -= sc[SC_TL] * EL;
-                } else {
-                    sc[SC_LW] -= td * EL;
-                    sc[SC_TL] -= td;
-                    int ms = sflag[1];
-                    if (ms >= M) ms = sflag[4];
-                    if (ms < 0) {
-                        action = 2;
-                    } else if (it + 1 >= kMaxIter) {
-                        action = 3;
-                    } else {
-                        action = 1;
-                        sflag[1] = ms;
-                        double rp[3];
-                        move_geometry(A, pos, sc + SC_R, ms, rp);
-                        sc[SC_RP] = rp[0]; sc[SC_RP + 1] = rp[1]; sc[SC_RP + 2] = rp[2];
-                    }
-                }
-            }
-            sflag[0] = action;
+        int ms = sflag[1];
+        if (ms >= M) ms = sflag[4];
+        if (ms < 0) {
+            if (tid == 0) report(A.err, kErrNonFinite, slot);
+            return;
         }
-        __syncthreads();
-        const int action = sflag[0];
-        if (action != 1) {
-            if (action >= 2) {
-                if (tid == 0) report(A.err, action == 2 ? kErrNonFinite : kErrIterCap, slot);
-                return;
-            }
-            break;
-        }
-        accept_move(A, lds, sflag[1] / 12);
+        const int k = ms / 12;
+        double rnew[3];
+        move_position(A, pos, R, ms, rnew);
+        const double rold[3] = {pos[3 * k], pos[3 * k + 1], pos[3 * k + 2]};
+        accept_move(A, lds, k, rold, rnew, EL, V);
         ++moves;
-        if (tid == 0 && !isfinite(sc[SC_EL])) sflag[5] = 1;
-        __syncthreads();
-        if (sflag[5]) {
+        if (!isfinite(EL)) {
             if (tid == 0) report(A.err, kErrNonFinite, slot);
             return;
         }
     }
     for (int t = tid; t < 3 * N; t += NT) A.pos_out[(size_t)slot * 3 * N + t] = pos[t];
     if (tid == 0) {
-        const double lw = sc[SC_LW];
         A.logw[slot] = lw;
-        A.el[slot] = sc[SC_EL];
+        A.el[slot] = EL;
         A.nmov[slot] = moves;
         if (!isfinite(lw)) report(A.err, kErrNonFinite, slot);
     }
@@ -811,7 +1057,8 @@ struct lrdmc_ctx {
     double b_ee = 0, b_en = 0, v_nn = 0;
     lrdmc_params prm{};
     double *d_Z = nullptr, *d_R = nullptr, *d_mo = nullptr, *d_galpha = nullptr;
-    int *d_heavy = nullptr, *d_gnuc = nullptr, *d_goff = nullptr;
+    int *d_heavy = nullptr, *d_gnuc = nullptr, *d_goff = nullptr, *d_chain = nullptr;
+    int n_chain = 0;
     double *d_pos[2] = {nullptr, nullptr};
     int cur = 0;
     double *d_logw = nullptr, *d_el = nullptr, *d_cw = nullptr;
@@ -822,6 +1069,13 @@ struct lrdmc_ctx {
     size_t lds_bytes = 0;
     Layout L{};
     std::string err;
+    // event timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, int>> ev_pending;  // (kind 0 project / 1 branch, first event index)
+    int ev_used = 0;
+    double t_ms[2] = {0.0, 0.0};
+    long long t_n[2] = {0, 0};
 };
 
 namespace {
@@ -841,7 +1095,10 @@ int fail(lrdmc_ctx *ctx, int code, const std::string &msg)
                         std::string(#expr) + ": " + hipGetErrorString(e_));                         \
     } while (0)
 
-Layout make_layout(int N, int ns, int K, int Kp, int M)
+// LDS layout of one walker.  c_lds: stage the occupied MO block.  The
+// electron batch of the generation start grows until the block reaches
+// `target` bytes (or all electrons fit), never below one electron.
+Layout make_layout(int N, int ns, int K, int Kp, int M, bool c_lds, size_t target)
 {
     Layout L{};
     int o = 0;
@@ -853,19 +1110,34 @@ Layout make_layout(int N, int ns, int K, int Kp, int M)
     L.gD = take(4 * N);
     L.gJ = take(4 * N);
     L.Jo = take(N);
-    L.Vi = take(N);
-    L.T = take(M);
-    L.bv = take(5 * K);
-    L.vrow = take(5 * ns);
-    L.wrow = take(ns);
-    L.colk = take(ns);
-    L.Yk = take(Kp);
-    L.G = take(2 * ns * 2 * ns);
-    L.piv = take(2 * 2 * 2 * ns);
-    L.fac = take(2 * ns);
+    L.C = c_lds ? take(K * ns) : -1;
     L.red = take(64);
     L.sc = take(32);
-    L.total = o;
+    L.rng = take(16 * 12);
+    L.acc = take(32);
+    const int U = o;
+    // move-loop view
+    int q = U;
+    L.T = q; q += M;
+    L.bv = q; q += 5 * K;
+    L.vrow = q; q += 5 * ns;
+    L.wrow = q; q += ns;
+    L.colk = q; q += ns;
+    L.Yk = q; q += Kp;
+    const int loop_end = q;
+    // generation-start view
+    q = U;
+    L.G = q; q += 2 * ns * 2 * ns;
+    L.piv = q; q += 2 * 2 * 2 * ns;
+    L.fac = q; q += 2 * ns;
+    L.bvb = q;
+    const int fixed_end = q;
+    int EB = 1;
+    while (EB < N && (size_t)(fixed_end + (EB + 1) * 5 * K) * sizeof(double) <= target &&
+           fixed_end + (EB + 1) * 5 * K <= loop_end + 5 * K)
+        ++EB;
+    L.EB = EB;
+    L.total = std::max(loop_end, fixed_end + EB * 5 * K);
     return L;
 }
 
@@ -876,7 +1148,8 @@ KArgs base_args(const lrdmc_ctx *c)
     A.n_orb = c->n_orb; A.n_nuc = c->n_nuc; A.n_grp = c->n_grp; A.n_heavy = c->n_heavy; A.M = c->M;
     A.Znuc = c->d_Z; A.Rnuc = c->d_R; A.heavy = c->d_heavy; A.grp_nuc = c->d_gnuc;
     A.grp_alpha = c->d_galpha; A.grp_off = c->d_goff; A.mo = c->d_mo;
-    A.b_ee = c->b_ee; A.b_en = c->b_en; A.v_nn = c->v_nn;
+    A.n_chain = c->n_chain; A.chain = c->d_chain;
+    A.b_ee = c->b_ee; A.b_en = c->b_en; A.v_nn = c->v_nn; A.c_lds = c->L.C >= 0;
     A.a = c->prm.a; A.ap = c->prm.a_prime;
     A.inv_a2 = 1.0 / (c->prm.a * c->prm.a);
     A.inv_ap2 = 1.0 / (c->prm.a_prime * c->prm.a_prime);
@@ -886,9 +1159,12 @@ KArgs base_args(const lrdmc_ctx *c)
     return A;
 }
 
+void timing_collect(lrdmc_ctx *c);
+
 int check_kernel_error(lrdmc_ctx *c, hipStream_t st)
 {
     HIP_TRY(c, hipStreamSynchronize(st));
+    timing_collect(c);
     int e[2] = {0, 0};
     HIP_TRY(c, hipMemcpy(e, c->d_err, sizeof(e), hipMemcpyDeviceToHost));
     if (e[0] == 0) return LRDMC_OK;
@@ -908,6 +1184,44 @@ int check_kernel_error(lrdmc_ctx *c, hipStream_t st)
     }
 }
 
+// Record a start event for a kernel of the given kind; returns the index of
+// the event pair or -1 when timing is off.
+int timing_begin(lrdmc_ctx *c, hipStream_t st, int kind)
+{
+    if (!c->timing) return -1;
+    if (c->ev_used + 2 > (int)c->ev_pool.size()) {
+        for (int q = 0; q < 64; ++q) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return -1;
+            c->ev_pool.push_back(e);
+        }
+    }
+    const int i = c->ev_used;
+    c->ev_used += 2;
+    if (hipEventRecord(c->ev_pool[i], st) != hipSuccess) return -1;
+    c->ev_pending.push_back({kind, i});
+    return i;
+}
+
+void timing_end(lrdmc_ctx *c, hipStream_t st, int i)
+{
+    if (i >= 0) (void)hipEventRecord(c->ev_pool[i + 1], st);
+}
+
+// After the stream has been synchronized: fold the recorded pairs into the totals.
+void timing_collect(lrdmc_ctx *c)
+{
+    for (const auto &p : c->ev_pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->ev_pool[p.second], c->ev_pool[p.second + 1]) == hipSuccess) {
+            c->t_ms[p.first] += ms;
+            c->t_n[p.first] += 1;
+        }
+    }
+    c->ev_pending.clear();
+    c->ev_used = 0;
+}
+
 int launch_project(lrdmc_ctx *c, hipStream_t st, const double *pos_in, const int *idx_in, double *pos_out,
                    int eval, double *rho, double *k, double *diag)
 {
@@ -922,16 +1236,20 @@ int launch_project(lrdmc_ctx *c, hipStream_t st, const double *pos_in, const int
     A.rho_out = rho;
     A.k_out = k;
     A.diag_out = diag;
+    const int ev = eval ? -1 : timing_begin(c, st, 0);
     hipLaunchKernelGGL(project_kernel, dim3(c->W), dim3(c->nt), c->lds_bytes, st, A);
     HIP_TRY(c, hipGetLastError());
+    timing_end(c, st, ev);
     return LRDMC_OK;
 }
 
 int launch_branch(lrdmc_ctx *c, hipStream_t st, double *lwb, double *eb, int64_t *nm, int *idx_out)
 {
+    const int ev = timing_begin(c, st, 1);
     hipLaunchKernelGGL(reconfigure_kernel, dim3(1), dim3(1024), 0, st, c->d_logw, c->d_el, c->d_nmov, c->W,
                        -1.0, c->prm.seed, c->gen, c->d_cw, c->d_idx, lwb, eb, (long long *)nm, c->d_err);
     HIP_TRY(c, hipGetLastError());
+    timing_end(c, st, ev);
     if (idx_out)
         HIP_TRY(c, hipMemcpyAsync(idx_out, c->d_idx, sizeof(int) * c->W, hipMemcpyDeviceToDevice, st));
     return LRDMC_OK;
@@ -1065,11 +1383,51 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
         mu += 2 * l + 1;
     }
 
+    // Order groups by nucleus and exponent; cut them into chains whose
+    // exponent ratio is one constant beta (step code 1, 2, 3 for beta = 2,
+    // 2.5, 3; 0 for anything else).
+    {
+        std::vector<int> order(gnuc.size());
+        for (size_t g = 0; g < order.size(); ++g) order[g] = (int)g;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+            return gnuc[x] != gnuc[y] ? gnuc[x] < gnuc[y] : galpha[x] < galpha[y];
+        });
+        std::vector<int> n2, o2;
+        std::vector<double> a2;
+        for (int g : order) {
+            n2.push_back(gnuc[g]);
+            a2.push_back(galpha[g]);
+            o2.insert(o2.end(), {goff[3 * g], goff[3 * g + 1], goff[3 * g + 2]});
+        }
+        gnuc.swap(n2);
+        galpha.swap(a2);
+        goff.swap(o2);
+    }
+    std::vector<int> chains;
+    {
+        auto code_of = [](double ratio) {
+            const double betas[3] = {2.0, 2.5, 3.0};
+            for (int q = 0; q < 3; ++q)
+                if (std::fabs(ratio - betas[q]) <= 1e-12 * betas[q]) return q + 1;
+            return 0;
+        };
+        size_t g = 0;
+        while (g < gnuc.size()) {
+            size_t e = g + 1;
+            int code = 0;
+            if (e < gnuc.size() && gnuc[e] == gnuc[g] && galpha[g] > 0.0) code = code_of(galpha[e] / galpha[g]);
+            if (code)
+                while (e < gnuc.size() && gnuc[e] == gnuc[g] && code_of(galpha[e] / galpha[e - 1]) == code) ++e;
+            chains.insert(chains.end(), {(int)g, (int)(e - g), code});
+            g = e;
+        }
+    }
+
     lrdmc_ctx *c = new (std::nothrow) lrdmc_ctx();
     if (!c) return fail(nullptr, LRDMC_ENOMEM, "lrdmc_create: host allocation");
     c->W = n_walkers; c->N = N; c->n_up = sys->n_up; c->n_dn = sys->n_dn; c->ns = ns; c->K = K;
     c->Kp = K | 1; c->n_orb = sys->n_orb; c->n_nuc = sys->n_nuc; c->n_grp = (int)gnuc.size();
-    c->n_heavy = (int)heavy.size(); c->M = 12 * N; c->b_ee = sys->b_ee; c->b_en = sys->b_en; c->prm = *prm;
+    c->n_heavy = (int)heavy.size(); c->M = 12 * N; c->n_chain = (int)chains.size() / 3; c->b_ee = sys->b_ee; c->b_en = sys->b_en; c->prm = *prm;
     double vnn = 0.0;
     for (int I = 0; I < sys->n_nuc; ++I)
         for (int J = I + 1; J < sys->n_nuc; ++J) {
@@ -1079,7 +1437,10 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
         }
     c->v_nn = vnn;
     c->nt = std::min(kMaxThreads, std::max(64, ((c->M + 63) / 64) * 64));
-    c->L = make_layout(N, ns, K, c->Kp, c->M);
+    // Stage the occupied MO block in LDS only for small walker states; larger
+    // ones read it through the caches so that more walkers share a CU.
+    c->L = make_layout(N, ns, K, c->Kp, c->M, true, 32 * 1024);
+    if (sizeof(double) * (size_t)c->L.total > 16 * 1024) c->L = make_layout(N, ns, K, c->Kp, c->M, false, 32 * 1024);
     c->lds_bytes = sizeof(double) * (size_t)c->L.total;
 
     auto cleanup = [&](int code, const std::string &m) {
@@ -1105,6 +1466,7 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
               alloc((void **)&c->d_galpha, sizeof(double) * gnuc.size()) &&
               alloc((void **)&c->d_gnuc, sizeof(int) * gnuc.size()) &&
               alloc((void **)&c->d_goff, sizeof(int) * goff.size()) &&
+              alloc((void **)&c->d_chain, sizeof(int) * chains.size()) &&
               alloc((void **)&c->d_heavy, sizeof(int) * heavy.size()) &&
               alloc((void **)&c->d_pos[0], sizeof(double) * W * s3) &&
               alloc((void **)&c->d_pos[1], sizeof(double) * W * s3) &&
@@ -1118,6 +1480,7 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
          hipMemcpy(c->d_galpha, galpha.data(), sizeof(double) * gnuc.size(), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(c->d_gnuc, gnuc.data(), sizeof(int) * gnuc.size(), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(c->d_goff, goff.data(), sizeof(int) * goff.size(), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(c->d_chain, chains.data(), sizeof(int) * chains.size(), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(c->d_heavy, heavy.data(), sizeof(int) * heavy.size(), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemset(c->d_err, 0, 2 * sizeof(int)) == hipSuccess &&
          hipMemset(c->d_logw, 0, sizeof(double) * W) == hipSuccess &&
@@ -1242,6 +1605,27 @@ int lrdmc_reconfigure(const double *log_w, const double *e_loc, int32_t W, doubl
     return LRDMC_OK;
 }
 
+int lrdmc_set_timing(lrdmc_ctx *c, int32_t enable)
+{
+    if (!c) return fail(nullptr, LRDMC_EINVAL, "lrdmc_set_timing: NULL context");
+    c->timing = enable != 0;
+    c->t_ms[0] = c->t_ms[1] = 0.0;
+    c->t_n[0] = c->t_n[1] = 0;
+    c->ev_pending.clear();
+    c->ev_used = 0;
+    return LRDMC_OK;
+}
+
+int lrdmc_timing(const lrdmc_ctx *c, double *out)
+{
+    if (!c || !out) return fail(nullptr, LRDMC_EINVAL, "lrdmc_timing: NULL argument");
+    out[0] = c->t_ms[0];
+    out[1] = (double)c->t_n[0];
+    out[2] = c->t_ms[1];
+    out[3] = (double)c->t_n[1];
+    return LRDMC_OK;
+}
+
 uint64_t lrdmc_generation(const lrdmc_ctx *c) { return c ? c->gen : 0; }
 
 const char *lrdmc_last_error(const lrdmc_ctx *c) { return c ? c->err.c_str() : g_error.c_str(); }
@@ -1249,10 +1633,11 @@ const char *lrdmc_last_error(const lrdmc_ctx *c) { return c ? c->err.c_str() : g
 void lrdmc_destroy(lrdmc_ctx *c)
 {
     if (!c) return;
-    void *ptrs[] = {c->d_Z,    c->d_R,    c->d_mo,   c->d_galpha, c->d_gnuc, c->d_goff, c->d_heavy, c->d_pos[0],
+    void *ptrs[] = {c->d_Z,    c->d_R,    c->d_mo,   c->d_galpha, c->d_gnuc, c->d_goff, c->d_chain, c->d_heavy, c->d_pos[0],
                     c->d_pos[1], c->d_logw, c->d_el, c->d_cw,     c->d_nmov, c->d_idx,  c->d_err};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }
 

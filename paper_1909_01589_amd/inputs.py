@@ -257,15 +257,16 @@ class Config:
 
 def _configs() -> Dict[str, Config]:
     # tau follows the rule "about one move per electron per generation":
-    # tau = N / <Delta>, <Delta> measured on equilibrated walkers of each
-    # workload and frozen here with three significant figures.
+    # tau = N / <Delta>, <Delta> = mean total move rate of 512 walkers after
+    # 60 generations of equilibration on the MI355X, frozen here with three
+    # significant figures.
     out = {
-        "be": Config("be", be_like(0), a=0.2, walkers=512, generations=500, tau=0.0161),
-        "ar_a0.2": Config("ar_a0.2", ar_like(0), a=0.2, walkers=4096, generations=2000, tau=0.0109),
-        "ar_a0.1": Config("ar_a0.1", ar_like(0), a=0.1, walkers=4096, generations=2000, tau=0.00318),
-        "molecule": Config("molecule", molecule(0), a=1.0 / 28.0, walkers=16384, generations=100, tau=0.00150),
+        "be": Config("be", be_like(0), a=0.2, walkers=512, generations=500, tau=0.0217),
+        "ar_a0.2": Config("ar_a0.2", ar_like(0), a=0.2, walkers=4096, generations=2000, tau=0.0375),
+        "ar_a0.1": Config("ar_a0.1", ar_like(0), a=0.1, walkers=4096, generations=2000, tau=0.00842),
+        "molecule": Config("molecule", molecule(0), a=1.0 / 28.0, walkers=16384, generations=100, tau=0.00179),
     }
-    for Z, tau in ((10, 0.00147), (18, 0.00148), (36, 0.000575), (54, 0.000319)):
+    for Z, tau in ((10, 0.00115), (18, 0.000473), (36, 0.000167), (54, 0.0000912)):
         out[f"zsweep{Z}"] = Config(f"zsweep{Z}", zsweep_atom(Z, 0), a=1.0 / (3.5 * Z),
                                    walkers=8192, generations=100, tau=tau)
     return out

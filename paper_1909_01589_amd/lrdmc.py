@@ -54,7 +54,7 @@ class lrdmc_params(C.Structure):
 _lib = None
 EXPORTS = ("lrdmc_spacing", "lrdmc_create", "lrdmc_set_walkers", "lrdmc_project", "lrdmc_branch",
            "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure",
-           "lrdmc_generation", "lrdmc_last_error", "lrdmc_destroy")
+           "lrdmc_set_timing", "lrdmc_timing", "lrdmc_generation", "lrdmc_last_error", "lrdmc_destroy")
 
 
 def load():
@@ -75,6 +75,8 @@ def load():
     lib.lrdmc_get_walkers.argtypes = [P, P, P, P, P, P]
     lib.lrdmc_eval_moves.argtypes = [P, P, P, P, P, P]
     lib.lrdmc_reconfigure.argtypes = [P, P, I32, D, P, P, P]
+    lib.lrdmc_set_timing.argtypes = [P, I32]
+    lib.lrdmc_timing.argtypes = [P, P]
     lib.lrdmc_generation.argtypes = [P]
     lib.lrdmc_generation.restype = U64
     lib.lrdmc_last_error.argtypes = [P]
@@ -82,7 +84,8 @@ def load():
     lib.lrdmc_destroy.argtypes = [P]
     lib.lrdmc_destroy.restype = None
     for name in ("lrdmc_spacing", "lrdmc_create", "lrdmc_set_walkers", "lrdmc_project", "lrdmc_branch",
-                 "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure"):
+                 "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure",
+                 "lrdmc_set_timing", "lrdmc_timing"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -181,6 +184,17 @@ def lrdmc_reconfigure(log_w, e_loc, xi: float, idx, stats=None, stream=None):
     _check(load().lrdmc_reconfigure(_dptr(log_w, torch.float64), _dptr(e_loc, torch.float64),
                                     int(log_w.shape[0]), float(xi), _dptr(idx, torch.int32),
                                     _dptr(stats, torch.float64), _stream(stream)))
+
+
+def lrdmc_set_timing(ctx, enable: bool = True):
+    _check(load().lrdmc_set_timing(ctx, 1 if enable else 0), ctx)
+
+
+def lrdmc_timing(ctx):
+    """(projection ms, projection launches, reconfiguration ms, launches)."""
+    out = (C.c_double * 4)()
+    _check(load().lrdmc_timing(ctx, out), ctx)
+    return tuple(out)
 
 
 def lrdmc_generation(ctx) -> int:

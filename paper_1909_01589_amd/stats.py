@@ -29,8 +29,14 @@ def reblock_error(y: np.ndarray, min_blocks: int = 16) -> float:
     return float(max(errs)) if errs else float("nan")
 
 
-def estimate(log_wbar, ebar, p: int = 0, skip: int = 0):
-    """(E_p, sigma) from generation records, skipping the first `skip`."""
+def estimate(log_wbar, ebar, p=None, skip: int = 0):
+    """(E, sigma) from generation records, skipping the first `skip`.
+    p=None: plain mean of e_bar_n (no correcting factors); p >= 0: E_p."""
+    if p is None:
+        e = np.asarray(ebar, dtype=np.float64)[skip:]
+        if e.size == 0:
+            return float("nan"), float("nan")
+        return float(e.mean()), reblock_error(e)
     lg = _log_gamma(np.asarray(log_wbar)[skip:], p)
     e = np.asarray(ebar, dtype=np.float64)[skip:]
     keep = np.isfinite(lg)
