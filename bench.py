@@ -80,7 +80,7 @@ def run_workload(name, steps, warmup, want_cpu, cpu_seconds):
     s = cfg.system
     rc, ap, nc = lrdmc_spacing(s.z_max, cfg.a)
     W = cfg.walkers
-    gpu = LRDMC(s, cfg.a, ap, rc, cfg.tau, W, seed=cfg.seed, rotate=cfg.rotate)
+    gpu = LRDMC(s, cfg.a, ap, rc, cfg.tau, W, seed=cfg.seed, rotate=cfg.rotate, refresh=cfg.refresh)
     gpu.set_walkers(inputs.initial_walkers(s, W, cfg.seed), 0)
     if warmup:
         gpu.run(warmup)
@@ -113,6 +113,7 @@ def run_workload(name, steps, warmup, want_cpu, cpu_seconds):
         "E_Ha": E, "sigma_E_Ha": sig,
         "time_to_sigma_1mHa_s": wall * (sig / 1e-3) ** 2 if np.isfinite(sig) else None,
         "a": cfg.a, "a_prime": ap, "r_c": rc, "n_core": nc, "tau": cfg.tau, "walkers": W,
+        "refresh": cfg.refresh,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
                      "kernel": "project_kernel", "avg_launch_ms": avg_ms,
@@ -167,6 +168,7 @@ def main():
                         f"{cfg.walkers} walkers, tau={cfg.tau} per generation",
             "walkers": cfg.walkers, "electrons": s.n_elec, "basis": s.n_basis,
             "a": cfg.a, "a_prime": main_res["a_prime"], "r_c": main_res["r_c"], "tau": cfg.tau,
+            "refresh": cfg.refresh,
         },
         "roofline": main_res["roofline"],
         "moves_per_walker_gen": main_res["moves_per_walker_gen"],

@@ -92,12 +92,17 @@ typedef struct {
  * a: small (core) spacing; a_prime: large spacing, a_prime >= a;
  * r_c: width of the switch p (main text Eq. (3)); nuclei with Z >= z_heavy
  * define R_c; tau: projection time per generation (1/Ha); seed: Philox key;
- * rotate: random lattice orientation per move (0 = fixed x, y, z axes). */
+ * rotate: random lattice orientation per move (0 = fixed x, y, z axes);
+ * refresh: generations between recomputations of a walker's inverse Slater
+ * matrices and derivative tables from its positions.  0 or 1 recomputes at
+ * every generation start; R > 1 keeps the Sherman-Morrison-updated state in
+ * device memory and recomputes it at generations that are multiples of R
+ * (and after lrdmc_set_walkers).  The results agree up to rounding. */
 typedef struct {
     double a, a_prime, r_c, z_heavy, tau;
     uint64_t seed;
     int32_t rotate;
-    int32_t reserved;           /* must be 0                                 */
+    int32_t refresh;
 } lrdmc_params;
 
 /* Host-side parameter choice of the paper for heaviest charge Z and small
@@ -115,7 +120,7 @@ int lrdmc_spacing(double Z, double a, double beta, double kappa,
  * Errors: LRDMC_EINVAL (n_walkers < 1; n_up < 1; n_dn < 0; max(n_up, n_dn)
  * > 32; N > 64; n_orb < max(n_up, n_dn); K > 512; n_nuc < 1 or > 64; l
  * outside 0..2; alpha < 0; a <= 0; a_prime < a; r_c <= 0; tau <= 0; no
- * nucleus with Z >= z_heavy; reserved != 0), LRDMC_ENOMEM, LRDMC_EDEVICE. */
+ * nucleus with Z >= z_heavy; refresh < 0), LRDMC_ENOMEM, LRDMC_EDEVICE. */
 int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm,
                  int32_t n_walkers, lrdmc_ctx **out);
 

@@ -49,14 +49,16 @@ struct Layout {
     int pos;    // [N][3]            positions
     int Y;      // [N][Kp]           Y[i][mu] = sum_j C[mu][j] Ainv_sigma(i)[j][i_sigma]
     int Ainv;   // [2][ns][ns]       Ainv_sigma[j][i]
-    int dphi;   // [N][4][ns]        grad (x,y,z) and Laplacian of phi_j at r_i
+    int dphi;   // [N][dld]          grad (x,y,z) and Laplacian of phi_j at r_i: [i*dld + c*ns + j]
+    int dld;    // 4 ns + 1 (odd: electrons on different LDS banks)
     int gD;     // [N][4]            grad D/D (3) and lap D/D of electron i
     int gJ;     // [N][4]            grad J (3) and lap J of electron i
     int Jo;     // [N]               Jastrow terms that contain electron i
     int C;      // [K][ns]           MO coefficients of the occupied orbitals, or -1 (read from HBM)
     int red;    // [64]              reduction scratch
     int sc;     // [32]              block scalars
-    int rng;    // [16][12]          rotations and (u1, u2) of the next sixteen iterations
+    int rng;    // [2][8][12]        rotations, -ln u1 and u2 of sixteen iterations (two halves)
+    int xs;     // [NT]              per-thread inclusive prefix of T within its wavefront
     int acc;    // [4][6]            per-wavefront partial sums of the moved electron's Jastrow
     // move-loop view of U
     int T;      // [M]               heat-bath weights of the moves
@@ -82,6 +84,7 @@ struct KArgs {
     const int *grp_nuc;            // [n_grp]
     const double *grp_alpha;       // [n_grp]
     const int *grp_off;            // [n_grp][3] first basis index of the s, p, d shell, -1 if none
+    const int *fn_info;            // [K]: group | l << 16 | component << 20
     int n_chain;
     const int *chain;              // [n_chain][3]: first group, length, step code (see basis_dot)
     const double *mo;              // [K][n_orb]
@@ -96,6 +99,9 @@ struct KArgs {
     uint64_t gen;
     const double *pos_in;
     const int *idx_in;             // gather on load, or nullptr
+    const double *state_in;        // walker state blobs to resume from, or nullptr (recompute)
+    double *state_out;             // walker state blobs at the end of the projection
+    int state_len;                 // doubles per blob: LDS [Y, Jo + N) plus E_L and V
     double *pos_out, *logw, *el;
     int *nmov;
     int *err;
@@ -115,54 +121,52 @@ __device__ __forceinline__ void report(int *err, int code, int slot)
 
 __device__ __forceinline__ int spin_of(const KArgs &A, int i) { return i < A.n_up ? 0 : 1; }
 
+// Values that every lane of the workgroup holds identically are moved to
+// scalar registers (they are read from LDS, so the compiler cannot prove it).
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ double uni(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // -- basis -------------------------------------------------------------------
 
-// Values, gradients and Laplacians of every function of group g at r into
-// bv[5][K].  For a harmonic polynomial P of degree l:
-// grad g = (grad P - 2 alpha d P) e, lap g = (4 alpha^2 d^2 - (6 + 4 l) alpha) P e.
-__device__ void basis_group_full(const KArgs &A, int g, const double r[3], double *bv)
+// Value, gradient and Laplacian of basis function mu at r into bv[5][Kp].
+// For a harmonic polynomial P of degree l: grad g = (grad P - 2 alpha d P) e,
+// lap g = (4 alpha^2 d^2 - (6 + 4 l) alpha) P e.
+__device__ __forceinline__ void basis_fn_full(const KArgs &A, int mu, const double r[3], double *bv)
 {
-    const int K = A.K;
+    const int K = A.Kp, info = A.fn_info[mu];
+    const int g = info & 0xffff, l = (info >> 16) & 0xf, c = info >> 20;
     const double *Rn = A.Rnuc + 3 * A.grp_nuc[g];
-    const double dx = r[0] - Rn[0], dy = r[1] - Rn[1], dz = r[2] - Rn[2];
-    const double d2 = dx * dx + dy * dy + dz * dz;
+    const double d[3] = {r[0] - Rn[0], r[1] - Rn[1], r[2] - Rn[2]};
+    const double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
     const double al = A.grp_alpha[g];
     const double e = exp(-al * d2);
+    double P, dP[3];
+    if (l == 0) {
+        P = 1.0; dP[0] = dP[1] = dP[2] = 0.0;
+    } else if (l == 1) {
+        P = d[c]; dP[0] = dP[1] = dP[2] = 0.0; dP[c] = 1.0;
+    } else {
+        const double x = d[0], y = d[1], z = d[2];
+        switch (c) {
+        case 0: P = x * y; dP[0] = y; dP[1] = x; dP[2] = 0.0; break;
+        case 1: P = y * z; dP[0] = 0.0; dP[1] = z; dP[2] = y; break;
+        case 2: P = z * x; dP[0] = z; dP[1] = 0.0; dP[2] = x; break;
+        case 3: P = x * x - y * y; dP[0] = 2.0 * x; dP[1] = -2.0 * y; dP[2] = 0.0; break;
+        default: P = 2.0 * z * z - x * x - y * y; dP[0] = -2.0 * x; dP[1] = -2.0 * y; dP[2] = 4.0 * z; break;
+        }
+    }
     const double t2a = 2.0 * al;
-    const double q = 4.0 * al * al * d2;
-    const int *off = A.grp_off + 3 * g;
-    if (off[0] >= 0) {
-        const int mu = off[0];
-        bv[mu] = e;
-        bv[K + mu] = -t2a * dx * e;
-        bv[2 * K + mu] = -t2a * dy * e;
-        bv[3 * K + mu] = -t2a * dz * e;
-        bv[4 * K + mu] = (q - 6.0 * al) * e;
-    }
-    if (off[1] >= 0) {
-        const int mu = off[1];
-        const double d[3] = {dx, dy, dz};
-        const double lf = (q - 10.0 * al) * e;
-        for (int c = 0; c < 3; ++c) {
-            bv[mu + c] = d[c] * e;
-            for (int k = 0; k < 3; ++k)
-                bv[(1 + k) * K + mu + c] = ((k == c ? 1.0 : 0.0) - t2a * d[k] * d[c]) * e;
-            bv[4 * K + mu + c] = d[c] * lf;
-        }
-    }
-    if (off[2] >= 0) {
-        const int mu = off[2];
-        const double P[5] = {dx * dy, dy * dz, dz * dx, dx * dx - dy * dy, 2.0 * dz * dz - dx * dx - dy * dy};
-        const double dP[5][3] = {{dy, dx, 0.0}, {0.0, dz, dy}, {dz, 0.0, dx},
-                                 {2.0 * dx, -2.0 * dy, 0.0}, {-2.0 * dx, -2.0 * dy, 4.0 * dz}};
-        const double d[3] = {dx, dy, dz};
-        const double lf = (q - 14.0 * al) * e;
-        for (int c = 0; c < 5; ++c) {
-            bv[mu + c] = P[c] * e;
-            for (int k = 0; k < 3; ++k) bv[(1 + k) * K + mu + c] = (dP[c][k] - t2a * d[k] * P[c]) * e;
-            bv[4 * K + mu + c] = P[c] * lf;
-        }
-    }
+    bv[mu] = P * e;
+    bv[K + mu] = (dP[0] - t2a * d[0] * P) * e;
+    bv[2 * K + mu] = (dP[1] - t2a * d[1] * P) * e;
+    bv[3 * K + mu] = (dP[2] - t2a * d[2] * P) * e;
+    bv[4 * K + mu] = (4.0 * al * al * d2 - (6.0 + 4.0 * l) * al) * P * e;
 }
 
 // sqrt of e in [0, 1] through the refined reciprocal square root; values
@@ -254,18 +258,17 @@ __device__ __forceinline__ MoView mo_view(const KArgs &A, const double *lds)
     return {A.mo, A.n_orb};
 }
 
-// out(e, c, j) = sum_mu b[e][c][mu] C[mu][j] for ne basis blocks b[e][5][K],
+// out(e, c, j) = sum_mu b[e][c][mu] C[mu][j] for ne basis blocks b[e][5][Kp],
 // c < 5, j < n.  Each output is split over P adjacent lanes (a power of two,
-// at most 16) that sum slices of mu and combine with lane shuffles, so the
-// loads of one output are independent and the chains short.
+// at most 16); lane p sums mu = p, p + P, ... (neighbouring lanes touch
+// neighbouring LDS banks) and the lanes combine with shuffles.
 template <typename Store>
 __device__ __forceinline__ void orb_contract(const KArgs &A, const double *b, int ne, int n, MoView C,
                                              Store store)
 {
-    const int K = A.K, NT = blockDim.x, nout = ne * 5 * n;
+    const int K = A.K, Kp = A.Kp, NT = blockDim.x, nout = ne * 5 * n;
     int P = 1;
     while (P < 16 && nout * P * 2 <= NT) P <<= 1;
-    const int S = (K + P - 1) / P;
     for (int base = 0; base < nout * P; base += NT) {
         const int t = base + threadIdx.x, o = t / P, part = t - o * P;
         double acc0 = 0.0, acc1 = 0.0;
@@ -275,14 +278,13 @@ __device__ __forceinline__ void orb_contract(const KArgs &A, const double *b, in
             const int r = o - e * 5 * n;
             c = r / n;
             j = r - c * n;
-            const double *bb = b + (e * 5 + c) * K;
-            const int mu1 = min(K, (part + 1) * S);
-            int mu = part * S;
-            for (; mu + 1 < mu1; mu += 2) {
+            const double *bb = b + (e * 5 + c) * Kp;
+            int mu = part;
+            for (; mu + P < K; mu += 2 * P) {
                 acc0 += bb[mu] * C.p[mu * C.ld + j];
-                acc1 += bb[mu + 1] * C.p[(mu + 1) * C.ld + j];
+                acc1 += bb[mu + P] * C.p[(mu + P) * C.ld + j];
             }
-            if (mu < mu1) acc0 += bb[mu] * C.p[mu * C.ld + j];
+            if (mu < K) acc0 += bb[mu] * C.p[mu * C.ld + j];
         }
         double acc = acc0 + acc1;
         for (int off = P >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -356,21 +358,31 @@ __device__ __forceinline__ PairD pade_d(double c, double b, double d2)
 }
 
 // Jastrow terms containing electron i when it sits at r (others fixed).
+// Four partners per step with independent accumulators; the partner j = i
+// enters with weight 0.
 __device__ __forceinline__ double jastrow_point(const KArgs &A, const double *pos, int i, const double r[3])
 {
-    const int si = spin_of(A, i);
-    double acc = 0.0;
-    for (int j = 0; j < A.N; ++j) {
-        if (j == i) continue;
+    const bool up = i < A.n_up;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    auto cw = [&](int j) { return j == i ? 0.0 : (((j < A.n_up) == up) ? 0.25 : 0.5); };
+    auto d2 = [&](int j) {
         const double dx = r[0] - pos[3 * j], dy = r[1] - pos[3 * j + 1], dz = r[2] - pos[3 * j + 2];
-        acc += pade_u((spin_of(A, j) == si) ? 0.25 : 0.5, A.b_ee, dx * dx + dy * dy + dz * dz);
+        return dx * dx + dy * dy + dz * dz;
+    };
+    int j = 0;
+    for (; j + 3 < A.N; j += 4) {
+        a0 += pade_u(cw(j), A.b_ee, d2(j));
+        a1 += pade_u(cw(j + 1), A.b_ee, d2(j + 1));
+        a2 += pade_u(cw(j + 2), A.b_ee, d2(j + 2));
+        a3 += pade_u(cw(j + 3), A.b_ee, d2(j + 3));
     }
+    for (; j < A.N; ++j) a0 += pade_u(cw(j), A.b_ee, d2(j));
     for (int I = 0; I < A.n_nuc; ++I) {
         const double *R = A.Rnuc + 3 * I;
         const double dx = r[0] - R[0], dy = r[1] - R[1], dz = r[2] - R[2];
-        acc += pade_u(-A.Znuc[I], A.b_en, dx * dx + dy * dy + dz * dz);
+        a1 += pade_u(-A.Znuc[I], A.b_en, dx * dx + dy * dy + dz * dz);
     }
-    return acc;
+    return (a0 + a1) + (a2 + a3);
 }
 
 // Displaced position of move m.
@@ -445,7 +457,7 @@ __device__ __forceinline__ void det_derivs_all(const KArgs &A, const double *Ain
         const int i = t >> 2, c = t & 3;
         const int s = spin_of(A, i), n = s ? A.n_dn : A.n_up, il = s ? i - A.n_up : i;
         const double *inv = Ainv + s * ns * ns;
-        const double *dp = dphi + (i * 4 + c) * ns;
+        const double *dp = dphi + i * A.L.dld + c * ns;
         double acc = 0.0;
         for (int j = 0; j < n; ++j) acc += dp[j] * inv[j * ns + il];
         gD[4 * i + c] = acc;
@@ -477,17 +489,17 @@ __device__ int walker_setup(const KArgs &A, double *lds, int *sflag, double &EL,
     }
     for (int e0 = 0; e0 < N; e0 += L.EB) {
         const int ne = min(L.EB, N - e0);
-        for (int t = tid; t < ne * A.n_grp; t += NT) {
-            const int e = t / A.n_grp, g = t - e * A.n_grp, i = e0 + e;
+        for (int t = tid; t < ne * K; t += NT) {
+            const int e = t / K, mu = t - e * K, i = e0 + e;
             const double r[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
-            basis_group_full(A, g, r, bvb + e * 5 * K);
+            basis_fn_full(A, mu, r, bvb + e * 5 * Kp);
         }
         __syncthreads();
         orb_contract(A, bvb, ne, ns, Cv, [&](int e, int c, int j, double v) {
             const int i = e0 + e, s = spin_of(A, i), n = s ? A.n_dn : A.n_up, il = s ? i - A.n_up : i;
             if (j >= n) return;
             if (c == 0) G[(s * ns + il) * two + j] = v;
-            else dphi[(i * 4 + c - 1) * ns + j] = v;
+            else dphi[i * L.dld + (c - 1) * ns + j] = v;
         });
         __syncthreads();
     }
@@ -559,32 +571,46 @@ __device__ int walker_setup(const KArgs &A, double *lds, int *sflag, double &EL,
         Y[i * Kp + mu] = acc;
     }
     det_derivs_all(A, Ainv, dphi, lds + L.gD);
-    V = jastrow_setup(A, lds);          // ends with workgroup barriers
+    V = uni(jastrow_setup(A, lds));     // ends with workgroup barriers
     double v[1] = {0.0};
     for (int i = tid; i < N; i += NT) v[0] += psi_lap_term(lds + L.gD + 4 * i, lds + L.gJ + 4 * i);
     block_sum<1>(v, lds + L.red);
-    LAP = v[0];
-    EL = -0.5 * LAP + V;
+    LAP = uni(v[0]);
+    EL = uni(-0.5 * LAP + V);
     return isfinite(EL) ? 0 : kErrNonFinite;
 }
 
-// Random numbers of iterations it .. it+15 (rotation and u1, u2), computed by
-// sixteen lanes at once into rng[16][12].
+// Random numbers of iterations it .. it+7 (rotation, -ln u1 and u2), computed
+// by eight lanes at once into half (it / 8) % 2 of rng[2][8][12].
 __device__ __forceinline__ void refill_rng(const KArgs &A, double *rng, int slot, int it)
 {
-    if (threadIdx.x < 16) {
-        const int q = threadIdx.x;
+    const int q = threadIdx.x;
+    if (q < 8) {
         double Rm[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, u[4];
         if (A.rotate) {
             draw4(A.seed, slot, A.gen, (uint64_t)(it + q), 1, u);
             rotation(u, Rm);
         }
-        double *o = rng + 12 * q;
+        double *o = rng + 12 * (((it >> 3) & 1) * 8 + q);
         for (int c = 0; c < 9; ++c) o[c] = Rm[c];
         draw4(A.seed, slot, A.gen, (uint64_t)(it + q), 0, u);
-        o[9] = u[0];
+        o[9] = -log(u[0]);   // exponential variate of the holding time
         o[10] = u[1];
     }
+}
+
+__device__ __forceinline__ const double *rng_slot(const double *rng, int it)
+{
+    return rng + 12 * (((it >> 3) & 1) * 8 + (it & 7));
+}
+
+// Orders the LDS accesses of one wavefront (its lanes exchange data through
+// LDS between the steps of the accepted-move update).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Heat-bath weights of the moves m in [c0, c1) (S1-S6); returns their sum.
@@ -619,24 +645,27 @@ __device__ __forceinline__ double move_table(const KArgs &A, double *lds, const 
 }
 
 // Sherman-Morrison update after electron k moved from rold to rnew (S8).
-// Updates Ainv, Y, the derivative rows, the determinant and Jastrow
-// derivatives, the Jastrow own sums and the potential; EL and V are
-// returned to every thread.
+// The basis block, the orbital contraction and the rank-1 updates use the
+// whole workgroup; the per-electron Jastrow and determinant derivatives and
+// the local-energy reduction run in the first wavefront, ordered by
+// wave_sync.  Updates Ainv, Y, the derivative rows, the determinant and
+// Jastrow derivatives, the Jastrow own sums and the potential; the new E_L
+// and V go to the block scalars (read after the caller's barrier).
 __device__ void accept_move(const KArgs &A, double *lds, int k, const double rold[3], const double rnew[3],
-                            double &EL, double &V)
+                            double V)
 {
     const Layout &L = A.L;
     const int N = A.N, ns = A.ns, K = A.K, Kp = A.Kp, tid = threadIdx.x, NT = blockDim.x;
-    const int lane = tid & 63, wv = tid >> 6, nw = NT >> 6;
+    const int lane = tid & 63, wv = tid >> 6;
     const int s = spin_of(A, k), n = s ? A.n_dn : A.n_up, kl = s ? k - A.n_up : k, i0 = s ? A.n_up : 0;
     double *pos = lds + L.pos, *bv = lds + L.bv, *vrow = lds + L.vrow, *wrow = lds + L.wrow;
     double *colk = lds + L.colk, *Yk = lds + L.Yk, *Y = lds + L.Y, *dphi = lds + L.dphi;
-    double *gD = lds + L.gD, *gJ = lds + L.gJ, *Jo = lds + L.Jo, *accw = lds + L.acc;
+    double *gD = lds + L.gD, *gJ = lds + L.gJ, *Jo = lds + L.Jo;
     double *inv = lds + L.Ainv + s * ns * ns;
     const MoView Cv = mo_view(A, lds);
 
     // A1: basis block at the new position
-    for (int g = tid; g < A.n_grp; g += NT) basis_group_full(A, g, rnew, bv);
+    for (int mu = tid; mu < K; mu += NT) basis_fn_full(A, mu, rnew, bv);
     __syncthreads();
 
     // A2: new orbital row with derivatives (vrow), w_i = g(r_new) . Y_i, and
@@ -645,19 +674,17 @@ __device__ void accept_move(const KArgs &A, double *lds, int k, const double rol
     {
         int P = 1;
         while (P < 16 && n * P * 2 <= NT) P <<= 1;
-        const int S = (K + P - 1) / P;
         for (int base = 0; base < n * P; base += NT) {
             const int t = base + tid, o = t / P, part = t - o * P;
             double a0 = 0.0, a1 = 0.0;
             if (o < n) {
                 const double *yr = Y + (i0 + o) * Kp;
-                const int mu1 = min(K, (part + 1) * S);
-                int mu = part * S;
-                for (; mu + 1 < mu1; mu += 2) {
+                int mu = part;
+                for (; mu + P < K; mu += 2 * P) {
                     a0 += bv[mu] * yr[mu];
-                    a1 += bv[mu + 1] * yr[mu + 1];
+                    a1 += bv[mu + P] * yr[mu + P];
                 }
-                if (mu < mu1) a0 += bv[mu] * yr[mu];
+                if (mu < K) a0 += bv[mu] * yr[mu];
             }
             double acc = a0 + a1;
             for (int off = P >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -670,7 +697,7 @@ __device__ void accept_move(const KArgs &A, double *lds, int k, const double rol
     }
     __syncthreads();
 
-    const double irho = 1.0 / wrow[kl];
+    const double irho = uni(1.0 / wrow[kl]);
     // A3: rank-1 updates of Ainv and of the spin's rows of Y; new derivative
     // row and position of electron k.
     for (int t = tid; t < n * n + n * K + 4 * n + 3; t += NT) {
@@ -684,60 +711,61 @@ __device__ void accept_move(const KArgs &A, double *lds, int k, const double rol
             Y[(i0 + i) * Kp + mu] -= Yk[mu] * f;
         } else if (t < n * n + n * K + 4 * n) {
             const int u = t - n * n - n * K, c = u / n, j = u - c * n;
-            dphi[(k * 4 + c) * ns + j] = vrow[(c + 1) * ns + j];
+            dphi[k * L.dld + c * ns + j] = vrow[(c + 1) * ns + j];
         } else {
             const int c = t - n * n - n * K - 4 * n;
             pos[3 * k + c] = rnew[c];
         }
     }
-    // A4a: thread i < N updates electron i.  For i != k: the Jastrow pair with
-    // k (new minus old) and, for the moved spin, grad/lap D/D through
-    // Ainv' = Ainv - colk (w - e_k)^T / rho.  For i == k: grad/lap D/D from
-    // the new derivative row and Ainv'[:, k] = colk / rho.
-    double dv = 0.0;
-    if (tid < N) {
-        const int i = tid;
-        if (i != k) {
-            const double c = (spin_of(A, i) == s) ? 0.25 : 0.5;
-            const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
-            const double ax = xi - rnew[0], ay = yi - rnew[1], az = zi - rnew[2];
-            const double bx = xi - rold[0], by = yi - rold[1], bz = zi - rold[2];
-            const PairD pn = pade_d(c, A.b_ee, ax * ax + ay * ay + az * az);
-            const PairD po = pade_d(c, A.b_ee, bx * bx + by * by + bz * bz);
-            gJ[4 * i] += pn.f * ax - po.f * bx;
-            gJ[4 * i + 1] += pn.f * ay - po.f * by;
-            gJ[4 * i + 2] += pn.f * az - po.f * bz;
-            gJ[4 * i + 3] += pn.lap - po.lap;
-            Jo[i] += pn.u - po.u;
-            dv = pn.y - po.y;
-            if (spin_of(A, i) == s) {
-                const int il = i - i0;
-                const double f = wrow[il] * irho;
+    if (wv != 0) return;
+
+    // A4 (first wavefront): items t < N update electron t (pair with k, new
+    // minus old; grad/lap D/D through Ainv' = Ainv - colk (w - e_k)^T / rho,
+    // or for t == k from the new derivative row and Ainv'[:, k] = colk / rho);
+    // items t >= N are the partners of electron k at r_new (Jastrow gradient,
+    // Laplacian, own sum) and the electron-nucleus change of the potential.
+    // None of these reads what A3 writes.
+    double dv = 0.0, o[6] = {0, 0, 0, 0, 0, 0};
+    const int np = N + A.n_nuc;
+    for (int t = lane; t < N + np; t += 64) {
+        if (t < N) {
+            const int i = t;
+            if (i != k) {
+                const double c = (spin_of(A, i) == s) ? 0.25 : 0.5;
+                const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+                const double ax = xi - rnew[0], ay = yi - rnew[1], az = zi - rnew[2];
+                const double bx = xi - rold[0], by = yi - rold[1], bz = zi - rold[2];
+                const PairD pn = pade_d(c, A.b_ee, ax * ax + ay * ay + az * az);
+                const PairD po = pade_d(c, A.b_ee, bx * bx + by * by + bz * bz);
+                gJ[4 * i] += pn.f * ax - po.f * bx;
+                gJ[4 * i + 1] += pn.f * ay - po.f * by;
+                gJ[4 * i + 2] += pn.f * az - po.f * bz;
+                gJ[4 * i + 3] += pn.lap - po.lap;
+                Jo[i] += pn.u - po.u;
+                dv += pn.y - po.y;
+                if (spin_of(A, i) == s) {
+                    const double f = wrow[i - i0] * irho;
+                    for (int c4 = 0; c4 < 4; ++c4) {
+                        const double *dp = dphi + i * L.dld + c4 * ns;
+                        double acc = 0.0;
+                        for (int j = 0; j < n; ++j) acc += dp[j] * colk[j];
+                        gD[4 * i + c4] -= f * acc;
+                    }
+                }
+            } else {
                 for (int c4 = 0; c4 < 4; ++c4) {
-                    const double *dp = dphi + (i * 4 + c4) * ns;
                     double acc = 0.0;
-                    for (int j = 0; j < n; ++j) acc += dp[j] * colk[j];
-                    gD[4 * i + c4] -= f * acc;
+                    for (int j = 0; j < n; ++j) acc += vrow[(c4 + 1) * ns + j] * colk[j];
+                    gD[4 * k + c4] = acc * irho;
                 }
             }
         } else {
-            for (int c4 = 0; c4 < 4; ++c4) {
-                double acc = 0.0;
-                for (int j = 0; j < n; ++j) acc += vrow[(c4 + 1) * ns + j] * colk[j];
-                gD[4 * k + c4] = acc * irho;
-            }
-        }
-    }
-    // A4b: Jastrow gradient, Laplacian and own sum of electron k at r_new,
-    // and the electron-nucleus change of the potential; partners spread over
-    // the wavefronts after the first (or thread k alone for one wavefront).
-    {
-        const int sk = s;
-        auto partner = [&](int p, double o[6]) {
+            const int p = t - N;
+            if (p == k) continue;
             double dx, dy, dz, c, b;
             if (p < N) {
                 dx = rnew[0] - pos[3 * p]; dy = rnew[1] - pos[3 * p + 1]; dz = rnew[2] - pos[3 * p + 2];
-                c = (spin_of(A, p) == sk) ? 0.25 : 0.5;
+                c = (spin_of(A, p) == s) ? 0.25 : 0.5;
                 b = A.b_ee;
             } else {
                 const double *R = A.Rnuc + 3 * (p - N);
@@ -754,53 +782,24 @@ __device__ void accept_move(const KArgs &A, double *lds, int k, const double rol
                 const double ex = rold[0] - R[0], ey = rold[1] - R[1], ez = rold[2] - R[2];
                 o[5] += c * (pr.y - rsqrt_nr(ex * ex + ey * ey + ez * ez));
             }
-        };
-        const int np = N + A.n_nuc;
-        if (nw == 1) {
-            if (tid == k) {
-                double o[6] = {0, 0, 0, 0, 0, 0};
-                for (int p = 0; p < np; ++p)
-                    if (p != k) partner(p, o);
-                for (int q = 0; q < 6; ++q) accw[q] = o[q];
-            }
-        } else if (wv >= 1) {
-            double o[6] = {0, 0, 0, 0, 0, 0};
-            for (int p = tid - 64; p < np; p += NT - 64)
-                if (p != k) partner(p, o);
-            for (int q = 0; q < 6; ++q) o[q] = wave_sum(o[q]);
-            if (lane == 0)
-                for (int q = 0; q < 6; ++q) accw[6 * wv + q] = o[q];
         }
     }
-    __syncthreads();
+    for (int q = 0; q < 6; ++q) o[q] = wave_sum(o[q]);
+    if (lane == 0) {
+        gJ[4 * k] = o[0]; gJ[4 * k + 1] = o[1]; gJ[4 * k + 2] = o[2]; gJ[4 * k + 3] = o[3];
+        Jo[k] = o[4];
+    }
+    wave_sync();
 
-    // A5: electron k's Jastrow values, the Laplacian terms and the potential
-    // change, reduced over the first wavefront.
-    if (wv == 0) {
-        double term = 0.0, dvn = 0.0;
-        if (tid < N) {
-            if (tid == k) {
-                double o[6] = {0, 0, 0, 0, 0, 0};
-                const int w0 = nw == 1 ? 0 : 1;
-                for (int w = w0; w < max(nw, 1); ++w)
-                    for (int q = 0; q < 6; ++q) o[q] += accw[6 * w + q];
-                gJ[4 * k] = o[0]; gJ[4 * k + 1] = o[1]; gJ[4 * k + 2] = o[2]; gJ[4 * k + 3] = o[3];
-                Jo[k] = o[4];
-                dvn = o[5];
-            }
-            term = psi_lap_term(gD + 4 * tid, gJ + 4 * tid);
-        }
-        term = wave_sum(term);
-        const double dvt = wave_sum(dv + dvn);
-        if (tid == 0) {
-            const double Vn = V + dvt;
-            lds[L.sc + SC_V] = Vn;
-            lds[L.sc + SC_EL] = -0.5 * term + Vn;
-        }
+    // A5: Laplacian terms and the potential change over the wavefront
+    // (N <= 64: lane i holds electron i).
+    const double term = wave_sum(lane < N ? psi_lap_term(gD + 4 * lane, gJ + 4 * lane) : 0.0);
+    const double dvt = wave_sum(dv) + o[5];
+    if (lane == 0) {
+        const double Vn = V + dvt;
+        lds[L.sc + SC_V] = Vn;
+        lds[L.sc + SC_EL] = -0.5 * term + Vn;
     }
-    __syncthreads();
-    V = lds[L.sc + SC_V];
-    EL = lds[L.sc + SC_EL];
 }
 
 // One workgroup per walker slot: a generation of continuous-time projection,
@@ -808,11 +807,12 @@ __device__ void accept_move(const KArgs &A, double *lds, int k, const double rol
 __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) project_kernel(KArgs A)
 {
     extern __shared__ double lds[];
-    __shared__ int sflag[8];  // 1: m*, 2-3: pivots, 4: last m with T>0, 5: stop
+    __shared__ int sflag[8];   // 2-3: pivots of the generation start, 5: stop
+    __shared__ int slast[16];  // per wavefront: last move with T > 0
     const Layout &L = A.L;
     const int tid = threadIdx.x, NT = blockDim.x, slot = blockIdx.x, N = A.N, M = A.M;
     const int lane = tid & 63, wv = tid >> 6, nw = NT >> 6;
-    double *pos = lds + L.pos, *T = lds + L.T, *rng = lds + L.rng, *red = lds + L.red;
+    double *pos = lds + L.pos, *T = lds + L.T, *rng = lds + L.rng, *red = lds + L.red, *xs = lds + L.xs;
 
     const int src = A.idx_in ? A.idx_in[slot] : slot;
     for (int t = tid; t < 3 * N; t += NT) pos[t] = A.pos_in[(size_t)src * 3 * N + t];
@@ -826,11 +826,20 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
     __syncthreads();
     if (sflag[5]) return;
 
-    double EL, LAP, V;
-    int rc = walker_setup(A, lds, sflag, EL, LAP, V);
-    if (rc) {
-        if (tid == 0) report(A.err, rc, slot);
-        return;
+    double EL, LAP = 0.0, V;
+    const int blob = A.state_len - 2;  // LDS part of the state blob
+    if (A.state_in && !A.eval) {
+        const double *sb = A.state_in + (size_t)src * A.state_len;
+        for (int t = tid; t < blob; t += NT) lds[L.Y + t] = sb[t];
+        EL = uni(sb[blob]);
+        V = uni(sb[blob + 1]);
+        __syncthreads();
+    } else {
+        int rc = walker_setup(A, lds, sflag, EL, LAP, V);
+        if (rc) {
+            if (tid == 0) report(A.err, rc, slot);
+            return;
+        }
     }
 
     // contiguous chunk of moves per thread
@@ -840,7 +849,7 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
     if (A.eval) {
         double acc[3] = {0.0, 0.0, 0.0};
         int last = -1;
-        const double part = move_table(A, lds, rng, c0, c1, &last,
+        const double part = move_table(A, lds, rng_slot(rng, 0), c0, c1, &last,
                                        A.rho_out ? A.rho_out + (size_t)slot * M : nullptr,
                                        A.k_out ? A.k_out + (size_t)slot * M : nullptr, acc, true);
         double v[4] = {acc[0], acc[1], acc[2], part};
@@ -864,35 +873,28 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
     double tl = A.tau, lw = 0.0;
     int moves = 0;
     for (int it = 0;; ++it) {
-        if (it > 0 && (it & 15) == 0) {
-            refill_rng(A, rng, slot, it);
-            __syncthreads();
-        }
-        const double *R = rng + 12 * (it & 15);
-        if (tid == 0) {
-            sflag[1] = M;
-            sflag[4] = -1;
-        }
+        const double *R = rng_slot(rng, it);
         int last = -1;
         double dummy[3];
         const double part = move_table(A, lds, R, c0, c1, &last, nullptr, nullptr, dummy, false);
 
-        // Delta = sum T and the first m with C_m > u2 Delta (scan over threads)
+        // inclusive prefix of the per-thread sums within each wavefront; the
+        // wavefront totals and last moves with T > 0 go to LDS
         double x = part;
         for (int off = 1; off < 64; off <<= 1) {
             const double y = __shfl_up(x, off, 64);
             if (lane >= off) x += y;
         }
-        double excl = __shfl_up(x, 1, 64);
-        if (lane == 0) excl = 0.0;
+        xs[tid] = x;
+        int lm = last;
+        for (int off = 32; off > 0; off >>= 1) lm = max(lm, __shfl_xor(lm, off, 64));
         if (lane == 63) red[wv] = x;
+        if (lane == 0) slast[wv] = lm;
         __syncthreads();
-        double pre = excl, Delta = 0.0;
-        for (int w = 0; w < nw; ++w) {
-            const double r = red[w];
-            if (w < wv) pre += r;
-            Delta += r;
-        }
+
+        double Delta = 0.0;
+        for (int w = 0; w < nw; ++w) Delta += red[w];
+        Delta = uni(Delta);
         // every thread takes the same decision
         int action = 0;  // 0 stop, 1 move, 2 error
         double thr = 0.0;
@@ -901,7 +903,7 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
         } else if (!isfinite(Delta)) {
             action = 2;
         } else {
-            const double td = -log(R[9]) / Delta;
+            const double td = R[9] / Delta;
             if (td >= tl) {
                 lw -= tl * EL;
             } else {
@@ -918,29 +920,53 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
             }
             break;
         }
-        if (pre <= thr && c1 > c0) {
-            double C = pre;
-            for (int m = c0; m < c1; ++m) {
-                C += T[m];
-                if (C > thr) {
-                    atomicMin(&sflag[1], m);
-                    break;
+        // m* = first m with C_m > thr, found by every wavefront from the LDS
+        // prefix sums: the wavefront, then the lane (ballot), then the move
+        // inside that lane's chunk; the last move with T > 0 if rounding
+        // leaves none.
+        int ms = -1;
+        {
+            double cum = 0.0;
+            int ws = -1;
+            for (int w = 0; w < nw; ++w) {
+                const double r = red[w];
+                if (cum + r > thr) { ws = w; break; }
+                cum += r;
+            }
+            if (ws >= 0) {
+                const double incl = cum + xs[ws * 64 + lane];
+                const unsigned long long hit = __ballot(incl > thr);
+                if (hit) {
+                    const int ls = __ffsll((long long)hit) - 1;
+                    const int ts = ws * 64 + ls;
+                    double C = cum + (ls ? xs[ts - 1] : 0.0);
+                    const int m0 = min(M, ts * chunk), m1 = min(M, m0 + chunk);
+                    for (int m = m0; m < m1; ++m) {
+                        C += T[m];
+                        if (C > thr) { ms = m; break; }
+                    }
                 }
             }
+            if (ms < 0)
+                for (int w = 0; w < nw; ++w) ms = max(ms, slast[w]);
         }
-        if (last >= 0) atomicMax(&sflag[4], last);
-        __syncthreads();
-        int ms = sflag[1];
-        if (ms >= M) ms = sflag[4];
+        ms = uni(ms);
         if (ms < 0) {
             if (tid == 0) report(A.err, kErrNonFinite, slot);
             return;
         }
-        const int k = ms / 12;
-        double rnew[3];
-        move_position(A, pos, R, ms, rnew);
-        const double rold[3] = {pos[3 * k], pos[3 * k + 1], pos[3 * k + 2]};
-        accept_move(A, lds, k, rold, rnew, EL, V);
+        {
+            const int k = ms / 12;
+            double rnew[3];
+            move_position(A, pos, R, ms, rnew);
+            for (int c = 0; c < 3; ++c) rnew[c] = uni(rnew[c]);
+            const double rold[3] = {uni(pos[3 * k]), uni(pos[3 * k + 1]), uni(pos[3 * k + 2])};
+            accept_move(A, lds, k, rold, rnew, V);
+            if (((it + 1) & 7) == 0) refill_rng(A, rng, slot, it + 1);
+        }
+        __syncthreads();
+        EL = uni(lds[L.sc + SC_EL]);
+        V = uni(lds[L.sc + SC_V]);
         ++moves;
         if (!isfinite(EL)) {
             if (tid == 0) report(A.err, kErrNonFinite, slot);
@@ -948,6 +974,14 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
         }
     }
     for (int t = tid; t < 3 * N; t += NT) A.pos_out[(size_t)slot * 3 * N + t] = pos[t];
+    if (A.state_out) {
+        double *sb = A.state_out + (size_t)slot * A.state_len;
+        for (int t = tid; t < blob; t += NT) sb[t] = lds[L.Y + t];
+        if (tid == 0) {
+            sb[blob] = EL;
+            sb[blob + 1] = V;
+        }
+    }
     if (tid == 0) {
         A.logw[slot] = lw;
         A.el[slot] = EL;
@@ -1057,10 +1091,14 @@ struct lrdmc_ctx {
     double b_ee = 0, b_en = 0, v_nn = 0;
     lrdmc_params prm{};
     double *d_Z = nullptr, *d_R = nullptr, *d_mo = nullptr, *d_galpha = nullptr;
-    int *d_heavy = nullptr, *d_gnuc = nullptr, *d_goff = nullptr, *d_chain = nullptr;
+    int *d_heavy = nullptr, *d_gnuc = nullptr, *d_goff = nullptr, *d_chain = nullptr, *d_fn = nullptr;
     int n_chain = 0;
     double *d_pos[2] = {nullptr, nullptr};
     int cur = 0;
+    // walker state blobs (double-buffered, follow d_pos through reconfiguration)
+    double *d_state[2] = {nullptr, nullptr};
+    int state_len = 0;
+    bool state_ok = false;  // d_state[cur] holds the state of d_pos[cur]
     double *d_logw = nullptr, *d_el = nullptr, *d_cw = nullptr;
     int *d_nmov = nullptr, *d_idx = nullptr, *d_err = nullptr;
     bool loaded = false, projected = false, pending = false;
@@ -1106,7 +1144,8 @@ Layout make_layout(int N, int ns, int K, int Kp, int M, bool c_lds, size_t targe
     L.pos = take(3 * N);
     L.Y = take(N * Kp);
     L.Ainv = take(2 * ns * ns);
-    L.dphi = take(N * 4 * ns);
+    L.dld = 4 * ns + 1;
+    L.dphi = take(N * L.dld);
     L.gD = take(4 * N);
     L.gJ = take(4 * N);
     L.Jo = take(N);
@@ -1114,12 +1153,13 @@ Layout make_layout(int N, int ns, int K, int Kp, int M, bool c_lds, size_t targe
     L.red = take(64);
     L.sc = take(32);
     L.rng = take(16 * 12);
+    L.xs = take(kMaxThreads);
     L.acc = take(32);
     const int U = o;
     // move-loop view
     int q = U;
     L.T = q; q += M;
-    L.bv = q; q += 5 * K;
+    L.bv = q; q += 5 * Kp;
     L.vrow = q; q += 5 * ns;
     L.wrow = q; q += ns;
     L.colk = q; q += ns;
@@ -1133,11 +1173,12 @@ Layout make_layout(int N, int ns, int K, int Kp, int M, bool c_lds, size_t targe
     L.bvb = q;
     const int fixed_end = q;
     int EB = 1;
-    while (EB < N && (size_t)(fixed_end + (EB + 1) * 5 * K) * sizeof(double) <= target &&
-           fixed_end + (EB + 1) * 5 * K <= loop_end + 5 * K)
+    const int base_total = std::max(loop_end, fixed_end + 5 * Kp);
+    while (EB < N && (size_t)std::max(loop_end, fixed_end + (EB + 1) * 5 * Kp) * sizeof(double) <=
+                         std::max(target, (size_t)base_total * sizeof(double)))
         ++EB;
     L.EB = EB;
-    L.total = std::max(loop_end, fixed_end + EB * 5 * K);
+    L.total = std::max(loop_end, fixed_end + EB * 5 * Kp);
     return L;
 }
 
@@ -1148,7 +1189,7 @@ KArgs base_args(const lrdmc_ctx *c)
     A.n_orb = c->n_orb; A.n_nuc = c->n_nuc; A.n_grp = c->n_grp; A.n_heavy = c->n_heavy; A.M = c->M;
     A.Znuc = c->d_Z; A.Rnuc = c->d_R; A.heavy = c->d_heavy; A.grp_nuc = c->d_gnuc;
     A.grp_alpha = c->d_galpha; A.grp_off = c->d_goff; A.mo = c->d_mo;
-    A.n_chain = c->n_chain; A.chain = c->d_chain;
+    A.n_chain = c->n_chain; A.chain = c->d_chain; A.fn_info = c->d_fn;
     A.b_ee = c->b_ee; A.b_en = c->b_en; A.v_nn = c->v_nn; A.c_lds = c->L.C >= 0;
     A.a = c->prm.a; A.ap = c->prm.a_prime;
     A.inv_a2 = 1.0 / (c->prm.a * c->prm.a);
@@ -1229,6 +1270,14 @@ int launch_project(lrdmc_ctx *c, hipStream_t st, const double *pos_in, const int
     A.pos_in = pos_in;
     A.idx_in = idx_in;
     A.pos_out = pos_out;
+    A.state_len = c->state_len;
+    if (!eval) {
+        // resume from the stored state except on refresh generations
+        const int R = std::max(1, (int)c->prm.refresh);
+        const bool resume = c->state_ok && R > 1 && (c->gen % (uint64_t)R) != 0;
+        A.state_in = resume ? c->d_state[c->cur] : nullptr;
+        A.state_out = R > 1 ? c->d_state[c->cur ^ 1] : nullptr;
+    }
     A.logw = c->d_logw;
     A.el = c->d_el;
     A.nmov = c->d_nmov;
@@ -1347,7 +1396,7 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
         !sys->shell_l || !sys->shell_alpha || !sys->mo)
         return fail(nullptr, LRDMC_EINVAL, "lrdmc_create: invalid system sizes or pointers");
     if (!(prm->a > 0.0) || !(prm->a_prime >= prm->a) || !(prm->r_c > 0.0) || !(prm->tau > 0.0) ||
-        !std::isfinite(prm->a_prime) || !std::isfinite(prm->tau) || prm->reserved != 0)
+        !std::isfinite(prm->a_prime) || !std::isfinite(prm->tau) || prm->refresh < 0)
         return fail(nullptr, LRDMC_EINVAL, "lrdmc_create: invalid lattice parameters (need a > 0, a' >= a, r_c > 0, tau > 0)");
     int K = 0;
     for (int q = 0; q < sys->n_shell; ++q) {
@@ -1423,6 +1472,15 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
         }
     }
 
+    // Per basis function: its group (after sorting), l and component.
+    std::vector<int> fn_info(K);
+    for (size_t g = 0; g < gnuc.size(); ++g)
+        for (int l = 0; l < 3; ++l) {
+            const int o = goff[3 * g + l];
+            if (o < 0) continue;
+            for (int cmp = 0; cmp < 2 * l + 1; ++cmp) fn_info[o + cmp] = (int)g | (l << 16) | (cmp << 20);
+        }
+
     lrdmc_ctx *c = new (std::nothrow) lrdmc_ctx();
     if (!c) return fail(nullptr, LRDMC_ENOMEM, "lrdmc_create: host allocation");
     c->W = n_walkers; c->N = N; c->n_up = sys->n_up; c->n_dn = sys->n_dn; c->ns = ns; c->K = K;
@@ -1439,9 +1497,11 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
     c->nt = std::min(kMaxThreads, std::max(64, ((c->M + 63) / 64) * 64));
     // Stage the occupied MO block in LDS only for small walker states; larger
     // ones read it through the caches so that more walkers share a CU.
-    c->L = make_layout(N, ns, K, c->Kp, c->M, true, 32 * 1024);
-    if (sizeof(double) * (size_t)c->L.total > 16 * 1024) c->L = make_layout(N, ns, K, c->Kp, c->M, false, 32 * 1024);
+    c->L = make_layout(N, ns, K, c->Kp, c->M, true, 16 * 1024);
+    if (sizeof(double) * (size_t)c->L.total > 16 * 1024)
+        c->L = make_layout(N, ns, K, c->Kp, c->M, false, prm->refresh > 1 ? 0 : 38 * 1024);
     c->lds_bytes = sizeof(double) * (size_t)c->L.total;
+    c->state_len = (c->L.Jo + N - c->L.Y) + 2;
 
     auto cleanup = [&](int code, const std::string &m) {
         lrdmc_destroy(c);
@@ -1467,9 +1527,12 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
               alloc((void **)&c->d_gnuc, sizeof(int) * gnuc.size()) &&
               alloc((void **)&c->d_goff, sizeof(int) * goff.size()) &&
               alloc((void **)&c->d_chain, sizeof(int) * chains.size()) &&
+              alloc((void **)&c->d_fn, sizeof(int) * K) &&
               alloc((void **)&c->d_heavy, sizeof(int) * heavy.size()) &&
               alloc((void **)&c->d_pos[0], sizeof(double) * W * s3) &&
               alloc((void **)&c->d_pos[1], sizeof(double) * W * s3) &&
+              (prm->refresh <= 1 || (alloc((void **)&c->d_state[0], sizeof(double) * W * c->state_len) &&
+                                     alloc((void **)&c->d_state[1], sizeof(double) * W * c->state_len))) &&
               alloc((void **)&c->d_logw, sizeof(double) * W) && alloc((void **)&c->d_el, sizeof(double) * W) &&
               alloc((void **)&c->d_cw, sizeof(double) * W) && alloc((void **)&c->d_nmov, sizeof(int) * W) &&
               alloc((void **)&c->d_idx, sizeof(int) * W) && alloc((void **)&c->d_err, sizeof(int) * 2);
@@ -1481,6 +1544,7 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
          hipMemcpy(c->d_gnuc, gnuc.data(), sizeof(int) * gnuc.size(), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(c->d_goff, goff.data(), sizeof(int) * goff.size(), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(c->d_chain, chains.data(), sizeof(int) * chains.size(), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(c->d_fn, fn_info.data(), sizeof(int) * K, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(c->d_heavy, heavy.data(), sizeof(int) * heavy.size(), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemset(c->d_err, 0, 2 * sizeof(int)) == hipSuccess &&
          hipMemset(c->d_logw, 0, sizeof(double) * W) == hipSuccess &&
@@ -1502,6 +1566,7 @@ int lrdmc_set_walkers(lrdmc_ctx *c, const double *pos, uint64_t generation, void
     c->loaded = true;
     c->projected = false;
     c->pending = false;
+    c->state_ok = false;
     return LRDMC_OK;
 }
 
@@ -1513,6 +1578,7 @@ int lrdmc_project(lrdmc_ctx *c, void *stream)
                             nullptr, nullptr, nullptr);
     if (rc) return rc;
     c->cur ^= 1;
+    c->state_ok = c->prm.refresh > 1;
     c->pending = false;
     c->projected = true;
     return check_kernel_error(c, st);
@@ -1540,6 +1606,7 @@ int lrdmc_run(lrdmc_ctx *c, int32_t n_gen, void *stream, double *log_wbar, doubl
                                 0, nullptr, nullptr, nullptr);
         if (rc) return rc;
         c->cur ^= 1;
+        c->state_ok = c->prm.refresh > 1;
         rc = launch_branch(c, st, log_wbar ? log_wbar + g : nullptr, ebar ? ebar + g : nullptr,
                            n_moves ? n_moves + g : nullptr, idx ? idx + (size_t)g * c->W : nullptr);
         if (rc) return rc;
@@ -1633,7 +1700,7 @@ const char *lrdmc_last_error(const lrdmc_ctx *c) { return c ? c->err.c_str() : g
 void lrdmc_destroy(lrdmc_ctx *c)
 {
     if (!c) return;
-    void *ptrs[] = {c->d_Z,    c->d_R,    c->d_mo,   c->d_galpha, c->d_gnuc, c->d_goff, c->d_chain, c->d_heavy, c->d_pos[0],
+    void *ptrs[] = {c->d_Z,    c->d_R,    c->d_mo,   c->d_galpha, c->d_gnuc, c->d_goff, c->d_chain, c->d_fn, c->d_heavy, c->d_pos[0], c->d_state[0], c->d_state[1],
                     c->d_pos[1], c->d_logw, c->d_el, c->d_cw,     c->d_nmov, c->d_idx,  c->d_err};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);

@@ -252,6 +252,7 @@ class Config:
     tau: float                 # projection time per generation (1/Ha)
     rotate: int = 1
     seed: int = 0
+    refresh: int = 8           # generations between full walker-state recomputations
     extra: Dict = field(default_factory=dict)
 
 

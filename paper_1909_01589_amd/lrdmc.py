@@ -47,7 +47,7 @@ class lrdmc_params(C.Structure):
     _fields_ = [
         ("a", C.c_double), ("a_prime", C.c_double), ("r_c", C.c_double),
         ("z_heavy", C.c_double), ("tau", C.c_double),
-        ("seed", C.c_uint64), ("rotate", C.c_int32), ("reserved", C.c_int32),
+        ("seed", C.c_uint64), ("rotate", C.c_int32), ("refresh", C.c_int32),
     ]
 
 
@@ -138,10 +138,10 @@ def _pack_system(system):
 
 
 def lrdmc_create(system, a: float, a_prime: float, r_c: float, tau: float, n_walkers: int,
-                 z_heavy: Optional[float] = None, seed: int = 0, rotate: int = 1) -> int:
+                 z_heavy: Optional[float] = None, seed: int = 0, rotate: int = 1, refresh: int = 1) -> int:
     s, keep = _pack_system(system)
     zh = float(np.max(system.Z)) if z_heavy is None else float(z_heavy)
-    p = lrdmc_params(a, a_prime, r_c, zh, tau, seed, rotate, 0)
+    p = lrdmc_params(a, a_prime, r_c, zh, tau, seed, rotate, refresh)
     ctx = C.c_void_p()
     _check(load().lrdmc_create(C.byref(s), C.byref(p), int(n_walkers), C.byref(ctx)))
     del keep
@@ -216,7 +216,7 @@ class LRDMC:
     """A context bound to one system and walker count, with torch buffers."""
 
     def __init__(self, system, a: float, a_prime: float, r_c: float, tau: float, n_walkers: int,
-                 z_heavy: Optional[float] = None, seed: int = 0, rotate: int = 1,
+                 z_heavy: Optional[float] = None, seed: int = 0, rotate: int = 1, refresh: int = 1,
                  device: str = "cuda:0"):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the LRDMC projection runs only on the HIP device")
@@ -228,7 +228,7 @@ class LRDMC:
         self.W = int(n_walkers)
         self.N = system.n_elec
         self.M = 12 * self.N
-        self.ctx = lrdmc_create(system, a, a_prime, r_c, tau, n_walkers, z_heavy, seed, rotate)
+        self.ctx = lrdmc_create(system, a, a_prime, r_c, tau, n_walkers, z_heavy, seed, rotate, refresh)
 
     def close(self):
         if self.ctx:

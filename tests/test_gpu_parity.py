@@ -50,10 +50,10 @@ def _case(name):
     raise KeyError(name)
 
 
-def _pair(name, W, seed=3, rotate=1, tau=None):
+def _pair(name, W, seed=3, rotate=1, tau=None, refresh=1):
     s, a, ap, rc, t = _case(name)
     t = tau if tau is not None else t
-    gpu = _lrdmc()(s, a, ap, rc, t, W, seed=seed, rotate=rotate)
+    gpu = _lrdmc()(s, a, ap, rc, t, W, seed=seed, rotate=rotate, refresh=refresh)
     orc = oracle.Oracle(s, a, ap, rc, tau=t, seed=seed, rotate=rotate)
     return s, gpu, orc
 
@@ -116,9 +116,13 @@ def test_reconfigure_matches_oracle_bit_exact():
             assert st[1] == pytest.approx(eb_o, rel=1e-13, abs=1e-13)
 
 
-@pytest.mark.parametrize("name,W,n_gen", [("be", 64, 8), ("tiny", 32, 6), ("hydrogenic", 16, 5)])
-def test_run_matches_oracle(name, W, n_gen):
-    s, gpu, orc = _pair(name, W, seed=9)
+@pytest.mark.parametrize("name,W,n_gen,refresh", [("be", 64, 8, 1), ("tiny", 32, 6, 1), ("hydrogenic", 16, 5, 1),
+                                                   ("be", 64, 8, 3), ("tiny", 32, 6, 4), ("ar", 16, 5, 2)])
+def test_run_matches_oracle(name, W, n_gen, refresh):
+    """Whole projections: move counts and reconfiguration indices bit-exact,
+    generation energies within the FP64 bound.  refresh > 1 carries the
+    Sherman-Morrison-updated walker state across generations."""
+    s, gpu, orc = _pair(name, W, seed=9, refresh=refresh)
     pos = inputs.initial_walkers(s, W, 2)
     if name == "hydrogenic":
         pos = pos * 0.5
