@@ -807,7 +807,7 @@ __device__ void accept_move(const KArgs &A, double *lds, int k, const double rol
 __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) project_kernel(KArgs A)
 {
     extern __shared__ double lds[];
-    __shared__ int sflag[8];   // 2-3: pivots of the generation start, 5: stop
+    __shared__ int sflag[8];   // 2-3: pivots of the generation start, 5: stop, 6: bad input
     __shared__ int slast[16];  // per wavefront: last move with T > 0
     const Layout &L = A.L;
     const int tid = threadIdx.x, NT = blockDim.x, slot = blockIdx.x, N = A.N, M = A.M;
@@ -815,16 +815,28 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
     double *pos = lds + L.pos, *T = lds + L.T, *rng = lds + L.rng, *red = lds + L.red, *xs = lds + L.xs;
 
     const int src = A.idx_in ? A.idx_in[slot] : slot;
-    for (int t = tid; t < 3 * N; t += NT) pos[t] = A.pos_in[(size_t)src * 3 * N + t];
+    if (tid == 0) {
+        sflag[5] = (A.err[0] != 0);
+        sflag[6] = 0;
+    }
+    __syncthreads();
+    for (int t = tid; t < 3 * N; t += NT) {
+        const double v = A.pos_in[(size_t)src * 3 * N + t];
+        pos[t] = v;
+        if (!isfinite(v)) sflag[6] = 1;
+    }
     if (A.c_lds)
         for (int t = tid; t < A.K * A.ns; t += NT) {
             const int mu = t / A.ns, j = t - mu * A.ns;
             lds[L.C + t] = A.mo[mu * A.n_orb + j];
         }
-    if (tid == 0) sflag[5] = (A.err[0] != 0);
     refill_rng(A, rng, slot, 0);
     __syncthreads();
     if (sflag[5]) return;
+    if (sflag[6]) {
+        if (tid == 0) report(A.err, kErrNonFinite, slot);
+        return;
+    }
 
     double EL, LAP = 0.0, V;
     const int blob = A.state_len - 2;  // LDS part of the state blob

@@ -1,0 +1,175 @@
+"""GPU edge cases through the C ABI: error paths, degenerate sizes,
+determinism, resume from saved walkers, the single-grid limit and the
+timing hooks.  Every case runs the fixed kernels to a normal exit; invalid
+inputs are rejected by the host or by the kernels' own checks."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from oracle import spacing  # noqa: E402
+from paper_1909_01589_amd import inputs  # noqa: E402
+
+
+def _LRDMC():
+    from paper_1909_01589_amd.lrdmc import LRDMC
+    return LRDMC
+
+
+def _be(W, **kw):
+    s = inputs.be_like(0)
+    rc, ap, _ = spacing.spacing(4, 0.2)
+    return s, _LRDMC()(s, 0.2, ap, rc, 0.0217, W, **kw), (0.2, ap, rc)
+
+
+def test_single_walker_matches_oracle():
+    s, gpu, (a, ap, rc) = _be(1, seed=4)
+    pos = inputs.initial_walkers(s, 1, 3)
+    gpu.set_walkers(pos, 2)
+    out = gpu.run(4, want_idx=True)
+    ref = oracle.Oracle(s, a, ap, rc, tau=0.0217, seed=4).run(pos, 4, gen0=2)
+    assert np.array_equal(out["n_moves"].cpu().numpy(), ref["n_moves"])
+    assert np.all(out["idx"].cpu().numpy() == 0)
+    assert np.allclose(out["ebar"].cpu().numpy(), ref["ebar"], rtol=1e-12, atol=1e-10)
+    gpu.close()
+
+
+def test_singular_slater_matrix_is_reported():
+    """Two identical MO columns make every Slater matrix singular."""
+    from paper_1909_01589_amd.lrdmc import LRDMCError
+    s = inputs.be_like(0)
+    mo = s.mo.copy()
+    mo[:, 1] = mo[:, 0]
+    bad = inputs.System(Z=s.Z, R=s.R, n_up=2, n_dn=2, shell_nuc=s.shell_nuc, shell_l=s.shell_l,
+                        shell_alpha=s.shell_alpha, mo=mo)
+    gpu = _LRDMC()(bad, 0.2, 0.28, 0.44, 0.02, 8)
+    gpu.set_walkers(inputs.initial_walkers(bad, 8, 0), 0)
+    with pytest.raises(LRDMCError) as e:
+        gpu.project()
+    assert e.value.code == -2 and "slot" in str(e.value)
+    with pytest.raises(LRDMCError) as e:
+        gpu.eval_moves(inputs.initial_walkers(bad, 8, 1))
+    assert e.value.code == -2
+    gpu.close()
+
+
+def test_non_finite_position_is_reported_and_context_recovers():
+    from paper_1909_01589_amd.lrdmc import LRDMCError
+    s, gpu, _ = _be(8)
+    pos = inputs.initial_walkers(s, 8, 0)
+    pos[5, 1, 2] = np.nan
+    gpu.set_walkers(pos, 0)
+    with pytest.raises(LRDMCError) as e:
+        gpu.project()
+    assert e.value.code == -3 and "slot 5" in str(e.value)
+    # the context stays usable with valid walkers
+    gpu.set_walkers(inputs.initial_walkers(s, 8, 0), 0)
+    gpu.project()
+    out = gpu.branch()
+    assert np.isfinite(out["ebar"])
+    gpu.close()
+
+
+def test_call_order_errors():
+    from paper_1909_01589_amd.lrdmc import LRDMCError
+    s, gpu, _ = _be(4)
+    with pytest.raises(LRDMCError) as e:
+        gpu.project()                   # no walkers loaded
+    assert e.value.code == -1
+    gpu.set_walkers(inputs.initial_walkers(s, 4, 0), 0)
+    with pytest.raises(LRDMCError) as e:
+        gpu.branch()                    # nothing projected yet
+    assert e.value.code == -1
+    gpu.close()
+
+
+def test_state_too_large_for_lds_is_refused():
+    """64 electrons with 512 basis functions cannot keep a walker in LDS."""
+    from paper_1909_01589_amd.lrdmc import LRDMCError
+    counts = (112, 100, 20)   # 112 + 300 + 100 = 512 functions
+    s = inputs.atom(64, counts, 0.05, 2.0, seed=0)
+    with pytest.raises(LRDMCError) as e:
+        _LRDMC()(s, 0.01, 0.02, 0.05, 1e-4, 2)
+    assert e.value.code == -1
+
+
+def test_runs_are_deterministic():
+    s, g1, _ = _be(64, seed=7, refresh=4)
+    _, g2, _ = _be(64, seed=7, refresh=4)
+    pos = inputs.initial_walkers(s, 64, 5)
+    outs = []
+    for g in (g1, g2):
+        g.set_walkers(pos, 10)
+        o = g.run(6, want_idx=True)
+        outs.append({k: v.cpu().numpy() for k, v in o.items()})
+        outs[-1]["pos"] = g.get_walkers()["pos"].cpu().numpy()
+        g.close()
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
+def test_resume_from_saved_walkers_is_bit_identical():
+    """Checkpoint/resume: positions plus generation counter reproduce an
+    uninterrupted run exactly (state recomputed every generation)."""
+    s, g, _ = _be(32, seed=2, refresh=1)
+    pos = inputs.initial_walkers(s, 32, 1)
+    g.set_walkers(pos, 0)
+    full = {k: v.cpu().numpy() for k, v in g.run(6, want_idx=True).items()}
+    g.set_walkers(pos, 0)
+    first = {k: v.cpu().numpy() for k, v in g.run(3, want_idx=True).items()}
+    saved = g.get_walkers()["pos"].clone()
+    assert g.generation == 3
+    g.set_walkers(saved, 3)
+    second = {k: v.cpu().numpy() for k, v in g.run(3, want_idx=True).items()}
+    for k in ("ebar", "log_wbar", "n_moves", "idx"):
+        assert np.array_equal(np.concatenate([first[k], second[k]]), full[k]), k
+    g.close()
+
+
+def test_equal_spacings_reduce_to_single_grid():
+    """a' = a: the table equals the single grid (p = 1 everywhere) move for
+    move up to the split of each coefficient between the two grids."""
+    s = inputs.ar_like(0)
+    W = 4
+    pos = inputs.initial_walkers(s, W, 9)
+    dbl = _LRDMC()(s, 0.1, 0.1, 0.2, 0.01, W, rotate=0)
+    sgl = _LRDMC()(s, 0.1, 0.1, 1e150, 0.01, W, rotate=0)
+    r1, k1, d1 = (x.cpu().numpy() for x in dbl.eval_moves(pos))
+    r2, k2, d2 = (x.cpu().numpy() for x in sgl.eval_moves(pos))
+    k1 = k1.reshape(W, -1, 2, 6).sum(axis=2)
+    k2 = k2.reshape(W, -1, 2, 6).sum(axis=2)
+    assert np.allclose(k1, k2, rtol=1e-13)
+    assert np.allclose(d1[:, 2], d2[:, 2], rtol=1e-11)     # L^a
+    assert np.allclose(r1, r2, rtol=0, atol=0)
+    dbl.close()
+    sgl.close()
+
+
+def test_timing_hooks_count_launches():
+    from paper_1909_01589_amd.lrdmc import lrdmc_set_timing, lrdmc_timing
+    s, g, _ = _be(64)
+    g.set_walkers(inputs.initial_walkers(s, 64, 0), 0)
+    lrdmc_set_timing(g.ctx, True)
+    g.run(5)
+    ms, n, bms, bn = lrdmc_timing(g.ctx)
+    assert n == 5 and bn == 5 and ms > 0 and bms > 0
+    lrdmc_set_timing(g.ctx, False)
+    g.close()
+
+
+def test_get_walkers_after_branch_returns_selected_copies():
+    s, g, _ = _be(32, seed=5)
+    g.set_walkers(inputs.initial_walkers(s, 32, 0), 0)
+    g.project()
+    before = {k: v.cpu().numpy() for k, v in g.get_walkers().items()}
+    rec = g.branch()
+    idx = rec["idx"].cpu().numpy()
+    after = {k: v.cpu().numpy() for k, v in g.get_walkers().items()}
+    assert np.array_equal(after["pos"], before["pos"][idx])
+    assert np.array_equal(after["e_l"], before["e_l"][idx])
+    assert np.all(after["log_w"] == 0) and np.all(after["n_moves"] == 0)
+    assert rec["n_moves"] == before["n_moves"].sum()
+    g.close()

@@ -1,0 +1,71 @@
+"""GPU parity at the benchmark's full size and launch configuration:
+Ar-like atom, a = 0.1 bohr, 4096 walkers, 256-thread workgroups, refresh 8,
+random lattice rotations.  The whole population runs on the GPU; sampled
+walker slots are recomputed one by one by the oracle from the same start
+positions and random-number keys, and the reconfiguration of the GPU's own
+weights is recomputed in full.  Also the Z = 54 Z-sweep atom (largest LDS
+footprint) and the molecule (several heavy nuclei) on sampled slots."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from oracle import spacing  # noqa: E402
+from paper_1909_01589_amd import inputs  # noqa: E402
+
+
+def _check_generation(gpu, orc, start, gen, slots):
+    gpu.project()
+    out = {k: v.cpu().numpy() for k, v in gpu.get_walkers().items()}
+    for w in slots:
+        print(f"fullsize slot={w} gen={gen}", flush=True)
+        p_o, lw_o, el_o, nm_o = orc.generation(start[w], w, gen)
+        assert out["n_moves"][w] == nm_o
+        assert np.allclose(out["pos"][w], p_o, rtol=0, atol=1e-11)
+        assert abs(out["e_l"][w] - el_o) <= 1e-9 * (1 + abs(el_o))
+        assert abs(out["log_w"][w] - lw_o) <= 1e-9 * (1 + abs(lw_o))
+    return out
+
+
+@pytest.mark.parametrize("name", ["ar_a0.1"])
+def test_full_population_sampled_parity(name):
+    from paper_1909_01589_amd.lrdmc import LRDMC
+    cfg = inputs.get_config(name)
+    s = cfg.system
+    rc, ap, _ = spacing.spacing(s.z_max, cfg.a)
+    W = cfg.walkers
+    gpu = LRDMC(s, cfg.a, ap, rc, cfg.tau, W, seed=cfg.seed, rotate=cfg.rotate, refresh=cfg.refresh)
+    orc = oracle.Oracle(s, cfg.a, ap, rc, tau=cfg.tau, seed=cfg.seed, rotate=cfg.rotate)
+    assert gpu.M == 216
+    pos = inputs.initial_walkers(s, W, cfg.seed)
+    gpu.set_walkers(pos, 0)
+    slots = [0, 1, 777, 2048, 4001, W - 1]
+    # generation 0 (fresh state), its reconfiguration, then generation 1
+    # (state resumed from the Sherman-Morrison-updated blobs)
+    out0 = _check_generation(gpu, orc, pos, 0, slots)
+    rec = gpu.branch()
+    idx_o, lwb_o, eb_o = orc.reconfigure(out0["log_w"], out0["e_l"], orc.xi(0))
+    assert np.array_equal(rec["idx"].cpu().numpy(), idx_o)
+    assert abs(rec["ebar"] - eb_o) <= 1e-10 + 1e-12 * abs(eb_o)
+    assert rec["n_moves"] == out0["n_moves"].sum()
+    start1 = gpu.get_walkers()["pos"].cpu().numpy()
+    assert np.array_equal(start1, out0["pos"][idx_o])
+    _check_generation(gpu, orc, start1, 1, slots)
+    gpu.close()
+
+
+@pytest.mark.parametrize("name,W", [("zsweep54", 64), ("molecule", 32)])
+def test_large_systems_sampled_parity(name, W):
+    from paper_1909_01589_amd.lrdmc import LRDMC
+    cfg = inputs.get_config(name)
+    s = cfg.system
+    rc, ap, _ = spacing.spacing(s.z_max, cfg.a)
+    gpu = LRDMC(s, cfg.a, ap, rc, cfg.tau, W, seed=cfg.seed, rotate=1, refresh=cfg.refresh)
+    orc = oracle.Oracle(s, cfg.a, ap, rc, tau=cfg.tau, seed=cfg.seed, rotate=1)
+    pos = inputs.initial_walkers(s, W, 1)
+    gpu.set_walkers(pos, 0)
+    _check_generation(gpu, orc, pos, 0, [0, W // 2, W - 1])
+    gpu.close()
