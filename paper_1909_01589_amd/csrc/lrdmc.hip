@@ -214,6 +214,67 @@ __device__ __forceinline__ double basis_dot(const KArgs &A, const double r[3], c
     return acc;
 }
 
+// basis_dot for the two points of a +/- move pair (same electron, so the
+// same row y): the chains of both points run side by side and share the loads.
+__device__ __forceinline__ void basis_dot2(const KArgs &A, const double ra[3], const double rb[3],
+                                           const double *y, double &out_a, double &out_b)
+{
+    double acc_a = 0.0, acc_b = 0.0;
+    for (int ch = 0; ch < A.n_chain; ++ch) {
+        const int g0 = A.chain[3 * ch], len = A.chain[3 * ch + 1], code = A.chain[3 * ch + 2];
+        const double *Rn = A.Rnuc + 3 * A.grp_nuc[g0];
+        const double ax = ra[0] - Rn[0], ay = ra[1] - Rn[1], az = ra[2] - Rn[2];
+        const double bx = rb[0] - Rn[0], by = rb[1] - Rn[1], bz = rb[2] - Rn[2];
+        const double a2 = ax * ax + ay * ay + az * az, b2 = bx * bx + by * by + bz * bz;
+        const double al0 = A.grp_alpha[g0];
+        double ea = exp(-al0 * a2), eb = exp(-al0 * b2);
+        for (int q = 0; q < len; ++q) {
+            const int g = g0 + q;
+            const int *off = A.grp_off + 3 * g;
+            double pa = 0.0, pb = 0.0;
+            if (off[0] >= 0) {
+                const double ys = y[off[0]];
+                pa += ys;
+                pb += ys;
+            }
+            if (off[1] >= 0) {
+                const double *yp = y + off[1];
+                const double y0 = yp[0], y1 = yp[1], y2 = yp[2];
+                pa += ax * y0 + ay * y1 + az * y2;
+                pb += bx * y0 + by * y1 + bz * y2;
+            }
+            if (off[2] >= 0) {
+                const double *yd = y + off[2];
+                const double y0 = yd[0], y1 = yd[1], y2 = yd[2], y3 = yd[3], y4 = yd[4];
+                pa += ax * ay * y0 + ay * az * y1 + az * ax * y2 + (ax * ax - ay * ay) * y3 +
+                      (2.0 * az * az - ax * ax - ay * ay) * y4;
+                pb += bx * by * y0 + by * bz * y1 + bz * bx * y2 + (bx * bx - by * by) * y3 +
+                      (2.0 * bz * bz - bx * bx - by * by) * y4;
+            }
+            acc_a += ea * pa;
+            acc_b += eb * pb;
+            if (q + 1 < len) {
+                if (code == 3) {
+                    ea = ea * ea * ea;
+                    eb = eb * eb * eb;
+                } else if (code == 2) {
+                    ea = (ea * ea) * sqrt_unit(ea);
+                    eb = (eb * eb) * sqrt_unit(eb);
+                } else if (code == 1) {
+                    ea = ea * ea;
+                    eb = eb * eb;
+                } else {
+                    const double al = A.grp_alpha[g + 1];
+                    ea = exp(-al * a2);
+                    eb = exp(-al * b2);
+                }
+            }
+        }
+    }
+    out_a = acc_a;
+    out_b = acc_b;
+}
+
 // Switch p at x: Gaussian of the distance to the nearest heavy nucleus.
 __device__ __forceinline__ double p_switch(const KArgs &A, const double x[3])
 {
@@ -383,6 +444,47 @@ __device__ __forceinline__ double jastrow_point(const KArgs &A, const double *po
         a1 += pade_u(-A.Znuc[I], A.b_en, dx * dx + dy * dy + dz * dz);
     }
     return (a0 + a1) + (a2 + a3);
+}
+
+// jastrow_point for the two points of a +/- move pair of electron i.
+__device__ __forceinline__ void jastrow_point2(const KArgs &A, const double *pos, int i, const double ra[3],
+                                               const double rb[3], double &out_a, double &out_b)
+{
+    const bool up = i < A.n_up;
+    double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
+    int j = 0;
+    for (; j + 1 < A.N; j += 2) {
+        const double c0 = j == i ? 0.0 : (((j < A.n_up) == up) ? 0.25 : 0.5);
+        const double c1 = j + 1 == i ? 0.0 : (((j + 1 < A.n_up) == up) ? 0.25 : 0.5);
+        const double x0 = pos[3 * j], y0 = pos[3 * j + 1], z0 = pos[3 * j + 2];
+        const double x1 = pos[3 * j + 3], y1 = pos[3 * j + 4], z1 = pos[3 * j + 5];
+        double dx = ra[0] - x0, dy = ra[1] - y0, dz = ra[2] - z0;
+        a0 += pade_u(c0, A.b_ee, dx * dx + dy * dy + dz * dz);
+        dx = rb[0] - x0; dy = rb[1] - y0; dz = rb[2] - z0;
+        b0 += pade_u(c0, A.b_ee, dx * dx + dy * dy + dz * dz);
+        dx = ra[0] - x1; dy = ra[1] - y1; dz = ra[2] - z1;
+        a1 += pade_u(c1, A.b_ee, dx * dx + dy * dy + dz * dz);
+        dx = rb[0] - x1; dy = rb[1] - y1; dz = rb[2] - z1;
+        b1 += pade_u(c1, A.b_ee, dx * dx + dy * dy + dz * dz);
+    }
+    if (j < A.N) {
+        const double c0 = j == i ? 0.0 : (((j < A.n_up) == up) ? 0.25 : 0.5);
+        const double x0 = pos[3 * j], y0 = pos[3 * j + 1], z0 = pos[3 * j + 2];
+        double dx = ra[0] - x0, dy = ra[1] - y0, dz = ra[2] - z0;
+        a0 += pade_u(c0, A.b_ee, dx * dx + dy * dy + dz * dz);
+        dx = rb[0] - x0; dy = rb[1] - y0; dz = rb[2] - z0;
+        b0 += pade_u(c0, A.b_ee, dx * dx + dy * dy + dz * dz);
+    }
+    for (int I = 0; I < A.n_nuc; ++I) {
+        const double *R = A.Rnuc + 3 * I;
+        const double c = -A.Znuc[I];
+        double dx = ra[0] - R[0], dy = ra[1] - R[1], dz = ra[2] - R[2];
+        a1 += pade_u(c, A.b_en, dx * dx + dy * dy + dz * dz);
+        dx = rb[0] - R[0]; dy = rb[1] - R[1]; dz = rb[2] - R[2];
+        b1 += pade_u(c, A.b_en, dx * dx + dy * dy + dz * dz);
+    }
+    out_a = a0 + a1;
+    out_b = b0 + b1;
 }
 
 // Displaced position of move m.
@@ -613,8 +715,10 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Heat-bath weights of the moves m in [c0, c1) (S1-S6); returns their sum.
-// With diag, stores rho and k and accumulates sum k, L^a and V_sf.
+// Heat-bath weights of the moves m in [c0, c1) (S1-S6), c0 and c1 even:
+// each step evaluates the +/- pair (m, m + 1) along one axis of one grid of
+// one electron.  Returns the sum of the weights; with diag, stores rho and k
+// and accumulates sum k, L^a and V_sf.
 __device__ __forceinline__ double move_table(const KArgs &A, double *lds, const double *Rm, int c0, int c1,
                                              int *last, double *rho_g, double *k_g, double acc[3], bool diag)
 {
@@ -622,23 +726,41 @@ __device__ __forceinline__ double move_table(const KArgs &A, double *lds, const 
     const double *pos = lds + L.pos, *Y = lds + L.Y, *Jo = lds + L.Jo;
     double *T = lds + L.T;
     double part = 0.0;
-    for (int m = c0; m < c1; ++m) {
-        const int i = m / 12;
-        double rp[3];
-        const double k = move_geometry(A, pos, Rm, m, rp);
-        const double rd = basis_dot(A, rp, Y + i * A.Kp);
-        const double dJ = jastrow_point(A, pos, i, rp) - Jo[i];
-        const double rho = rd * exp(dJ);
-        const double t = 0.5 * k * (rho > 0.0 ? rho : 0.0);
-        T[m] = t;
-        part += t;
-        if (t > 0.0) *last = m;
+    for (int m = c0; m < c1; m += 2) {
+        const int i = m / 12, g = (m / 6) & 1, ax = (m % 6) >> 1;
+        const double h = g ? A.ap : A.a;
+        const double e[3] = {Rm[ax], Rm[3 + ax], Rm[6 + ax]};
+        double ra[3], rb[3], ma[3], mb[3];
+        for (int c = 0; c < 3; ++c) {
+            const double r = pos[3 * i + c];
+            ra[c] = r + h * e[c];
+            rb[c] = r + (-h) * e[c];
+            ma[c] = r + (0.5 * h) * e[c];
+            mb[c] = r + (-0.5 * h) * e[c];
+        }
+        const double pa = p_switch(A, ma), pb = p_switch(A, mb);
+        const double ka = g ? (1.0 - pa) * A.inv_ap2 : pa * A.inv_a2;
+        const double kb = g ? (1.0 - pb) * A.inv_ap2 : pb * A.inv_a2;
+        double rda, rdb, ja, jb;
+        basis_dot2(A, ra, rb, Y + i * A.Kp, rda, rdb);
+        jastrow_point2(A, pos, i, ra, rb, ja, jb);
+        const double jo = Jo[i];
+        const double rhoa = rda * exp(ja - jo), rhob = rdb * exp(jb - jo);
+        const double ta = 0.5 * ka * (rhoa > 0.0 ? rhoa : 0.0);
+        const double tb = 0.5 * kb * (rhob > 0.0 ? rhob : 0.0);
+        T[m] = ta;
+        T[m + 1] = tb;
+        part += ta;
+        part += tb;
+        if (ta > 0.0) *last = m;
+        if (tb > 0.0) *last = m + 1;
         if (diag) {
-            if (rho_g) rho_g[m] = rho;
-            if (k_g) k_g[m] = k;
-            acc[0] += k;
-            acc[1] += k * (rho - 1.0);
-            if (rho < 0.0) acc[2] += -0.5 * k * rho;
+            if (rho_g) { rho_g[m] = rhoa; rho_g[m + 1] = rhob; }
+            if (k_g) { k_g[m] = ka; k_g[m + 1] = kb; }
+            acc[0] += ka + kb;
+            acc[1] += ka * (rhoa - 1.0) + kb * (rhob - 1.0);
+            if (rhoa < 0.0) acc[2] += -0.5 * ka * rhoa;
+            if (rhob < 0.0) acc[2] += -0.5 * kb * rhob;
         }
     }
     return part;
@@ -804,7 +926,7 @@ __device__ void accept_move(const KArgs &A, double *lds, int k, const double rol
 
 // One workgroup per walker slot: a generation of continuous-time projection,
 // or (eval != 0) the move table at frozen positions.
-__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) project_kernel(KArgs A)
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(3))) project_kernel(KArgs A)
 {
     extern __shared__ double lds[];
     __shared__ int sflag[8];   // 2-3: pivots of the generation start, 5: stop, 6: bad input
@@ -854,8 +976,8 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
         }
     }
 
-    // contiguous chunk of moves per thread
-    const int chunk = (M + NT - 1) / NT;
+    // contiguous chunk of +/- move pairs per thread (moves [c0, c1))
+    const int chunk = 2 * ((M / 2 + NT - 1) / NT);
     const int c0 = min(M, tid * chunk), c1 = min(M, c0 + chunk);
 
     if (A.eval) {
@@ -1506,7 +1628,7 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
             vnn += sys->Z[I] * sys->Z[J] / std::sqrt(dx * dx + dy * dy + dz * dz);
         }
     c->v_nn = vnn;
-    c->nt = std::min(kMaxThreads, std::max(64, ((c->M + 63) / 64) * 64));
+    c->nt = std::min(kMaxThreads, std::max(64, ((c->M / 2 + 63) / 64) * 64));
     // Stage the occupied MO block in LDS only for small walker states; larger
     // ones read it through the caches so that more walkers share a CU.
     c->L = make_layout(N, ns, K, c->Kp, c->M, true, 16 * 1024);
