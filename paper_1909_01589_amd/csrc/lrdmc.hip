@@ -54,12 +54,10 @@ struct Layout {
     int gD;     // [N][4]            grad D/D (3) and lap D/D of electron i
     int gJ;     // [N][4]            grad J (3) and lap J of electron i
     int Jo;     // [N]               Jastrow terms that contain electron i
-    int C;      // [K][ns]           MO coefficients of the occupied orbitals, or -1 (read from HBM)
     int red;    // [64]              reduction scratch
     int sc;     // [32]              block scalars
     int rng;    // [2][8][12]        rotations, -ln u1 and u2 of sixteen iterations (two halves)
     int xs;     // [NT]              per-thread inclusive prefix of T within its wavefront
-    int acc;    // [4][6]            per-wavefront partial sums of the moved electron's Jastrow
     // move-loop view of U
     int T;      // [M]               heat-bath weights of the moves
     int bv;     // [5][K]            basis value, gradient, Laplacian at one point
@@ -67,6 +65,8 @@ struct Layout {
     int wrow;   // [ns]              w_i = phi(r_new) . Ainv[:, i]
     int colk;   // [ns]              column k of Ainv before the update
     int Yk;     // [Kp]              row k of Y before the update
+    int dq;     // [4][ns]           dphi_i[c] . Ainv[:, k] of the moved electron's spin
+    int kp;     // [6][N + n_nuc]    moved electron's Jastrow terms per partner, potential change
     // generation-start view of U
     int G;      // [2][ns][2ns]      Gauss-Jordan workspace
     int piv;    // [2][2][2ns]       pivot row and row c copies
@@ -87,9 +87,8 @@ struct KArgs {
     const int *fn_info;            // [K]: group | l << 16 | component << 20
     int n_chain;
     const int *chain;              // [n_chain][3]: first group, length, step code (see basis_dot)
-    const double *mo;              // [K][n_orb]
+    const double *moT;             // [ns][K]: occupied MO coefficients, orbital-major
     double b_ee, b_en, v_nn;
-    int c_lds;                     // 1: occupied MO block staged in LDS
     // lattice
     double a, ap, inv_a2, inv_ap2, inv_2rc2, tau;
     uint64_t seed;
@@ -112,7 +111,7 @@ struct KArgs {
 };
 
 // Block scalar slots.
-enum { SC_EL = 0, SC_V = 1 };
+enum { SC_DV = 0 };
 
 __device__ __forceinline__ void report(int *err, int code, int slot)
 {
@@ -307,49 +306,52 @@ __device__ __forceinline__ double move_geometry(const KArgs &A, const double *po
 
 // -- per-walker state ------------------------------------------------------
 
-// Occupied MO block: C[mu][j] at Cm[mu * ldc + j].
-struct MoView {
-    const double *p;
-    int ld;
-};
-
-__device__ __forceinline__ MoView mo_view(const KArgs &A, const double *lds)
+// Orbital contraction of basis blocks b[e][5][Kp] (value, gradient,
+// Laplacian of every basis function at the point of electron e of the
+// batch): for each group g = (e, j), e < ne, j < n,
+//   out[c] = sum_mu b[e][c][mu] C[mu][j]   (c < 5)
+// and with W also out[5] = sum_mu b[e][0][mu] Yrow_j[mu] with Yrow_j at
+// yrow + j Kp.  A group is split over P lanes (a power of two, at most 16);
+// lane p takes mu = p, p + P, ...  Loads go out four basis functions at a
+// time and the P partial sums are combined in registers (DPP).
+template <bool W, typename Store>
+__device__ __forceinline__ void contract(const KArgs &A, const double *b, int ne, int n, const double *yrow,
+                                         Store store)
 {
-    if (A.c_lds) return {lds + A.L.C, A.ns};
-    return {A.mo, A.n_orb};
-}
-
-// out(e, c, j) = sum_mu b[e][c][mu] C[mu][j] for ne basis blocks b[e][5][Kp],
-// c < 5, j < n.  Each output is split over P adjacent lanes (a power of two,
-// at most 16); lane p sums mu = p, p + P, ... (neighbouring lanes touch
-// neighbouring LDS banks) and the lanes combine with shuffles.
-template <typename Store>
-__device__ __forceinline__ void orb_contract(const KArgs &A, const double *b, int ne, int n, MoView C,
-                                             Store store)
-{
-    const int K = A.K, Kp = A.Kp, NT = blockDim.x, nout = ne * 5 * n;
-    int P = 1;
-    while (P < 16 && nout * P * 2 <= NT) P <<= 1;
-    for (int base = 0; base < nout * P; base += NT) {
-        const int t = base + threadIdx.x, o = t / P, part = t - o * P;
-        double acc0 = 0.0, acc1 = 0.0;
-        int e = 0, c = 0, j = 0;
-        if (o < nout) {
-            e = o / (5 * n);
-            const int r = o - e * 5 * n;
-            c = r / n;
-            j = r - c * n;
-            const double *bb = b + (e * 5 + c) * Kp;
-            int mu = part;
-            for (; mu + P < K; mu += 2 * P) {
-                acc0 += bb[mu] * C.p[mu * C.ld + j];
-                acc1 += bb[mu + P] * C.p[(mu + P) * C.ld + j];
+    const int K = A.K, Kp = A.Kp, NT = blockDim.x, ng = ne * n;
+    int lgP = 4;
+    while (lgP > 0 && (ng << lgP) > NT) --lgP;
+    const int P = 1 << lgP, Q = (K + P - 1) >> lgP;
+    for (int base = 0; base < (ng << lgP); base += NT) {
+        const int t = base + threadIdx.x, g = t >> lgP, part = t & (P - 1);
+        const bool live = g < ng;
+        const int e = live ? g / n : 0, j = live ? g - e * n : 0;
+        const double *bb = b + e * 5 * Kp, *ct = A.moT + (size_t)j * K, *yr = yrow + j * Kp;
+        double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (live) {
+            for (int q0 = 0; q0 < Q; q0 += 4) {
+                double cv[4], bq[5][4], yv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int mu = part + ((q0 + u) << lgP);
+                    const bool ok = mu < K;
+                    const int mc = ok ? mu : K - 1;
+                    cv[u] = ok ? ct[mc] : 0.0;
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) bq[c][u] = bb[c * Kp + mc];
+                    if (W) yv[u] = ok ? yr[mc] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) acc[c] = fma(bq[c][u], cv[u], acc[c]);
+                    if (W) acc[5] = fma(bq[0][u], yv[u], acc[5]);
+                }
             }
-            if (mu < K) acc0 += bb[mu] * C.p[mu * C.ld + j];
         }
-        double acc = acc0 + acc1;
-        for (int off = P >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-        if (o < nout && part == 0) store(e, c, j, acc);
+#pragma unroll
+        for (int c = 0; c < (W ? 6 : 5); ++c) acc[c] = group_sum(acc[c], P);
+        if (live && part == 0) store(e, j, acc);
     }
 }
 
@@ -536,10 +538,8 @@ __device__ double jastrow_setup(const KArgs &A, double *lds)
                 else if (j > i) vsum += pr.y;        // 1 / r_ij, each pair once
             }
         }
-        for (int off = seg >> 1; off > 0; off >>= 1) {
-            g0 += __shfl_xor(g0, off, 64); g1 += __shfl_xor(g1, off, 64); g2 += __shfl_xor(g2, off, 64);
-            lap += __shfl_xor(lap, off, 64); jo += __shfl_xor(jo, off, 64);
-        }
+        g0 = group_sum(g0, seg); g1 = group_sum(g1, seg); g2 = group_sum(g2, seg);
+        lap = group_sum(lap, seg); jo = group_sum(jo, seg);
         if (i < N && sub == 0) {
             gJ[4 * i] = g0; gJ[4 * i + 1] = g1; gJ[4 * i + 2] = g2; gJ[4 * i + 3] = lap;
             Jo[i] = jo;
@@ -582,7 +582,6 @@ __device__ int walker_setup(const KArgs &A, double *lds, int *sflag, double &EL,
     double *pos = lds + L.pos, *G = lds + L.G, *bvb = lds + L.bvb;
     double *dphi = lds + L.dphi, *Ainv = lds + L.Ainv;
     const int two = 2 * ns;
-    const MoView Cv = mo_view(A, lds);
 
     // right halves = identity
     for (int t = tid; t < 2 * ns * two; t += NT) {
@@ -597,11 +596,11 @@ __device__ int walker_setup(const KArgs &A, double *lds, int *sflag, double &EL,
             basis_fn_full(A, mu, r, bvb + e * 5 * Kp);
         }
         __syncthreads();
-        orb_contract(A, bvb, ne, ns, Cv, [&](int e, int c, int j, double v) {
+        contract<false>(A, bvb, ne, ns, nullptr, [&](int e, int j, const double *v) {
             const int i = e0 + e, s = spin_of(A, i), n = s ? A.n_dn : A.n_up, il = s ? i - A.n_up : i;
             if (j >= n) return;
-            if (c == 0) G[(s * ns + il) * two + j] = v;
-            else dphi[i * L.dld + (c - 1) * ns + j] = v;
+            G[(s * ns + il) * two + j] = v[0];
+            for (int c = 1; c < 5; ++c) dphi[i * L.dld + (c - 1) * ns + j] = v[c];
         });
         __syncthreads();
     }
@@ -669,7 +668,7 @@ __device__ int walker_setup(const KArgs &A, double *lds, int *sflag, double &EL,
         const int s = spin_of(A, i), n = s ? A.n_dn : A.n_up, il = s ? i - A.n_up : i;
         const double *inv = Ainv + s * ns * ns;
         double acc = 0.0;
-        for (int j = 0; j < n; ++j) acc += Cv.p[mu * Cv.ld + j] * inv[j * ns + il];
+        for (int j = 0; j < n; ++j) acc += A.moT[j * K + mu] * inv[j * ns + il];
         Y[i * Kp + mu] = acc;
     }
     det_derivs_all(A, Ainv, dphi, lds + L.gD);
@@ -766,162 +765,181 @@ __device__ __forceinline__ double move_table(const KArgs &A, double *lds, const 
     return part;
 }
 
-// Sherman-Morrison update after electron k moved from rold to rnew (S8).
-// The basis block, the orbital contraction and the rank-1 updates use the
-// whole workgroup; the per-electron Jastrow and determinant derivatives and
-// the local-energy reduction run in the first wavefront, ordered by
-// wave_sync.  Updates Ainv, Y, the derivative rows, the determinant and
-// Jastrow derivatives, the Jastrow own sums and the potential; the new E_L
-// and V go to the block scalars (read after the caller's barrier).
-__device__ void accept_move(const KArgs &A, double *lds, int k, const double rold[3], const double rnew[3],
-                            double V)
+// Index of item t in a flat range of rows of length len: t / len for
+// t < 2^16, len <= 2^12, through one single-precision multiply (the quotient
+// is at least 0.5 / len away from an integer, far above the rounding error).
+__device__ __forceinline__ int row_of(int t, float inv_len)
+{
+    return (int)(((float)t + 0.5f) * inv_len);
+}
+
+// Sum of x[0 .. len) in index order, loads issued eight at a time.
+__device__ __forceinline__ double seq_sum(const double *x, int len)
+{
+    double s = 0.0;
+    for (int p0 = 0; p0 < len; p0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = (p0 + u < len) ? x[min(p0 + u, len - 1)] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    return s;
+}
+
+// Dot product of x[0 .. len) and y[0], y[ys], ... in index order, loads
+// issued eight at a time.
+__device__ __forceinline__ double seq_dot(const double *x, const double *y, int len, int ys)
+{
+    double s = 0.0;
+    for (int p0 = 0; p0 < len; p0 += 8) {
+        double u0[8], v0[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = min(p0 + u, len - 1);
+            u0[u] = (p0 + u < len) ? x[q] : 0.0;
+            v0[u] = y[q * ys];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s = fma(u0[u], v0[u], s);
+    }
+    return s;
+}
+
+// Update of the walker state after electron k moved from rold to rnew (S8),
+// in three workgroup-wide phases separated by barriers:
+//  1. basis block at r_new; copies of row k of Y and column k of Ainv;
+//     dq = dphi_i . Ainv[:, k] of the other electrons of k's spin; the pair
+//     terms of every other electron i with k (new minus old) into its Jastrow
+//     gradient, Laplacian and own sum, and the terms of k with each partner
+//     (electrons and nuclei) with the potential change into kp;
+//  2. new orbital row with derivatives (vrow) and w_i = g(r_new) . Y_i;
+//  3. rank-1 (Sherman-Morrison) updates of Ainv and of the spin's rows of Y,
+//     the new derivative row and position of k, grad/lap D/D of the spin's
+//     electrons through Ainv' = Ainv - colk (w - e_k)^T / rho, and the sums
+//     of kp (Jastrow gradient, Laplacian and own sum of k; the potential
+//     change into the block scalars).
+// Item ranges of different cost start on wavefront boundaries.
+__device__ void accept_move(const KArgs &A, double *lds, int k, const double rold[3], const double rnew[3])
 {
     const Layout &L = A.L;
     const int N = A.N, ns = A.ns, K = A.K, Kp = A.Kp, tid = threadIdx.x, NT = blockDim.x;
-    const int lane = tid & 63, wv = tid >> 6;
     const int s = spin_of(A, k), n = s ? A.n_dn : A.n_up, kl = s ? k - A.n_up : k, i0 = s ? A.n_up : 0;
+    const int np = N + A.n_nuc;
     double *pos = lds + L.pos, *bv = lds + L.bv, *vrow = lds + L.vrow, *wrow = lds + L.wrow;
     double *colk = lds + L.colk, *Yk = lds + L.Yk, *Y = lds + L.Y, *dphi = lds + L.dphi;
-    double *gD = lds + L.gD, *gJ = lds + L.gJ, *Jo = lds + L.Jo;
+    double *gD = lds + L.gD, *gJ = lds + L.gJ, *Jo = lds + L.Jo, *dq = lds + L.dq, *kp = lds + L.kp;
     double *inv = lds + L.Ainv + s * ns * ns;
-    const MoView Cv = mo_view(A, lds);
+    auto up64 = [](int x) { return (x + 63) & ~63; };
 
-    // A1: basis block at the new position
-    for (int mu = tid; mu < K; mu += NT) basis_fn_full(A, mu, rnew, bv);
-    __syncthreads();
-
-    // A2: new orbital row with derivatives (vrow), w_i = g(r_new) . Y_i, and
-    // copies of column k of Ainv and row k of Y.
-    orb_contract(A, bv, 1, n, Cv, [&](int, int c, int j, double v) { vrow[c * ns + j] = v; });
+    // phase 1
     {
-        int P = 1;
-        while (P < 16 && n * P * 2 <= NT) P <<= 1;
-        for (int base = 0; base < n * P; base += NT) {
-            const int t = base + tid, o = t / P, part = t - o * P;
-            double a0 = 0.0, a1 = 0.0;
-            if (o < n) {
-                const double *yr = Y + (i0 + o) * Kp;
-                int mu = part;
-                for (; mu + P < K; mu += 2 * P) {
-                    a0 += bv[mu] * yr[mu];
-                    a1 += bv[mu + P] * yr[mu + P];
+        const int r0 = up64(np), r1 = r0 + up64(K), r2 = r1 + up64(4 * n), r3 = r2 + K + n;
+        for (int t = tid; t < r3; t += NT) {
+            if (t < r0) {
+                const int p = t;
+                if (p >= np) continue;
+                double o[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                if (p < N) {
+                    if (p != k) {
+                        const double c = (spin_of(A, p) == s) ? 0.25 : 0.5;
+                        const double xi = pos[3 * p], yi = pos[3 * p + 1], zi = pos[3 * p + 2];
+                        const double ax = xi - rnew[0], ay = yi - rnew[1], az = zi - rnew[2];
+                        const double bx = xi - rold[0], by = yi - rold[1], bz = zi - rold[2];
+                        const PairD pn = pade_d(c, A.b_ee, ax * ax + ay * ay + az * az);
+                        const PairD po = pade_d(c, A.b_ee, bx * bx + by * by + bz * bz);
+                        gJ[4 * p] += pn.f * ax - po.f * bx;
+                        gJ[4 * p + 1] += pn.f * ay - po.f * by;
+                        gJ[4 * p + 2] += pn.f * az - po.f * bz;
+                        gJ[4 * p + 3] += pn.lap - po.lap;
+                        Jo[p] += pn.u - po.u;
+                        o[0] = -(pn.f * ax); o[1] = -(pn.f * ay); o[2] = -(pn.f * az);
+                        o[3] = pn.lap; o[4] = pn.u; o[5] = pn.y - po.y;
+                    }
+                } else {
+                    const double *R = A.Rnuc + 3 * (p - N);
+                    const double c = -A.Znuc[p - N];
+                    const double dx = rnew[0] - R[0], dy = rnew[1] - R[1], dz = rnew[2] - R[2];
+                    const double ex = rold[0] - R[0], ey = rold[1] - R[1], ez = rold[2] - R[2];
+                    const PairD pr = pade_d(c, A.b_en, dx * dx + dy * dy + dz * dz);
+                    o[0] = pr.f * dx; o[1] = pr.f * dy; o[2] = pr.f * dz;
+                    o[3] = pr.lap; o[4] = pr.u; o[5] = c * (pr.y - rsqrt_nr(ex * ex + ey * ey + ez * ez));
                 }
-                if (mu < K) a0 += bv[mu] * yr[mu];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) kp[c * np + p] = o[c];
+            } else if (t < r1) {
+                const int mu = t - r0;
+                if (mu < K) basis_fn_full(A, mu, rnew, bv);
+            } else if (t < r2) {
+                const int u = t - r1;
+                if (u >= 4 * n) continue;
+                const int c4 = u & 3, il = u >> 2;
+                if (il != kl) dq[c4 * ns + il] = seq_dot(dphi + (i0 + il) * L.dld + c4 * ns, inv + kl, n, ns);
+            } else {
+                const int u = t - r2;
+                if (u < K) Yk[u] = Y[k * Kp + u];
+                else colk[u - K] = inv[(u - K) * ns + kl];
             }
-            double acc = a0 + a1;
-            for (int off = P >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-            if (o < n && part == 0) wrow[o] = acc;
         }
-    }
-    for (int t = tid; t < n + K; t += NT) {
-        if (t < n) colk[t] = inv[t * ns + kl];
-        else Yk[t - n] = Y[k * Kp + t - n];
     }
     __syncthreads();
 
-    const double irho = uni(1.0 / wrow[kl]);
-    // A3: rank-1 updates of Ainv and of the spin's rows of Y; new derivative
-    // row and position of electron k.
-    for (int t = tid; t < n * n + n * K + 4 * n + 3; t += NT) {
-        if (t < n * n) {
-            const int j = t / n, i = t - j * n;
-            const double f = (wrow[i] - (i == kl ? 1.0 : 0.0)) * irho;
-            inv[j * ns + i] -= colk[j] * f;
-        } else if (t < n * n + n * K) {
-            const int u = t - n * n, i = u / K, mu = u - i * K;
-            const double f = (wrow[i] - (i == kl ? 1.0 : 0.0)) * irho;
-            Y[(i0 + i) * Kp + mu] -= Yk[mu] * f;
-        } else if (t < n * n + n * K + 4 * n) {
-            const int u = t - n * n - n * K, c = u / n, j = u - c * n;
-            dphi[k * L.dld + c * ns + j] = vrow[(c + 1) * ns + j];
-        } else {
-            const int c = t - n * n - n * K - 4 * n;
-            pos[3 * k + c] = rnew[c];
-        }
-    }
-    if (wv != 0) return;
+    // phase 2
+    contract<true>(A, bv, 1, n, Y + i0 * Kp, [&](int, int j, const double *v) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) vrow[c * ns + j] = v[c];
+        wrow[j] = v[5];
+    });
+    __syncthreads();
 
-    // A4 (first wavefront): items t < N update electron t (pair with k, new
-    // minus old; grad/lap D/D through Ainv' = Ainv - colk (w - e_k)^T / rho,
-    // or for t == k from the new derivative row and Ainv'[:, k] = colk / rho);
-    // items t >= N are the partners of electron k at r_new (Jastrow gradient,
-    // Laplacian, own sum) and the electron-nucleus change of the potential.
-    // None of these reads what A3 writes.
-    double dv = 0.0, o[6] = {0, 0, 0, 0, 0, 0};
-    const int np = N + A.n_nuc;
-    for (int t = lane; t < N + np; t += 64) {
-        if (t < N) {
-            const int i = t;
-            if (i != k) {
-                const double c = (spin_of(A, i) == s) ? 0.25 : 0.5;
-                const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
-                const double ax = xi - rnew[0], ay = yi - rnew[1], az = zi - rnew[2];
-                const double bx = xi - rold[0], by = yi - rold[1], bz = zi - rold[2];
-                const PairD pn = pade_d(c, A.b_ee, ax * ax + ay * ay + az * az);
-                const PairD po = pade_d(c, A.b_ee, bx * bx + by * by + bz * bz);
-                gJ[4 * i] += pn.f * ax - po.f * bx;
-                gJ[4 * i + 1] += pn.f * ay - po.f * by;
-                gJ[4 * i + 2] += pn.f * az - po.f * bz;
-                gJ[4 * i + 3] += pn.lap - po.lap;
-                Jo[i] += pn.u - po.u;
-                dv += pn.y - po.y;
-                if (spin_of(A, i) == s) {
-                    const double f = wrow[i - i0] * irho;
-                    for (int c4 = 0; c4 < 4; ++c4) {
-                        const double *dp = dphi + i * L.dld + c4 * ns;
-                        double acc = 0.0;
-                        for (int j = 0; j < n; ++j) acc += dp[j] * colk[j];
-                        gD[4 * i + c4] -= f * acc;
+    // phase 3
+    const double irho = uni(1.0 / wrow[kl]);
+    {
+        const int r0 = up64(6 + 4 * n);
+        const int q0 = r0 + 4 * n, q1 = q0 + 3, q2 = q1 + n * n, q3 = q2 + n * K;
+        const float inv_n = 1.0f / (float)n, inv_K = 1.0f / (float)K;
+        for (int t = tid; t < q3; t += NT) {
+            if (t < r0) {
+                if (t < 6) {
+                    const double v = seq_sum(kp + t * np, np);
+                    if (t < 4) gJ[4 * k + t] = v;
+                    else if (t == 4) Jo[k] = v;
+                    else lds[L.sc + SC_DV] = v;
+                } else if (t < 6 + 4 * n) {
+                    const int u = t - 6, c4 = u & 3, il = u >> 2;
+                    if (il != kl) {
+                        gD[4 * (i0 + il) + c4] -= (wrow[il] * irho) * dq[c4 * ns + il];
+                    } else {
+                        gD[4 * k + c4] = seq_dot(vrow + (c4 + 1) * ns, colk, n, 1) * irho;
                     }
                 }
+            } else if (t < q0) {
+                const int u = t - r0, c = row_of(u, inv_n), j = u - c * n;
+                dphi[k * L.dld + c * ns + j] = vrow[(c + 1) * ns + j];
+            } else if (t < q1) {
+                pos[3 * k + t - q0] = rnew[t - q0];
+            } else if (t < q2) {
+                const int u = t - q1, j = row_of(u, inv_n), i = u - j * n;
+                const double f = (wrow[i] - (i == kl ? 1.0 : 0.0)) * irho;
+                inv[j * ns + i] -= colk[j] * f;
             } else {
-                for (int c4 = 0; c4 < 4; ++c4) {
-                    double acc = 0.0;
-                    for (int j = 0; j < n; ++j) acc += vrow[(c4 + 1) * ns + j] * colk[j];
-                    gD[4 * k + c4] = acc * irho;
-                }
-            }
-        } else {
-            const int p = t - N;
-            if (p == k) continue;
-            double dx, dy, dz, c, b;
-            if (p < N) {
-                dx = rnew[0] - pos[3 * p]; dy = rnew[1] - pos[3 * p + 1]; dz = rnew[2] - pos[3 * p + 2];
-                c = (spin_of(A, p) == s) ? 0.25 : 0.5;
-                b = A.b_ee;
-            } else {
-                const double *R = A.Rnuc + 3 * (p - N);
-                dx = rnew[0] - R[0]; dy = rnew[1] - R[1]; dz = rnew[2] - R[2];
-                c = -A.Znuc[p - N];
-                b = A.b_en;
-            }
-            const PairD pr = pade_d(c, b, dx * dx + dy * dy + dz * dz);
-            o[0] += pr.f * dx; o[1] += pr.f * dy; o[2] += pr.f * dz;
-            o[3] += pr.lap;
-            o[4] += pr.u;
-            if (p >= N) {
-                const double *R = A.Rnuc + 3 * (p - N);
-                const double ex = rold[0] - R[0], ey = rold[1] - R[1], ez = rold[2] - R[2];
-                o[5] += c * (pr.y - rsqrt_nr(ex * ex + ey * ey + ez * ez));
+                const int u = t - q2, i = row_of(u, inv_K), mu = u - i * K;
+                const double f = (wrow[i] - (i == kl ? 1.0 : 0.0)) * irho;
+                Y[(i0 + i) * Kp + mu] -= Yk[mu] * f;
             }
         }
     }
-    for (int q = 0; q < 6; ++q) o[q] = wave_sum(o[q]);
-    if (lane == 0) {
-        gJ[4 * k] = o[0]; gJ[4 * k + 1] = o[1]; gJ[4 * k + 2] = o[2]; gJ[4 * k + 3] = o[3];
-        Jo[k] = o[4];
-    }
-    wave_sync();
+}
 
-    // A5: Laplacian terms and the potential change over the wavefront
-    // (N <= 64: lane i holds electron i).
-    const double term = wave_sum(lane < N ? psi_lap_term(gD + 4 * lane, gJ + 4 * lane) : 0.0);
-    const double dvt = wave_sum(dv) + o[5];
-    if (lane == 0) {
-        const double Vn = V + dvt;
-        lds[L.sc + SC_V] = Vn;
-        lds[L.sc + SC_EL] = -0.5 * term + Vn;
-    }
+// Local energy from the determinant and Jastrow derivatives of every
+// electron: E_L = -1/2 sum_i (lap Psi / Psi)_i + V, summed by each wavefront
+// (identical in all of them).
+__device__ __forceinline__ double local_energy(const KArgs &A, const double *lds, double V)
+{
+    const int lane = threadIdx.x & 63;
+    double t = 0.0;
+    for (int i = lane; i < A.N; i += 64) t += psi_lap_term(lds + A.L.gD + 4 * i, lds + A.L.gJ + 4 * i);
+    return -0.5 * wave_sum(t) + V;
 }
 
 // One workgroup per walker slot: a generation of continuous-time projection,
@@ -929,8 +947,7 @@ __device__ void accept_move(const KArgs &A, double *lds, int k, const double rol
 __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(3))) project_kernel(KArgs A)
 {
     extern __shared__ double lds[];
-    __shared__ int sflag[8];   // 2-3: pivots of the generation start, 5: stop, 6: bad input
-    __shared__ int slast[16];  // per wavefront: last move with T > 0
+    __shared__ int sflag[8];   // 2-3: pivots of the generation start, 5: stop, 6: bad input, 7: last move
     const Layout &L = A.L;
     const int tid = threadIdx.x, NT = blockDim.x, slot = blockIdx.x, N = A.N, M = A.M;
     const int lane = tid & 63, wv = tid >> 6, nw = NT >> 6;
@@ -947,11 +964,6 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
         pos[t] = v;
         if (!isfinite(v)) sflag[6] = 1;
     }
-    if (A.c_lds)
-        for (int t = tid; t < A.K * A.ns; t += NT) {
-            const int mu = t / A.ns, j = t - mu * A.ns;
-            lds[L.C + t] = A.mo[mu * A.n_orb + j];
-        }
     refill_rng(A, rng, slot, 0);
     __syncthreads();
     if (sflag[5]) return;
@@ -1013,17 +1025,10 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
         const double part = move_table(A, lds, R, c0, c1, &last, nullptr, nullptr, dummy, false);
 
         // inclusive prefix of the per-thread sums within each wavefront; the
-        // wavefront totals and last moves with T > 0 go to LDS
-        double x = part;
-        for (int off = 1; off < 64; off <<= 1) {
-            const double y = __shfl_up(x, off, 64);
-            if (lane >= off) x += y;
-        }
+        // wavefront totals go to LDS
+        const double x = wave_inclusive_scan(part);
         xs[tid] = x;
-        int lm = last;
-        for (int off = 32; off > 0; off >>= 1) lm = max(lm, __shfl_xor(lm, off, 64));
         if (lane == 63) red[wv] = x;
-        if (lane == 0) slast[wv] = lm;
         __syncthreads();
 
         double Delta = 0.0;
@@ -1081,10 +1086,16 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
                     }
                 }
             }
-            if (ms < 0)
-                for (int w = 0; w < nw; ++w) ms = max(ms, slast[w]);
         }
         ms = uni(ms);
+        if (ms < 0) {
+            // rounding left no C_m above the threshold: the last move with T > 0
+            if (tid == 0) sflag[7] = -1;
+            __syncthreads();
+            if (last >= 0) atomicMax(&sflag[7], last);
+            __syncthreads();
+            ms = uni(sflag[7]);
+        }
         if (ms < 0) {
             if (tid == 0) report(A.err, kErrNonFinite, slot);
             return;
@@ -1095,12 +1106,12 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
             move_position(A, pos, R, ms, rnew);
             for (int c = 0; c < 3; ++c) rnew[c] = uni(rnew[c]);
             const double rold[3] = {uni(pos[3 * k]), uni(pos[3 * k + 1]), uni(pos[3 * k + 2])};
-            accept_move(A, lds, k, rold, rnew, V);
+            accept_move(A, lds, k, rold, rnew);
             if (((it + 1) & 7) == 0) refill_rng(A, rng, slot, it + 1);
         }
         __syncthreads();
-        EL = uni(lds[L.sc + SC_EL]);
-        V = uni(lds[L.sc + SC_V]);
+        V = uni(V + lds[L.sc + SC_DV]);
+        EL = uni(local_energy(A, lds, V));
         ++moves;
         if (!isfinite(EL)) {
             if (tid == 0) report(A.err, kErrNonFinite, slot);
@@ -1267,10 +1278,9 @@ int fail(lrdmc_ctx *ctx, int code, const std::string &msg)
                         std::string(#expr) + ": " + hipGetErrorString(e_));                         \
     } while (0)
 
-// LDS layout of one walker.  c_lds: stage the occupied MO block.  The
-// electron batch of the generation start grows until the block reaches
+// LDS layout of one walker.  The electron batch of the generation start grows until the block reaches
 // `target` bytes (or all electrons fit), never below one electron.
-Layout make_layout(int N, int ns, int K, int Kp, int M, bool c_lds, size_t target)
+Layout make_layout(int N, int ns, int K, int Kp, int M, int n_nuc, size_t target)
 {
     Layout L{};
     int o = 0;
@@ -1283,12 +1293,10 @@ Layout make_layout(int N, int ns, int K, int Kp, int M, bool c_lds, size_t targe
     L.gD = take(4 * N);
     L.gJ = take(4 * N);
     L.Jo = take(N);
-    L.C = c_lds ? take(K * ns) : -1;
     L.red = take(64);
     L.sc = take(32);
     L.rng = take(16 * 12);
     L.xs = take(kMaxThreads);
-    L.acc = take(32);
     const int U = o;
     // move-loop view
     int q = U;
@@ -1298,6 +1306,8 @@ Layout make_layout(int N, int ns, int K, int Kp, int M, bool c_lds, size_t targe
     L.wrow = q; q += ns;
     L.colk = q; q += ns;
     L.Yk = q; q += Kp;
+    L.dq = q; q += 4 * ns;
+    L.kp = q; q += 6 * (N + n_nuc);
     const int loop_end = q;
     // generation-start view
     q = U;
@@ -1322,9 +1332,9 @@ KArgs base_args(const lrdmc_ctx *c)
     A.N = c->N; A.n_up = c->n_up; A.n_dn = c->n_dn; A.ns = c->ns; A.K = c->K; A.Kp = c->Kp;
     A.n_orb = c->n_orb; A.n_nuc = c->n_nuc; A.n_grp = c->n_grp; A.n_heavy = c->n_heavy; A.M = c->M;
     A.Znuc = c->d_Z; A.Rnuc = c->d_R; A.heavy = c->d_heavy; A.grp_nuc = c->d_gnuc;
-    A.grp_alpha = c->d_galpha; A.grp_off = c->d_goff; A.mo = c->d_mo;
+    A.grp_alpha = c->d_galpha; A.grp_off = c->d_goff; A.moT = c->d_mo;
     A.n_chain = c->n_chain; A.chain = c->d_chain; A.fn_info = c->d_fn;
-    A.b_ee = c->b_ee; A.b_en = c->b_en; A.v_nn = c->v_nn; A.c_lds = c->L.C >= 0;
+    A.b_ee = c->b_ee; A.b_en = c->b_en; A.v_nn = c->v_nn;
     A.a = c->prm.a; A.ap = c->prm.a_prime;
     A.inv_a2 = 1.0 / (c->prm.a * c->prm.a);
     A.inv_ap2 = 1.0 / (c->prm.a_prime * c->prm.a_prime);
@@ -1631,9 +1641,7 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
     c->nt = std::min(kMaxThreads, std::max(64, ((c->M / 2 + 63) / 64) * 64));
     // Stage the occupied MO block in LDS only for small walker states; larger
     // ones read it through the caches so that more walkers share a CU.
-    c->L = make_layout(N, ns, K, c->Kp, c->M, true, 16 * 1024);
-    if (sizeof(double) * (size_t)c->L.total > 16 * 1024)
-        c->L = make_layout(N, ns, K, c->Kp, c->M, false, prm->refresh > 1 ? 0 : 38 * 1024);
+    c->L = make_layout(N, ns, K, c->Kp, c->M, sys->n_nuc, prm->refresh > 1 ? 0 : 38 * 1024);
     c->lds_bytes = sizeof(double) * (size_t)c->L.total;
     c->state_len = (c->L.Jo + N - c->L.Y) + 2;
 
@@ -1653,10 +1661,13 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
         return cleanup(LRDMC_EDEVICE, "lrdmc_create: cannot raise the LDS limit");
 
     const size_t W = n_walkers, s3 = 3 * (size_t)N;
+    std::vector<double> moT((size_t)ns * K);   // occupied block, orbital-major
+    for (int j = 0; j < ns; ++j)
+        for (int mu = 0; mu < K; ++mu) moT[(size_t)j * K + mu] = sys->mo[(size_t)mu * sys->n_orb + j];
     auto alloc = [&](void **p, size_t bytes) { return hipMalloc(p, bytes) == hipSuccess; };
     bool ok = alloc((void **)&c->d_Z, sizeof(double) * sys->n_nuc) &&
               alloc((void **)&c->d_R, sizeof(double) * 3 * sys->n_nuc) &&
-              alloc((void **)&c->d_mo, sizeof(double) * K * sys->n_orb) &&
+              alloc((void **)&c->d_mo, sizeof(double) * K * ns) &&
               alloc((void **)&c->d_galpha, sizeof(double) * gnuc.size()) &&
               alloc((void **)&c->d_gnuc, sizeof(int) * gnuc.size()) &&
               alloc((void **)&c->d_goff, sizeof(int) * goff.size()) &&
@@ -1673,7 +1684,7 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
     if (!ok) return cleanup(LRDMC_ENOMEM, "lrdmc_create: device allocation failed");
     ok = hipMemcpy(c->d_Z, sys->Z, sizeof(double) * sys->n_nuc, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(c->d_R, sys->R, sizeof(double) * 3 * sys->n_nuc, hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(c->d_mo, sys->mo, sizeof(double) * K * sys->n_orb, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(c->d_mo, moT.data(), sizeof(double) * K * ns, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(c->d_galpha, galpha.data(), sizeof(double) * gnuc.size(), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(c->d_gnuc, gnuc.data(), sizeof(int) * gnuc.size(), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(c->d_goff, goff.data(), sizeof(int) * goff.size(), hipMemcpyHostToDevice) == hipSuccess &&

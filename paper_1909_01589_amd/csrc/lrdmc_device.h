@@ -63,13 +63,82 @@ __device__ __forceinline__ void rotation(const double u[3], double Rm[9])
 }
 
 // ---------------------------------------------------------------------------
+// Cross-lane moves that stay in the VALU: DPP row operations and the gfx950
+// permlane swaps.  They read every lane of the wavefront, so callers keep the
+// whole wavefront active.
+
+// Value of the lane selected by the DPP control; 0 where there is none (row
+// shifts at the row edge) and in rows left out by row_mask.
+template <int ctrl, int row_mask = 0xf>
+__device__ __forceinline__ double dpp(double v)
+{
+    return __builtin_amdgcn_update_dpp(0.0, v, ctrl, row_mask, 0xf, false);
+}
+
+constexpr int kDppQuad1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuad2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;  // lane 7 - i within 8
+constexpr int kDppMirror = 0x140;      // lane 15 - i within 16
+constexpr int kDppShr = 0x110;         // + n: row_shr:n
+constexpr int kDppBcast15 = 0x142;     // lane 15 of the previous row
+constexpr int kDppBcast31 = 0x143;     // lane 31
+
+// v plus the value of the same lane in the neighbouring group of 16 (rows
+// 0 <-> 1, 2 <-> 3) or 32 (halves); both lanes of a pair get the same sum.
+__device__ __forceinline__ double add_swap16(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)b, hi = (unsigned)((unsigned long long)b >> 32);
+    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    const double a = __longlong_as_double((long long)(((unsigned long long)h[0] << 32) | l[0]));
+    const double c = __longlong_as_double((long long)(((unsigned long long)h[1] << 32) | l[1]));
+    return a + c;
+}
+
+__device__ __forceinline__ double add_swap32(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)b, hi = (unsigned)((unsigned long long)b >> 32);
+    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    const double a = __longlong_as_double((long long)(((unsigned long long)h[0] << 32) | l[0]));
+    const double c = __longlong_as_double((long long)(((unsigned long long)h[1] << 32) | l[1]));
+    return a + c;
+}
+
+// Sum over aligned groups of P lanes (P a power of two, at most 64, uniform).
+// A butterfly: every lane of a group ends with the same bits.
+__device__ __forceinline__ double group_sum(double v, int P)
+{
+    if (P >= 2) v += dpp<kDppQuad1>(v);
+    if (P >= 4) v += dpp<kDppQuad2>(v);
+    if (P >= 8) v += dpp<kDppHalfMirror>(v);
+    if (P >= 16) v += dpp<kDppMirror>(v);
+    if (P >= 32) v = add_swap16(v);
+    if (P >= 64) v = add_swap32(v);
+    return v;
+}
+
+// Inclusive prefix sum over the 64 lanes (Hillis-Steele inside rows of 16,
+// then the row totals by broadcast).
+__device__ __forceinline__ double wave_inclusive_scan(double x)
+{
+    x += dpp<kDppShr + 1>(x);
+    x += dpp<kDppShr + 2>(x);
+    x += dpp<kDppShr + 4>(x);
+    x += dpp<kDppShr + 8>(x);
+    x += dpp<kDppBcast15, 0xa>(x);
+    x += dpp<kDppBcast31, 0xc>(x);
+    return x;
+}
+
+// ---------------------------------------------------------------------------
 // Reductions over 64-lane wavefronts and over the workgroup.
 
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    return group_sum(v, 64);
 }
 
 __device__ __forceinline__ double wave_max(double v)
