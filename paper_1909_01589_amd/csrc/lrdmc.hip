@@ -54,12 +54,12 @@ struct Layout {
     int gD;     // [N][4]            grad D/D (3) and lap D/D of electron i
     int gJ;     // [N][4]            grad J (3) and lap J of electron i
     int Jo;     // [N]               Jastrow terms that contain electron i
-    int red;    // [64]              reduction scratch
-    int sc;     // [32]              block scalars
-    int rng;    // [2][8][12]        rotations, -ln u1 and u2 of sixteen iterations (two halves)
-    int xs;     // [NT]              per-thread inclusive prefix of T within its wavefront
+    int red;    // [16]              reduction scratch
+    int sc;     // [8]               block scalars
+    int rng;    // [8][12]           rotations, -ln u1 and u2 of eight iterations
     // move-loop view of U
-    int T;      // [M]               heat-bath weights of the moves
+    int xs;     // [NT]              per-thread inclusive prefix of T within its wavefront
+    int T;      // [M]               heat-bath weights of the moves (shared with vrow, wrow)
     int bv;     // [5][K]            basis value, gradient, Laplacian at one point
     int vrow;   // [5][ns]           orbital value, gradient, Laplacian at one point
     int wrow;   // [ns]              w_i = phi(r_new) . Ainv[:, i]
@@ -682,7 +682,8 @@ __device__ int walker_setup(const KArgs &A, double *lds, int *sflag, double &EL,
 }
 
 // Random numbers of iterations it .. it+7 (rotation, -ln u1 and u2), computed
-// by eight lanes at once into half (it / 8) % 2 of rng[2][8][12].
+// by eight lanes at once into rng[8][12] (it a multiple of 8; every read of
+// the previous eight is done when the refill runs).
 __device__ __forceinline__ void refill_rng(const KArgs &A, double *rng, int slot, int it)
 {
     const int q = threadIdx.x;
@@ -692,7 +693,7 @@ __device__ __forceinline__ void refill_rng(const KArgs &A, double *rng, int slot
             draw4(A.seed, slot, A.gen, (uint64_t)(it + q), 1, u);
             rotation(u, Rm);
         }
-        double *o = rng + 12 * (((it >> 3) & 1) * 8 + q);
+        double *o = rng + 12 * q;
         for (int c = 0; c < 9; ++c) o[c] = Rm[c];
         draw4(A.seed, slot, A.gen, (uint64_t)(it + q), 0, u);
         o[9] = -log(u[0]);   // exponential variate of the holding time
@@ -702,7 +703,7 @@ __device__ __forceinline__ void refill_rng(const KArgs &A, double *rng, int slot
 
 __device__ __forceinline__ const double *rng_slot(const double *rng, int it)
 {
-    return rng + 12 * (((it >> 3) & 1) * 8 + (it & 7));
+    return rng + 12 * (it & 7);
 }
 
 // Orders the LDS accesses of one wavefront (its lanes exchange data through
@@ -896,9 +897,9 @@ __device__ void accept_move(const KArgs &A, double *lds, int k, const double rol
     const double irho = uni(1.0 / wrow[kl]);
     {
         const int r0 = up64(6 + 4 * n);
-        const int q0 = r0 + 4 * n, q1 = q0 + 3, q2 = q1 + n * n, q3 = q2 + n * K;
+        const int q0 = r0 + 4 * n, q1 = q0 + 3, q2 = q1 + n * n;
         const float inv_n = 1.0f / (float)n, inv_K = 1.0f / (float)K;
-        for (int t = tid; t < q3; t += NT) {
+        for (int t = tid; t < q2; t += NT) {
             if (t < r0) {
                 if (t < 6) {
                     const double v = seq_sum(kp + t * np, np);
@@ -918,15 +919,28 @@ __device__ void accept_move(const KArgs &A, double *lds, int k, const double rol
                 dphi[k * L.dld + c * ns + j] = vrow[(c + 1) * ns + j];
             } else if (t < q1) {
                 pos[3 * k + t - q0] = rnew[t - q0];
-            } else if (t < q2) {
+            } else {
                 const int u = t - q1, j = row_of(u, inv_n), i = u - j * n;
                 const double f = (wrow[i] - (i == kl ? 1.0 : 0.0)) * irho;
                 inv[j * ns + i] -= colk[j] * f;
-            } else {
-                const int u = t - q2, i = row_of(u, inv_K), mu = u - i * K;
-                const double f = (wrow[i] - (i == kl ? 1.0 : 0.0)) * irho;
-                Y[(i0 + i) * Kp + mu] -= Yk[mu] * f;
             }
+        }
+        // the spin's rows of Y, four elements per thread in flight
+        const int nY = n * K;
+        for (int u0 = tid; u0 < nY; u0 += 4 * NT) {
+            double y[4], yk[4], f[4];
+            int at[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int u = min(u0 + v * NT, nY - 1), i = row_of(u, inv_K), mu = u - i * K;
+                at[v] = (i0 + i) * Kp + mu;
+                y[v] = Y[at[v]];
+                yk[v] = Yk[mu];
+                f[v] = (wrow[i] - (i == kl ? 1.0 : 0.0)) * irho;
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (u0 + v * NT < nY) Y[at[v]] = y[v] - yk[v] * f[v];
         }
     }
 }
@@ -999,7 +1013,7 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
                                        A.rho_out ? A.rho_out + (size_t)slot * M : nullptr,
                                        A.k_out ? A.k_out + (size_t)slot * M : nullptr, acc, true);
         double v[4] = {acc[0], acc[1], acc[2], part};
-        block_sum<4>(v, red);
+        block_sum<4>(v, xs);
         if (tid == 0 && A.diag_out) {
             double *d = A.diag_out + (size_t)slot * LRDMC_NDIAG;
             const double Va = V + 0.5 * (v[1] - LAP);
@@ -1280,7 +1294,7 @@ int fail(lrdmc_ctx *ctx, int code, const std::string &msg)
 
 // LDS layout of one walker.  The electron batch of the generation start grows until the block reaches
 // `target` bytes (or all electrons fit), never below one electron.
-Layout make_layout(int N, int ns, int K, int Kp, int M, int n_nuc, size_t target)
+Layout make_layout(int N, int ns, int K, int Kp, int M, int n_nuc, int NT, size_t target)
 {
     Layout L{};
     int o = 0;
@@ -1293,17 +1307,20 @@ Layout make_layout(int N, int ns, int K, int Kp, int M, int n_nuc, size_t target
     L.gD = take(4 * N);
     L.gJ = take(4 * N);
     L.Jo = take(N);
-    L.red = take(64);
-    L.sc = take(32);
-    L.rng = take(16 * 12);
-    L.xs = take(kMaxThreads);
+    L.red = take(16);
+    L.sc = take(8);
+    L.rng = take(8 * 12);
     const int U = o;
-    // move-loop view
+    // move-loop view.  The prefix sums and weights live from the table to
+    // the search, which some wavefronts finish while others already write
+    // the first-phase temporaries of the accepted move; only the second-phase
+    // outputs (vrow, wrow) may share their space.
     int q = U;
-    L.T = q; q += M;
+    L.xs = q; q += NT;
+    L.T = q; q += std::max(M, 6 * ns);
+    L.vrow = L.T;
+    L.wrow = L.T + 5 * ns;
     L.bv = q; q += 5 * Kp;
-    L.vrow = q; q += 5 * ns;
-    L.wrow = q; q += ns;
     L.colk = q; q += ns;
     L.Yk = q; q += Kp;
     L.dq = q; q += 4 * ns;
@@ -1639,9 +1656,7 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
         }
     c->v_nn = vnn;
     c->nt = std::min(kMaxThreads, std::max(64, ((c->M / 2 + 63) / 64) * 64));
-    // Stage the occupied MO block in LDS only for small walker states; larger
-    // ones read it through the caches so that more walkers share a CU.
-    c->L = make_layout(N, ns, K, c->Kp, c->M, sys->n_nuc, prm->refresh > 1 ? 0 : 38 * 1024);
+    c->L = make_layout(N, ns, K, c->Kp, c->M, sys->n_nuc, c->nt, prm->refresh > 1 ? 0 : 38 * 1024);
     c->lds_bytes = sizeof(double) * (size_t)c->L.total;
     c->state_len = (c->L.Jo + N - c->L.Y) + 2;
 
