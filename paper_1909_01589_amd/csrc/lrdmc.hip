@@ -76,17 +76,37 @@ struct Layout {
     int total;
 };
 
+// Basis functions are ordered group by group (s, then p x y z, then the five
+// d), groups by nucleus and exponent.  A chain is a run of groups on one
+// nucleus whose exponents grow by one constant ratio beta (see basis_dot2).
+struct ChainDesc {
+    double R[3];                 // nucleus
+    double alpha0;               // exponent of the first group
+    unsigned long long flags;    // 3 bits per group: s, p, d shell present
+    int len;                     // groups (at most 21)
+    int code;                    // 1, 2, 3: beta = 2, 2.5, 3; 0: single group
+    int mu0;                     // first basis function
+    int pad[3];
+};
+static_assert(sizeof(ChainDesc) == 64, "chain descriptor size");
+
+// One basis function: exponent, centre, angular momentum and component.
+struct FnDesc {
+    double alpha;
+    double R[3];
+    int l, comp;
+    int pad[2];
+};
+static_assert(sizeof(FnDesc) == 48, "basis function descriptor size");
+
 struct KArgs {
     // system
-    int N, n_up, n_dn, ns, K, Kp, n_orb, n_nuc, n_grp, n_heavy, M;
+    int N, n_up, n_dn, ns, K, Kp, n_nuc, n_heavy, M;
     const double *Znuc, *Rnuc;     // [n_nuc], [n_nuc][3]
-    const int *heavy;              // [n_heavy] indices of nuclei with Z >= z_heavy
-    const int *grp_nuc;            // [n_grp]
-    const double *grp_alpha;       // [n_grp]
-    const int *grp_off;            // [n_grp][3] first basis index of the s, p, d shell, -1 if none
-    const int *fn_info;            // [K]: group | l << 16 | component << 20
+    const double *Rheavy;          // [n_heavy][3] nuclei with Z >= z_heavy
+    const FnDesc *fns;             // [K]
     int n_chain;
-    const int *chain;              // [n_chain][3]: first group, length, step code (see basis_dot)
+    const ChainDesc *chains;       // [n_chain]
     const double *moT;             // [ns][K]: occupied MO coefficients, orbital-major
     double b_ee, b_en, v_nn;
     // lattice
@@ -120,6 +140,14 @@ __device__ __forceinline__ void report(int *err, int code, int slot)
 
 __device__ __forceinline__ int spin_of(const KArgs &A, int i) { return i < A.n_up ? 0 : 1; }
 
+// The system tables are read-only during a launch: reading them through the
+// constant address space lets uniform indices use scalar loads.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *cst(const T *p)
+{
+    return (const __attribute__((address_space(4))) T *)p;
+}
+
 // Values that every lane of the workgroup holds identically are moved to
 // scalar registers (they are read from LDS, so the compiler cannot prove it).
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -138,12 +166,12 @@ __device__ __forceinline__ double uni(double x)
 // lap g = (4 alpha^2 d^2 - (6 + 4 l) alpha) P e.
 __device__ __forceinline__ void basis_fn_full(const KArgs &A, int mu, const double r[3], double *bv)
 {
-    const int K = A.Kp, info = A.fn_info[mu];
-    const int g = info & 0xffff, l = (info >> 16) & 0xf, c = info >> 20;
-    const double *Rn = A.Rnuc + 3 * A.grp_nuc[g];
-    const double d[3] = {r[0] - Rn[0], r[1] - Rn[1], r[2] - Rn[2]};
+    const int K = A.Kp;
+    const FnDesc F = A.fns[mu];
+    const int l = F.l, c = F.comp;
+    const double d[3] = {r[0] - F.R[0], r[1] - F.R[1], r[2] - F.R[2]};
     const double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    const double al = A.grp_alpha[g];
+    const double al = F.alpha;
     const double e = exp(-al * d2);
     double P, dP[3];
     if (l == 0) {
@@ -172,83 +200,48 @@ __device__ __forceinline__ void basis_fn_full(const KArgs &A, int mu, const doub
 // below 1e-300 (whose powers vanish anyway) map to 0.
 __device__ __forceinline__ double sqrt_unit(double e);
 
-// sum_mu g_mu(r) y[mu]: the determinant ratio of moving an electron whose
-// orbital-projected inverse row is y to r.  Groups come in chains on one
-// nucleus with exponents alpha_{q+1} = beta alpha_q; for beta = 2, 2.5 and 3
-// the exponential of the next group is a power of the current one
-// (e^2, e^2 sqrt(e), e^3), so a chain costs one exp; other chains (code 0)
-// take one exp per group.
-__device__ __forceinline__ double basis_dot(const KArgs &A, const double r[3], const double *y)
-{
-    double acc = 0.0;
-    for (int ch = 0; ch < A.n_chain; ++ch) {
-        const int g0 = A.chain[3 * ch], len = A.chain[3 * ch + 1], code = A.chain[3 * ch + 2];
-        const double *Rn = A.Rnuc + 3 * A.grp_nuc[g0];
-        const double dx = r[0] - Rn[0], dy = r[1] - Rn[1], dz = r[2] - Rn[2];
-        const double d2 = dx * dx + dy * dy + dz * dz;
-        const double pd[5] = {dx * dy, dy * dz, dz * dx, dx * dx - dy * dy, 2.0 * dz * dz - dx * dx - dy * dy};
-        double e = exp(-A.grp_alpha[g0] * d2);
-        for (int q = 0; q < len; ++q) {
-            const int g = g0 + q;
-            const int *off = A.grp_off + 3 * g;
-            double poly = 0.0;
-            if (off[0] >= 0) poly += y[off[0]];
-            if (off[1] >= 0) {
-                const double *yp = y + off[1];
-                poly += dx * yp[0] + dy * yp[1] + dz * yp[2];
-            }
-            if (off[2] >= 0) {
-                const double *yd = y + off[2];
-                poly += pd[0] * yd[0] + pd[1] * yd[1] + pd[2] * yd[2] + pd[3] * yd[3] + pd[4] * yd[4];
-            }
-            acc += e * poly;
-            if (q + 1 < len) {
-                if (code == 3) e = e * e * e;
-                else if (code == 2) e = (e * e) * sqrt_unit(e);
-                else if (code == 1) e = e * e;
-                else e = exp(-A.grp_alpha[g + 1] * d2);
-            }
-        }
-    }
-    return acc;
-}
-
-// basis_dot for the two points of a +/- move pair (same electron, so the
-// same row y): the chains of both points run side by side and share the loads.
+// sum_mu g_mu(r) y[mu] at the two points ra, rb of a +/- move pair of one
+// electron (y: its orbital-projected inverse row): the determinant ratios of
+// the two moves.  Along a chain the exponential of the next group is a power
+// of the current one (e^2, e^2 sqrt(e), e^3 for beta = 2, 2.5, 3), so a chain
+// costs one exp per point; both points share the loads of y.
 __device__ __forceinline__ void basis_dot2(const KArgs &A, const double ra[3], const double rb[3],
                                            const double *y, double &out_a, double &out_b)
 {
     double acc_a = 0.0, acc_b = 0.0;
+    const auto *chains = cst(A.chains);
     for (int ch = 0; ch < A.n_chain; ++ch) {
-        const int g0 = A.chain[3 * ch], len = A.chain[3 * ch + 1], code = A.chain[3 * ch + 2];
-        const double *Rn = A.Rnuc + 3 * A.grp_nuc[g0];
-        const double ax = ra[0] - Rn[0], ay = ra[1] - Rn[1], az = ra[2] - Rn[2];
-        const double bx = rb[0] - Rn[0], by = rb[1] - Rn[1], bz = rb[2] - Rn[2];
+        const auto *D = chains + ch;
+        const double ax = ra[0] - D->R[0], ay = ra[1] - D->R[1], az = ra[2] - D->R[2];
+        const double bx = rb[0] - D->R[0], by = rb[1] - D->R[1], bz = rb[2] - D->R[2];
         const double a2 = ax * ax + ay * ay + az * az, b2 = bx * bx + by * by + bz * bz;
-        const double al0 = A.grp_alpha[g0];
+        const double al0 = D->alpha0;
         double ea = exp(-al0 * a2), eb = exp(-al0 * b2);
+        const unsigned long long fl = D->flags;
+        const int len = D->len, code = D->code;
+        const double *yq = y + D->mu0;
         for (int q = 0; q < len; ++q) {
-            const int g = g0 + q;
-            const int *off = A.grp_off + 3 * g;
+            const int f = (int)(fl >> (3 * q)) & 7;
             double pa = 0.0, pb = 0.0;
-            if (off[0] >= 0) {
-                const double ys = y[off[0]];
+            if (f & 1) {
+                const double ys = yq[0];
                 pa += ys;
                 pb += ys;
+                yq += 1;
             }
-            if (off[1] >= 0) {
-                const double *yp = y + off[1];
-                const double y0 = yp[0], y1 = yp[1], y2 = yp[2];
+            if (f & 2) {
+                const double y0 = yq[0], y1 = yq[1], y2 = yq[2];
                 pa += ax * y0 + ay * y1 + az * y2;
                 pb += bx * y0 + by * y1 + bz * y2;
+                yq += 3;
             }
-            if (off[2] >= 0) {
-                const double *yd = y + off[2];
-                const double y0 = yd[0], y1 = yd[1], y2 = yd[2], y3 = yd[3], y4 = yd[4];
+            if (f & 4) {
+                const double y0 = yq[0], y1 = yq[1], y2 = yq[2], y3 = yq[3], y4 = yq[4];
                 pa += ax * ay * y0 + ay * az * y1 + az * ax * y2 + (ax * ax - ay * ay) * y3 +
                       (2.0 * az * az - ax * ax - ay * ay) * y4;
                 pb += bx * by * y0 + by * bz * y1 + bz * bx * y2 + (bx * bx - by * by) * y3 +
                       (2.0 * bz * bz - bx * bx - by * by) * y4;
+                yq += 5;
             }
             acc_a += ea * pa;
             acc_b += eb * pb;
@@ -259,13 +252,9 @@ __device__ __forceinline__ void basis_dot2(const KArgs &A, const double ra[3], c
                 } else if (code == 2) {
                     ea = (ea * ea) * sqrt_unit(ea);
                     eb = (eb * eb) * sqrt_unit(eb);
-                } else if (code == 1) {
+                } else {
                     ea = ea * ea;
                     eb = eb * eb;
-                } else {
-                    const double al = A.grp_alpha[g + 1];
-                    ea = exp(-al * a2);
-                    eb = exp(-al * b2);
                 }
             }
         }
@@ -278,30 +267,14 @@ __device__ __forceinline__ void basis_dot2(const KArgs &A, const double ra[3], c
 __device__ __forceinline__ double p_switch(const KArgs &A, const double x[3])
 {
     double best = 0.0;
+    const auto *Rh = cst(A.Rheavy);
     for (int h = 0; h < A.n_heavy; ++h) {
-        const double *R = A.Rnuc + 3 * A.heavy[h];
+        const auto *R = Rh + 3 * h;
         const double dx = x[0] - R[0], dy = x[1] - R[1], dz = x[2] - R[2];
         const double d2 = dx * dx + dy * dy + dz * dz;
         if (h == 0 || d2 < best) best = d2;
     }
     return exp(-best * A.inv_2rc2);
-}
-
-// Displaced position and hopping coefficient of move m.
-__device__ __forceinline__ double move_geometry(const KArgs &A, const double *pos, const double *Rm,
-                                                int m, double rp[3])
-{
-    const int i = m / 12, g = (m / 6) & 1, dir = m % 6, ax = dir >> 1;
-    const double h = g ? A.ap : A.a;
-    const double t = (dir & 1) ? -h : h;
-    const double e[3] = {Rm[ax], Rm[3 + ax], Rm[6 + ax]};
-    double mid[3];
-    for (int c = 0; c < 3; ++c) {
-        rp[c] = pos[3 * i + c] + t * e[c];
-        mid[c] = pos[3 * i + c] + (0.5 * t) * e[c];
-    }
-    const double p = p_switch(A, mid);
-    return g ? (1.0 - p) * A.inv_ap2 : p * A.inv_a2;
 }
 
 // -- per-walker state ------------------------------------------------------
@@ -420,35 +393,8 @@ __device__ __forceinline__ PairD pade_d(double c, double b, double d2)
     return p;
 }
 
-// Jastrow terms containing electron i when it sits at r (others fixed).
-// Four partners per step with independent accumulators; the partner j = i
-// enters with weight 0.
-__device__ __forceinline__ double jastrow_point(const KArgs &A, const double *pos, int i, const double r[3])
-{
-    const bool up = i < A.n_up;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    auto cw = [&](int j) { return j == i ? 0.0 : (((j < A.n_up) == up) ? 0.25 : 0.5); };
-    auto d2 = [&](int j) {
-        const double dx = r[0] - pos[3 * j], dy = r[1] - pos[3 * j + 1], dz = r[2] - pos[3 * j + 2];
-        return dx * dx + dy * dy + dz * dz;
-    };
-    int j = 0;
-    for (; j + 3 < A.N; j += 4) {
-        a0 += pade_u(cw(j), A.b_ee, d2(j));
-        a1 += pade_u(cw(j + 1), A.b_ee, d2(j + 1));
-        a2 += pade_u(cw(j + 2), A.b_ee, d2(j + 2));
-        a3 += pade_u(cw(j + 3), A.b_ee, d2(j + 3));
-    }
-    for (; j < A.N; ++j) a0 += pade_u(cw(j), A.b_ee, d2(j));
-    for (int I = 0; I < A.n_nuc; ++I) {
-        const double *R = A.Rnuc + 3 * I;
-        const double dx = r[0] - R[0], dy = r[1] - R[1], dz = r[2] - R[2];
-        a1 += pade_u(-A.Znuc[I], A.b_en, dx * dx + dy * dy + dz * dz);
-    }
-    return (a0 + a1) + (a2 + a3);
-}
-
-// jastrow_point for the two points of a +/- move pair of electron i.
+// Jastrow terms containing electron i when it sits at ra and at rb (the two
+// points of a +/- move pair; the other electrons fixed).
 __device__ __forceinline__ void jastrow_point2(const KArgs &A, const double *pos, int i, const double ra[3],
                                                const double rb[3], double &out_a, double &out_b)
 {
@@ -478,8 +424,8 @@ __device__ __forceinline__ void jastrow_point2(const KArgs &A, const double *pos
         b0 += pade_u(c0, A.b_ee, dx * dx + dy * dy + dz * dz);
     }
     for (int I = 0; I < A.n_nuc; ++I) {
-        const double *R = A.Rnuc + 3 * I;
-        const double c = -A.Znuc[I];
+        const auto *R = cst(A.Rnuc) + 3 * I;
+        const double c = -cst(A.Znuc)[I];
         double dx = ra[0] - R[0], dy = ra[1] - R[1], dz = ra[2] - R[2];
         a1 += pade_u(c, A.b_en, dx * dx + dy * dy + dz * dz);
         dx = rb[0] - R[0]; dy = rb[1] - R[1]; dz = rb[2] - R[2];
@@ -1245,12 +1191,12 @@ std::string g_error;  // last failure without a context
 }  // namespace
 
 struct lrdmc_ctx {
-    int W = 0, N = 0, n_up = 0, n_dn = 0, ns = 0, K = 0, Kp = 0, n_orb = 0, n_nuc = 0, n_grp = 0,
-        n_heavy = 0, M = 0;
+    int W = 0, N = 0, n_up = 0, n_dn = 0, ns = 0, K = 0, Kp = 0, n_nuc = 0, n_heavy = 0, M = 0;
     double b_ee = 0, b_en = 0, v_nn = 0;
     lrdmc_params prm{};
-    double *d_Z = nullptr, *d_R = nullptr, *d_mo = nullptr, *d_galpha = nullptr;
-    int *d_heavy = nullptr, *d_gnuc = nullptr, *d_goff = nullptr, *d_chain = nullptr, *d_fn = nullptr;
+    double *d_Z = nullptr, *d_R = nullptr, *d_mo = nullptr, *d_Rheavy = nullptr;
+    FnDesc *d_fn = nullptr;
+    ChainDesc *d_chain = nullptr;
     int n_chain = 0;
     double *d_pos[2] = {nullptr, nullptr};
     int cur = 0;
@@ -1347,10 +1293,9 @@ KArgs base_args(const lrdmc_ctx *c)
 {
     KArgs A{};
     A.N = c->N; A.n_up = c->n_up; A.n_dn = c->n_dn; A.ns = c->ns; A.K = c->K; A.Kp = c->Kp;
-    A.n_orb = c->n_orb; A.n_nuc = c->n_nuc; A.n_grp = c->n_grp; A.n_heavy = c->n_heavy; A.M = c->M;
-    A.Znuc = c->d_Z; A.Rnuc = c->d_R; A.heavy = c->d_heavy; A.grp_nuc = c->d_gnuc;
-    A.grp_alpha = c->d_galpha; A.grp_off = c->d_goff; A.moT = c->d_mo;
-    A.n_chain = c->n_chain; A.chain = c->d_chain; A.fn_info = c->d_fn;
+    A.n_nuc = c->n_nuc; A.n_heavy = c->n_heavy; A.M = c->M;
+    A.Znuc = c->d_Z; A.Rnuc = c->d_R; A.Rheavy = c->d_Rheavy; A.moT = c->d_mo;
+    A.n_chain = c->n_chain; A.chains = c->d_chain; A.fns = c->d_fn;
     A.b_ee = c->b_ee; A.b_en = c->b_en; A.v_nn = c->v_nn;
     A.a = c->prm.a; A.ap = c->prm.a_prime;
     A.inv_a2 = 1.0 / (c->prm.a * c->prm.a);
@@ -1573,47 +1518,58 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
         if (sys->Z[I] >= prm->z_heavy) heavy.push_back(I);
     if (heavy.empty()) return fail(nullptr, LRDMC_EINVAL, "lrdmc_create: no nucleus with Z >= z_heavy");
 
-    // Group shells that share nucleus and exponent: one exponential serves them.
-    std::vector<int> gnuc, goff;
-    std::vector<double> galpha;
-    int mu = 0;
-    for (int q = 0; q < sys->n_shell; ++q) {
-        const int l = sys->shell_l[q], I = sys->shell_nuc[q];
-        const double al = sys->shell_alpha[q];
-        int gi = -1;
-        for (size_t g = 0; g < gnuc.size(); ++g)
-            if (gnuc[g] == I && galpha[g] == al && goff[3 * g + l] < 0) { gi = (int)g; break; }
-        if (gi < 0) {
-            gi = (int)gnuc.size();
-            gnuc.push_back(I);
-            galpha.push_back(al);
-            goff.insert(goff.end(), {-1, -1, -1});
-        }
-        goff[3 * gi + l] = mu;
-        mu += 2 * l + 1;
-    }
-
-    // Order groups by nucleus and exponent; cut them into chains whose
-    // exponent ratio is one constant beta (step code 1, 2, 3 for beta = 2,
-    // 2.5, 3; 0 for anything else).
+    // Group shells that share nucleus and exponent (one s, p and d shell at
+    // most): one exponential serves the group.  Groups are sorted by nucleus
+    // and exponent and cut into chains whose exponent ratio is one constant
+    // beta (step code 1, 2, 3 for beta = 2, 2.5, 3; other groups stand alone),
+    // and the basis functions are renumbered group by group (s, p x y z, the
+    // five d) so that a chain reads its coefficients in one sweep.
+    struct Grp { int nuc; double alpha; int shell[3]; };
+    std::vector<Grp> groups;
+    std::vector<int> shell_mu(sys->n_shell);   // first function of each shell, input numbering
     {
-        std::vector<int> order(gnuc.size());
-        for (size_t g = 0; g < order.size(); ++g) order[g] = (int)g;
-        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-            return gnuc[x] != gnuc[y] ? gnuc[x] < gnuc[y] : galpha[x] < galpha[y];
-        });
-        std::vector<int> n2, o2;
-        std::vector<double> a2;
-        for (int g : order) {
-            n2.push_back(gnuc[g]);
-            a2.push_back(galpha[g]);
-            o2.insert(o2.end(), {goff[3 * g], goff[3 * g + 1], goff[3 * g + 2]});
+        int mu = 0;
+        for (int q = 0; q < sys->n_shell; ++q) {
+            const int l = sys->shell_l[q], I = sys->shell_nuc[q];
+            const double al = sys->shell_alpha[q];
+            shell_mu[q] = mu;
+            mu += 2 * l + 1;
+            int gi = -1;
+            for (size_t g = 0; g < groups.size(); ++g)
+                if (groups[g].nuc == I && groups[g].alpha == al && groups[g].shell[l] < 0) { gi = (int)g; break; }
+            if (gi < 0) {
+                gi = (int)groups.size();
+                groups.push_back({I, al, {-1, -1, -1}});
+            }
+            groups[gi].shell[l] = q;
         }
-        gnuc.swap(n2);
-        galpha.swap(a2);
-        goff.swap(o2);
     }
-    std::vector<int> chains;
+    std::stable_sort(groups.begin(), groups.end(), [](const Grp &x, const Grp &y) {
+        return x.nuc != y.nuc ? x.nuc < y.nuc : x.alpha < y.alpha;
+    });
+    std::vector<int> perm(K);            // input function -> renumbered function
+    std::vector<FnDesc> fns(K);
+    std::vector<int> grp_mu(groups.size());
+    {
+        int mu = 0;
+        for (size_t g = 0; g < groups.size(); ++g) {
+            grp_mu[g] = mu;
+            for (int l = 0; l < 3; ++l) {
+                const int q = groups[g].shell[l];
+                if (q < 0) continue;
+                for (int cmp = 0; cmp < 2 * l + 1; ++cmp, ++mu) {
+                    perm[shell_mu[q] + cmp] = mu;
+                    FnDesc &F = fns[mu];
+                    F = FnDesc{};
+                    F.alpha = groups[g].alpha;
+                    for (int x = 0; x < 3; ++x) F.R[x] = sys->R[3 * groups[g].nuc + x];
+                    F.l = l;
+                    F.comp = cmp;
+                }
+            }
+        }
+    }
+    std::vector<ChainDesc> chains;
     {
         auto code_of = [](double ratio) {
             const double betas[3] = {2.0, 2.5, 3.0};
@@ -1622,31 +1578,38 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
             return 0;
         };
         size_t g = 0;
-        while (g < gnuc.size()) {
+        while (g < groups.size()) {
             size_t e = g + 1;
             int code = 0;
-            if (e < gnuc.size() && gnuc[e] == gnuc[g] && galpha[g] > 0.0) code = code_of(galpha[e] / galpha[g]);
+            if (e < groups.size() && groups[e].nuc == groups[g].nuc && groups[g].alpha > 0.0)
+                code = code_of(groups[e].alpha / groups[g].alpha);
             if (code)
-                while (e < gnuc.size() && gnuc[e] == gnuc[g] && code_of(galpha[e] / galpha[e - 1]) == code) ++e;
-            chains.insert(chains.end(), {(int)g, (int)(e - g), code});
+                while (e < groups.size() && e - g < 21 && groups[e].nuc == groups[g].nuc &&
+                       code_of(groups[e].alpha / groups[e - 1].alpha) == code)
+                    ++e;
+            if (e - g == 1) code = 0;
+            ChainDesc D{};
+            for (int x = 0; x < 3; ++x) D.R[x] = sys->R[3 * groups[g].nuc + x];
+            D.alpha0 = groups[g].alpha;
+            for (size_t q = g; q < e; ++q)
+                for (int l = 0; l < 3; ++l)
+                    if (groups[q].shell[l] >= 0) D.flags |= 1ull << (3 * (q - g) + l);
+            D.len = (int)(e - g);
+            D.code = code;
+            D.mu0 = grp_mu[g];
+            chains.push_back(D);
             g = e;
         }
     }
-
-    // Per basis function: its group (after sorting), l and component.
-    std::vector<int> fn_info(K);
-    for (size_t g = 0; g < gnuc.size(); ++g)
-        for (int l = 0; l < 3; ++l) {
-            const int o = goff[3 * g + l];
-            if (o < 0) continue;
-            for (int cmp = 0; cmp < 2 * l + 1; ++cmp) fn_info[o + cmp] = (int)g | (l << 16) | (cmp << 20);
-        }
+    std::vector<double> Rheavy;
+    for (int I : heavy)
+        for (int x = 0; x < 3; ++x) Rheavy.push_back(sys->R[3 * I + x]);
 
     lrdmc_ctx *c = new (std::nothrow) lrdmc_ctx();
     if (!c) return fail(nullptr, LRDMC_ENOMEM, "lrdmc_create: host allocation");
     c->W = n_walkers; c->N = N; c->n_up = sys->n_up; c->n_dn = sys->n_dn; c->ns = ns; c->K = K;
-    c->Kp = K | 1; c->n_orb = sys->n_orb; c->n_nuc = sys->n_nuc; c->n_grp = (int)gnuc.size();
-    c->n_heavy = (int)heavy.size(); c->M = 12 * N; c->n_chain = (int)chains.size() / 3; c->b_ee = sys->b_ee; c->b_en = sys->b_en; c->prm = *prm;
+    c->Kp = K | 1; c->n_nuc = sys->n_nuc;
+    c->n_heavy = (int)heavy.size(); c->M = 12 * N; c->n_chain = (int)chains.size(); c->b_ee = sys->b_ee; c->b_en = sys->b_en; c->prm = *prm;
     double vnn = 0.0;
     for (int I = 0; I < sys->n_nuc; ++I)
         for (int J = I + 1; J < sys->n_nuc; ++J) {
@@ -1676,19 +1639,16 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
         return cleanup(LRDMC_EDEVICE, "lrdmc_create: cannot raise the LDS limit");
 
     const size_t W = n_walkers, s3 = 3 * (size_t)N;
-    std::vector<double> moT((size_t)ns * K);   // occupied block, orbital-major
+    std::vector<double> moT((size_t)ns * K);   // occupied block, orbital-major, renumbered functions
     for (int j = 0; j < ns; ++j)
-        for (int mu = 0; mu < K; ++mu) moT[(size_t)j * K + mu] = sys->mo[(size_t)mu * sys->n_orb + j];
+        for (int mu = 0; mu < K; ++mu) moT[(size_t)j * K + perm[mu]] = sys->mo[(size_t)mu * sys->n_orb + j];
     auto alloc = [&](void **p, size_t bytes) { return hipMalloc(p, bytes) == hipSuccess; };
     bool ok = alloc((void **)&c->d_Z, sizeof(double) * sys->n_nuc) &&
               alloc((void **)&c->d_R, sizeof(double) * 3 * sys->n_nuc) &&
               alloc((void **)&c->d_mo, sizeof(double) * K * ns) &&
-              alloc((void **)&c->d_galpha, sizeof(double) * gnuc.size()) &&
-              alloc((void **)&c->d_gnuc, sizeof(int) * gnuc.size()) &&
-              alloc((void **)&c->d_goff, sizeof(int) * goff.size()) &&
-              alloc((void **)&c->d_chain, sizeof(int) * chains.size()) &&
-              alloc((void **)&c->d_fn, sizeof(int) * K) &&
-              alloc((void **)&c->d_heavy, sizeof(int) * heavy.size()) &&
+              alloc((void **)&c->d_chain, sizeof(ChainDesc) * chains.size()) &&
+              alloc((void **)&c->d_fn, sizeof(FnDesc) * K) &&
+              alloc((void **)&c->d_Rheavy, sizeof(double) * Rheavy.size()) &&
               alloc((void **)&c->d_pos[0], sizeof(double) * W * s3) &&
               alloc((void **)&c->d_pos[1], sizeof(double) * W * s3) &&
               (prm->refresh <= 1 || (alloc((void **)&c->d_state[0], sizeof(double) * W * c->state_len) &&
@@ -1700,12 +1660,9 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
     ok = hipMemcpy(c->d_Z, sys->Z, sizeof(double) * sys->n_nuc, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(c->d_R, sys->R, sizeof(double) * 3 * sys->n_nuc, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(c->d_mo, moT.data(), sizeof(double) * K * ns, hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(c->d_galpha, galpha.data(), sizeof(double) * gnuc.size(), hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(c->d_gnuc, gnuc.data(), sizeof(int) * gnuc.size(), hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(c->d_goff, goff.data(), sizeof(int) * goff.size(), hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(c->d_chain, chains.data(), sizeof(int) * chains.size(), hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(c->d_fn, fn_info.data(), sizeof(int) * K, hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(c->d_heavy, heavy.data(), sizeof(int) * heavy.size(), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(c->d_chain, chains.data(), sizeof(ChainDesc) * chains.size(), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(c->d_fn, fns.data(), sizeof(FnDesc) * K, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(c->d_Rheavy, Rheavy.data(), sizeof(double) * Rheavy.size(), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemset(c->d_err, 0, 2 * sizeof(int)) == hipSuccess &&
          hipMemset(c->d_logw, 0, sizeof(double) * W) == hipSuccess &&
          hipMemset(c->d_el, 0, sizeof(double) * W) == hipSuccess &&
@@ -1860,7 +1817,7 @@ const char *lrdmc_last_error(const lrdmc_ctx *c) { return c ? c->err.c_str() : g
 void lrdmc_destroy(lrdmc_ctx *c)
 {
     if (!c) return;
-    void *ptrs[] = {c->d_Z,    c->d_R,    c->d_mo,   c->d_galpha, c->d_gnuc, c->d_goff, c->d_chain, c->d_fn, c->d_heavy, c->d_pos[0], c->d_state[0], c->d_state[1],
+    void *ptrs[] = {c->d_Z,      c->d_R,        c->d_mo,       c->d_chain,    c->d_fn,   c->d_Rheavy, c->d_pos[0], c->d_state[0], c->d_state[1],
                     c->d_pos[1], c->d_logw, c->d_el, c->d_cw,     c->d_nmov, c->d_idx,  c->d_err};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
