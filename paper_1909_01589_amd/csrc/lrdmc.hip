@@ -49,17 +49,17 @@ struct Layout {
     int pos;    // [N][3]            positions
     int Y;      // [N][Kp]           Y[i][mu] = sum_j C[mu][j] Ainv_sigma(i)[j][i_sigma]
     int Ainv;   // [2][ns][ns]       Ainv_sigma[j][i]
-    int dphi;   // [N][dld]          grad (x,y,z) and Laplacian of phi_j at r_i: [i*dld + c*ns + j]
-    int dld;    // 4 ns + 1 (odd: electrons on different LDS banks)
+    int dld;    // row length of the derivative rows (in the walker's HBM state, see KArgs)
     int gD;     // [N][4]            grad D/D (3) and lap D/D of electron i
     int gJ;     // [N][4]            grad J (3) and lap J of electron i
     int Jo;     // [N]               Jastrow terms that contain electron i
     int red;    // [16]              reduction scratch
     int sc;     // [8]               block scalars
     int rng;    // [8][12]           rotations, -ln u1 and u2 of eight iterations
-    // move-loop view of U
+    // move-loop view of U: the weights and their prefix sums (table to search),
+    // then the accepted-move temporaries
     int xs;     // [NT]              per-thread inclusive prefix of T within its wavefront
-    int T;      // [M]               heat-bath weights of the moves (shared with vrow, wrow)
+    int T;      // [M]               heat-bath weights of the moves
     int bv;     // [5][K]            basis value, gradient, Laplacian at one point
     int vrow;   // [5][ns]           orbital value, gradient, Laplacian at one point
     int wrow;   // [ns]              w_i = phi(r_new) . Ainv[:, i]
@@ -119,8 +119,12 @@ struct KArgs {
     const double *pos_in;
     const int *idx_in;             // gather on load, or nullptr
     const double *state_in;        // walker state blobs to resume from, or nullptr (recompute)
-    double *state_out;             // walker state blobs at the end of the projection
-    int state_len;                 // doubles per blob: LDS [Y, Jo + N) plus E_L and V
+    double *state_out;             // walker state blobs: derivative rows during the projection,
+                                   // the rest at its end
+    int state_len;                 // doubles per blob: LDS [Y, Jo + N), E_L, V, derivative rows
+    int dphi_at;                   // offset of the derivative rows in a blob: [N][dld], row i holds
+                                   // grad (x, y, z) and Laplacian of phi_j at r_i at c * ns + j
+    int save_state;                // store the LDS part, E_L and V at the end
     double *pos_out, *logw, *el;
     int *nmov;
     int *err;
@@ -521,12 +525,13 @@ __device__ __forceinline__ double psi_lap_term(const double *d, const double *j)
 // Gauss-Jordan inversion with partial pivoting, Y = C Ainv, determinant and
 // Jastrow derivatives, local energy.  Returns an error code (uniform);
 // EL, LAP (sum_i lap_i Psi/Psi) and V reach every thread.
-__device__ int walker_setup(const KArgs &A, double *lds, int *sflag, double &EL, double &LAP, double &V)
+__device__ int walker_setup(const KArgs &A, double *lds, double *dphi, int *sflag, double &EL, double &LAP,
+                            double &V)
 {
     const Layout &L = A.L;
     const int N = A.N, ns = A.ns, K = A.K, Kp = A.Kp, tid = threadIdx.x, NT = blockDim.x;
     double *pos = lds + L.pos, *G = lds + L.G, *bvb = lds + L.bvb;
-    double *dphi = lds + L.dphi, *Ainv = lds + L.Ainv;
+    double *Ainv = lds + L.Ainv;
     const int two = 2 * ns;
 
     // right halves = identity
@@ -767,14 +772,15 @@ __device__ __forceinline__ double seq_dot(const double *x, const double *y, int 
 //     of kp (Jastrow gradient, Laplacian and own sum of k; the potential
 //     change into the block scalars).
 // Item ranges of different cost start on wavefront boundaries.
-__device__ void accept_move(const KArgs &A, double *lds, int k, const double rold[3], const double rnew[3])
+__device__ void accept_move(const KArgs &A, double *lds, double *dphi, int k, const double rold[3],
+                            const double rnew[3])
 {
     const Layout &L = A.L;
     const int N = A.N, ns = A.ns, K = A.K, Kp = A.Kp, tid = threadIdx.x, NT = blockDim.x;
     const int s = spin_of(A, k), n = s ? A.n_dn : A.n_up, kl = s ? k - A.n_up : k, i0 = s ? A.n_up : 0;
     const int np = N + A.n_nuc;
     double *pos = lds + L.pos, *bv = lds + L.bv, *vrow = lds + L.vrow, *wrow = lds + L.wrow;
-    double *colk = lds + L.colk, *Yk = lds + L.Yk, *Y = lds + L.Y, *dphi = lds + L.dphi;
+    double *colk = lds + L.colk, *Yk = lds + L.Yk, *Y = lds + L.Y;
     double *gD = lds + L.gD, *gJ = lds + L.gJ, *Jo = lds + L.Jo, *dq = lds + L.dq, *kp = lds + L.kp;
     double *inv = lds + L.Ainv + s * ns * ns;
     auto up64 = [](int x) { return (x + 63) & ~63; };
@@ -904,7 +910,7 @@ __device__ __forceinline__ double local_energy(const KArgs &A, const double *lds
 
 // One workgroup per walker slot: a generation of continuous-time projection,
 // or (eval != 0) the move table at frozen positions.
-__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(3))) project_kernel(KArgs A)
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) project_kernel(KArgs A)
 {
     extern __shared__ double lds[];
     __shared__ int sflag[8];   // 2-3: pivots of the generation start, 5: stop, 6: bad input, 7: last move
@@ -933,15 +939,17 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
     }
 
     double EL, LAP = 0.0, V;
-    const int blob = A.state_len - 2;  // LDS part of the state blob
+    const int blob = A.dphi_at - 2;  // LDS part of the state blob
+    double *dphi = A.state_out + (size_t)slot * A.state_len + A.dphi_at;
     if (A.state_in && !A.eval) {
         const double *sb = A.state_in + (size_t)src * A.state_len;
         for (int t = tid; t < blob; t += NT) lds[L.Y + t] = sb[t];
+        for (int t = tid; t < N * L.dld; t += NT) dphi[t] = sb[A.dphi_at + t];
         EL = uni(sb[blob]);
         V = uni(sb[blob + 1]);
         __syncthreads();
     } else {
-        int rc = walker_setup(A, lds, sflag, EL, LAP, V);
+        int rc = walker_setup(A, lds, dphi, sflag, EL, LAP, V);
         if (rc) {
             if (tid == 0) report(A.err, rc, slot);
             return;
@@ -1066,7 +1074,8 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
             move_position(A, pos, R, ms, rnew);
             for (int c = 0; c < 3; ++c) rnew[c] = uni(rnew[c]);
             const double rold[3] = {uni(pos[3 * k]), uni(pos[3 * k + 1]), uni(pos[3 * k + 2])};
-            accept_move(A, lds, k, rold, rnew);
+            __syncthreads();   // every wavefront is done with T and xs
+            accept_move(A, lds, dphi, k, rold, rnew);
             if (((it + 1) & 7) == 0) refill_rng(A, rng, slot, it + 1);
         }
         __syncthreads();
@@ -1079,7 +1088,7 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
         }
     }
     for (int t = tid; t < 3 * N; t += NT) A.pos_out[(size_t)slot * 3 * N + t] = pos[t];
-    if (A.state_out) {
+    if (A.save_state) {
         double *sb = A.state_out + (size_t)slot * A.state_len;
         for (int t = tid; t < blob; t += NT) sb[t] = lds[L.Y + t];
         if (tid == 0) {
@@ -1202,7 +1211,7 @@ struct lrdmc_ctx {
     int cur = 0;
     // walker state blobs (double-buffered, follow d_pos through reconfiguration)
     double *d_state[2] = {nullptr, nullptr};
-    int state_len = 0;
+    int state_len = 0, dphi_at = 0;
     bool state_ok = false;  // d_state[cur] holds the state of d_pos[cur]
     double *d_logw = nullptr, *d_el = nullptr, *d_cw = nullptr;
     int *d_nmov = nullptr, *d_idx = nullptr, *d_err = nullptr;
@@ -1249,7 +1258,6 @@ Layout make_layout(int N, int ns, int K, int Kp, int M, int n_nuc, int NT, size_
     L.Y = take(N * Kp);
     L.Ainv = take(2 * ns * ns);
     L.dld = 4 * ns + 1;
-    L.dphi = take(N * L.dld);
     L.gD = take(4 * N);
     L.gJ = take(4 * N);
     L.Jo = take(N);
@@ -1263,15 +1271,17 @@ Layout make_layout(int N, int ns, int K, int Kp, int M, int n_nuc, int NT, size_
     // outputs (vrow, wrow) may share their space.
     int q = U;
     L.xs = q; q += NT;
-    L.T = q; q += std::max(M, 6 * ns);
-    L.vrow = L.T;
-    L.wrow = L.T + 5 * ns;
+    L.T = q; q += M;
+    const int search_end = q;
+    q = U;
+    L.vrow = q; q += 5 * ns;
+    L.wrow = q; q += ns;
     L.bv = q; q += 5 * Kp;
     L.colk = q; q += ns;
     L.Yk = q; q += Kp;
     L.dq = q; q += 4 * ns;
     L.kp = q; q += 6 * (N + n_nuc);
-    const int loop_end = q;
+    const int loop_end = std::max(q, search_end);
     // generation-start view
     q = U;
     L.G = q; q += 2 * ns * 2 * ns;
@@ -1377,12 +1387,15 @@ int launch_project(lrdmc_ctx *c, hipStream_t st, const double *pos_in, const int
     A.idx_in = idx_in;
     A.pos_out = pos_out;
     A.state_len = c->state_len;
+    A.dphi_at = c->dphi_at;
+    // the derivative rows live in the output blobs (also as evaluation scratch)
+    A.state_out = c->d_state[c->cur ^ 1];
     if (!eval) {
         // resume from the stored state except on refresh generations
         const int R = std::max(1, (int)c->prm.refresh);
         const bool resume = c->state_ok && R > 1 && (c->gen % (uint64_t)R) != 0;
         A.state_in = resume ? c->d_state[c->cur] : nullptr;
-        A.state_out = R > 1 ? c->d_state[c->cur ^ 1] : nullptr;
+        A.save_state = R > 1;
     }
     A.logw = c->d_logw;
     A.el = c->d_el;
@@ -1621,7 +1634,8 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
     c->nt = std::min(kMaxThreads, std::max(64, ((c->M / 2 + 63) / 64) * 64));
     c->L = make_layout(N, ns, K, c->Kp, c->M, sys->n_nuc, c->nt, prm->refresh > 1 ? 0 : 38 * 1024);
     c->lds_bytes = sizeof(double) * (size_t)c->L.total;
-    c->state_len = (c->L.Jo + N - c->L.Y) + 2;
+    c->dphi_at = (c->L.Jo + N - c->L.Y) + 2;
+    c->state_len = c->dphi_at + N * c->L.dld;
 
     auto cleanup = [&](int code, const std::string &m) {
         lrdmc_destroy(c);
@@ -1651,8 +1665,8 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
               alloc((void **)&c->d_Rheavy, sizeof(double) * Rheavy.size()) &&
               alloc((void **)&c->d_pos[0], sizeof(double) * W * s3) &&
               alloc((void **)&c->d_pos[1], sizeof(double) * W * s3) &&
-              (prm->refresh <= 1 || (alloc((void **)&c->d_state[0], sizeof(double) * W * c->state_len) &&
-                                     alloc((void **)&c->d_state[1], sizeof(double) * W * c->state_len))) &&
+              alloc((void **)&c->d_state[0], sizeof(double) * W * c->state_len) &&
+              alloc((void **)&c->d_state[1], sizeof(double) * W * c->state_len) &&
               alloc((void **)&c->d_logw, sizeof(double) * W) && alloc((void **)&c->d_el, sizeof(double) * W) &&
               alloc((void **)&c->d_cw, sizeof(double) * W) && alloc((void **)&c->d_nmov, sizeof(int) * W) &&
               alloc((void **)&c->d_idx, sizeof(int) * W) && alloc((void **)&c->d_err, sizeof(int) * 2);
