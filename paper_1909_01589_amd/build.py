@@ -14,6 +14,9 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",
     # packed FP32 instructions stay off in every HIP object of this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no loop-invariant hoisting of machine instructions: hoisted 64-bit
+    # constants of exp/log stay live across the whole move loop and spill
+    "-mllvm", "-disable-machine-licm",
     "-Wall", "-Wno-unused-function",
 ]
 

@@ -200,9 +200,55 @@ __device__ __forceinline__ void basis_fn_full(const KArgs &A, int mu, const doub
     bv[4 * K + mu] = (4.0 * al * al * d2 - (6.0 + 4.0 * l) * al) * P * e;
 }
 
-// sqrt of e in [0, 1] through the refined reciprocal square root; values
-// below 1e-300 (whose powers vanish anyway) map to 0.
-__device__ __forceinline__ double sqrt_unit(double e);
+__device__ __forceinline__ double rsqrt_nr(double a);
+
+// One chain of basis_dot2 with its step code fixed at compile time.
+// e^2.5 = e^2 sqrt(e); below 1e-300 the argument of the square root is
+// clamped (e^2 is then zero anyway), which keeps the chain free of branches.
+template <int CODE>
+__device__ __forceinline__ void chain_dot2(unsigned long long fl, int len, const double *yq, double ax,
+                                           double ay, double az, double bx, double by, double bz, double ea,
+                                           double eb, double &acc_a, double &acc_b)
+{
+    for (int q = 0; q < len; ++q) {
+        const int f = (int)(fl >> (3 * q)) & 7;
+        double pa = 0.0, pb = 0.0;
+        if (f & 1) {
+            const double ys = yq[0];
+            pa += ys;
+            pb += ys;
+            yq += 1;
+        }
+        if (f & 2) {
+            const double y0 = yq[0], y1 = yq[1], y2 = yq[2];
+            pa += ax * y0 + ay * y1 + az * y2;
+            pb += bx * y0 + by * y1 + bz * y2;
+            yq += 3;
+        }
+        if (f & 4) {
+            const double y0 = yq[0], y1 = yq[1], y2 = yq[2], y3 = yq[3], y4 = yq[4];
+            pa += ax * ay * y0 + ay * az * y1 + az * ax * y2 + (ax * ax - ay * ay) * y3 +
+                  (2.0 * az * az - ax * ax - ay * ay) * y4;
+            pb += bx * by * y0 + by * bz * y1 + bz * bx * y2 + (bx * bx - by * by) * y3 +
+                  (2.0 * bz * bz - bx * bx - by * by) * y4;
+            yq += 5;
+        }
+        acc_a += ea * pa;
+        acc_b += eb * pb;
+        if (q + 1 == len) break;
+        if (CODE == 3) {
+            ea = ea * ea * ea;
+            eb = eb * eb * eb;
+        } else if (CODE == 2) {
+            const double ra = rsqrt_nr(fmax(ea, 1e-300)), rb = rsqrt_nr(fmax(eb, 1e-300));
+            ea = (ea * ea) * (ea * ra);
+            eb = (eb * eb) * (eb * rb);
+        } else if (CODE == 1) {
+            ea = ea * ea;
+            eb = eb * eb;
+        }
+    }
+}
 
 // sum_mu g_mu(r) y[mu] at the two points ra, rb of a +/- move pair of one
 // electron (y: its orbital-projected inverse row): the determinant ratios of
@@ -220,48 +266,18 @@ __device__ __forceinline__ void basis_dot2(const KArgs &A, const double ra[3], c
         const double bx = rb[0] - D->R[0], by = rb[1] - D->R[1], bz = rb[2] - D->R[2];
         const double a2 = ax * ax + ay * ay + az * az, b2 = bx * bx + by * by + bz * bz;
         const double al0 = D->alpha0;
-        double ea = exp(-al0 * a2), eb = exp(-al0 * b2);
+        const double ea = exp(-al0 * a2), eb = exp(-al0 * b2);
         const unsigned long long fl = D->flags;
         const int len = D->len, code = D->code;
         const double *yq = y + D->mu0;
-        for (int q = 0; q < len; ++q) {
-            const int f = (int)(fl >> (3 * q)) & 7;
-            double pa = 0.0, pb = 0.0;
-            if (f & 1) {
-                const double ys = yq[0];
-                pa += ys;
-                pb += ys;
-                yq += 1;
-            }
-            if (f & 2) {
-                const double y0 = yq[0], y1 = yq[1], y2 = yq[2];
-                pa += ax * y0 + ay * y1 + az * y2;
-                pb += bx * y0 + by * y1 + bz * y2;
-                yq += 3;
-            }
-            if (f & 4) {
-                const double y0 = yq[0], y1 = yq[1], y2 = yq[2], y3 = yq[3], y4 = yq[4];
-                pa += ax * ay * y0 + ay * az * y1 + az * ax * y2 + (ax * ax - ay * ay) * y3 +
-                      (2.0 * az * az - ax * ax - ay * ay) * y4;
-                pb += bx * by * y0 + by * bz * y1 + bz * bx * y2 + (bx * bx - by * by) * y3 +
-                      (2.0 * bz * bz - bx * bx - by * by) * y4;
-                yq += 5;
-            }
-            acc_a += ea * pa;
-            acc_b += eb * pb;
-            if (q + 1 < len) {
-                if (code == 3) {
-                    ea = ea * ea * ea;
-                    eb = eb * eb * eb;
-                } else if (code == 2) {
-                    ea = (ea * ea) * sqrt_unit(ea);
-                    eb = (eb * eb) * sqrt_unit(eb);
-                } else {
-                    ea = ea * ea;
-                    eb = eb * eb;
-                }
-            }
-        }
+        if (code == 2)
+            chain_dot2<2>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+        else if (code == 1)
+            chain_dot2<1>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+        else if (code == 3)
+            chain_dot2<3>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+        else
+            chain_dot2<0>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
     }
     out_a = acc_a;
     out_b = acc_b;
@@ -359,10 +375,6 @@ __device__ __forceinline__ double rsqrt_nr(double a)
     return fma(y, e, y);
 }
 
-__device__ __forceinline__ double sqrt_unit(double e)
-{
-    return e > 1e-300 ? e * rsqrt_nr(e) : 0.0;
-}
 
 // u(r) for the move table: one Newton-Raphson step on each hardware estimate
 // (relative error about 3e-14), enough for the ratio exp(dJ).
