@@ -21,6 +21,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -33,18 +34,41 @@ FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector peak (vendor figure)
 METRIC = "LRDMC electron-moves/s"
 
 
+def kernel_source_hash() -> str:
+    """SHA-256 over the kernel sources and the build script (flags)."""
+    h = hashlib.sha256()
+    for rel in ("paper_1909_01589_amd/csrc/lrdmc.hip", "paper_1909_01589_amd/csrc/lrdmc_device.h",
+                "paper_1909_01589_amd/build.py"):
+        h.update(open(os.path.join(ROOT, rel), "rb").read())
+    return h.hexdigest()
+
+
 def _traffic_record(workload: str):
-    """HBM bytes per projection launch measured with rocprofv3 counters, if
-    they were taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "traffic_project_kernel.json")
+    """HBM bytes per projection launch measured with rocprofv3 counters
+    (profiles/traffic_project_kernel.md), if they were taken on the current
+    kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_project_kernel.md")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_1909_01589_amd", "csrc", "lrdmc.hip"), "rb").read()
-    if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
+    text = open(path).read()
+    m = re.search(r"^source_sha256 = ([0-9a-f]{64})$", text, re.M)
+    if not m or m.group(1) != kernel_source_hash():
         return None
-    ent = rec.get("workloads", {}).get(workload)
-    return None if ent is None else float(ent["bytes_per_launch"])
+    m = re.search(r"^" + re.escape(workload) + r" bytes_per_launch = ([0-9.eE+]+)$", text, re.M)
+    return float(m.group(1)) if m else None
+
+
+def copy_probe():
+    """A plain device copy of 512 MiB: the reference for scaling the HBM byte
+    counters (FETCH_SIZE, WRITE_SIZE) of a profiled run."""
+    import torch
+    n = 64 * 1024 * 1024
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 8}), flush=True)
 
 
 def cpu_baseline(system, a, ap, rc, tau, seed, pos, gen0, seconds):
@@ -136,7 +160,13 @@ def main():
     ap.add_argument("--second", default="ar_a0.2", help="second workload line ('' to skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 512 MiB device copy (counter calibration) and exit")
+    ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
     args = ap.parse_args()
+    if args.source_hash:
+        print(kernel_source_hash())
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus must be 1 "
@@ -148,6 +178,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_probe:
+        copy_probe()
+        return
 
     cfg, main_res = run_workload(args.workload, args.steps, args.warmup, not args.no_cpu_baseline,
                                  args.cpu_seconds)
