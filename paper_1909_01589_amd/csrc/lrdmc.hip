@@ -200,11 +200,21 @@ __device__ __forceinline__ void basis_fn_full(const KArgs &A, int mu, const doub
     bv[4 * K + mu] = (4.0 * al * al * d2 - (6.0 + 4.0 * l) * al) * P * e;
 }
 
-__device__ __forceinline__ double rsqrt_nr(double a);
+// sqrt(e) for e in [0, 1]: s = e y0 from the hardware reciprocal square-root
+// estimate y0 (relative error below 2^-24 on gfx950), then two corrections
+// s += (y0 / 2)(e - s^2) with fused residuals, which leave s at rounding
+// level.  The estimate is taken at e + 1e-300: that shift changes nothing
+// above 1e-284, and below 1e-154 the chain multiplies the result by e^2 = 0.
+__device__ __forceinline__ double sqrt_chain(double e)
+{
+    const double y = __builtin_amdgcn_rsq(e + 1e-300), h = 0.5 * y;
+    double s = e * y;
+    s = fma(h, fma(-s, s, e), s);
+    return fma(h, fma(-s, s, e), s);
+}
 
-// One chain of basis_dot2 with its step code fixed at compile time.
-// e^2.5 = e^2 sqrt(e); below 1e-300 the argument of the square root is
-// clamped (e^2 is then zero anyway), which keeps the chain free of branches.
+// One chain of basis_dot2 with its step code fixed at compile time
+// (e^2.5 = e^2 sqrt(e)); the chain has no branches on the data.
 template <int CODE>
 __device__ __forceinline__ void chain_dot2(unsigned long long fl, int len, const double *yq, double ax,
                                            double ay, double az, double bx, double by, double bz, double ea,
@@ -240,9 +250,9 @@ __device__ __forceinline__ void chain_dot2(unsigned long long fl, int len, const
             ea = ea * ea * ea;
             eb = eb * eb * eb;
         } else if (CODE == 2) {
-            const double ra = rsqrt_nr(fmax(ea, 1e-300)), rb = rsqrt_nr(fmax(eb, 1e-300));
-            ea = (ea * ea) * (ea * ra);
-            eb = (eb * eb) * (eb * rb);
+            const double sa = sqrt_chain(ea), sb = sqrt_chain(eb);
+            ea = (ea * ea) * sa;
+            eb = (eb * eb) * sb;
         } else if (CODE == 1) {
             ea = ea * ea;
             eb = eb * eb;
@@ -377,7 +387,8 @@ __device__ __forceinline__ double rsqrt_nr(double a)
 
 
 // u(r) for the move table: one Newton-Raphson step on each hardware estimate
-// (relative error about 3e-14), enough for the ratio exp(dJ).
+// (estimates within 2^-24 on gfx950, so about 5e-15 relative after the
+// step), enough for the ratio exp(dJ).
 __device__ __forceinline__ double pade_u(double c, double b, double d2)
 {
     double y = __builtin_amdgcn_rsq(d2);
