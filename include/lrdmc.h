@@ -194,6 +194,18 @@ int lrdmc_reconfigure(const double *log_w, const double *e_loc, int32_t W, doubl
 int lrdmc_set_timing(lrdmc_ctx *ctx, int32_t enable);
 int lrdmc_timing(const lrdmc_ctx *ctx, double *out);
 
+/* Kernel selection.  The library carries, besides the projection kernel for
+ * any system, kernels built for fixed system sizes (electrons per spin, basis
+ * functions, nuclei; see LRDMC_FIXED_SHAPES in the kernel source).
+ * lrdmc_create picks such a kernel when the system's sizes and LDS layout
+ * match one; both compute the same method and agree to rounding.
+ * lrdmc_use_generic(ctx, enable != 0) forces the general kernel for later
+ * launches (for comparison and testing); errors: LRDMC_EINVAL (NULL).
+ * lrdmc_is_specialized returns 1 when the next projection runs a fixed-size
+ * kernel, else 0 (also for NULL). */
+int lrdmc_use_generic(lrdmc_ctx *ctx, int32_t enable);
+int32_t lrdmc_is_specialized(const lrdmc_ctx *ctx);
+
 /* Generation counter of the next projection. */
 uint64_t lrdmc_generation(const lrdmc_ctx *ctx);
 

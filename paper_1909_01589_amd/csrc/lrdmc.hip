@@ -76,6 +76,67 @@ struct Layout {
     int total;
 };
 
+constexpr __host__ __device__ int cmax(int a, int b) { return a > b ? a : b; }
+
+// Threads per walker: one per +/- pair of moves, in whole wavefronts, at
+// most kMaxThreads (then a thread takes several pairs).
+constexpr __host__ __device__ int threads_for(int M)
+{
+    return cmax(64, ((M / 2 + 63) / 64) * 64) < kMaxThreads ? cmax(64, ((M / 2 + 63) / 64) * 64) : kMaxThreads;
+}
+
+// LDS layout of one walker.  The electron batch of the generation start grows until the block reaches
+// `target` bytes (or all electrons fit), never below one electron.
+constexpr __host__ __device__ Layout make_layout(int N, int ns, int K, int Kp, int M, int n_nuc, int NT,
+                                                 size_t target)
+{
+    Layout L{};
+    int o = 0;
+    auto take = [&](int n) { int r = o; o += n; return r; };
+    L.pos = take(3 * N);
+    L.Y = take(N * Kp);
+    L.Ainv = take(2 * ns * ns);
+    L.dld = 4 * ns + 1;
+    L.gD = take(4 * N);
+    L.gJ = take(4 * N);
+    L.Jo = take(N);
+    L.red = take(16);
+    L.sc = take(8);
+    L.rng = take(8 * 12);
+    const int U = o;
+    // move-loop view.  The prefix sums and weights live from the table to
+    // the search, which some wavefronts finish while others already write
+    // the first-phase temporaries of the accepted move; only the second-phase
+    // outputs (vrow, wrow) may share their space.
+    int q = U;
+    L.xs = q; q += NT;
+    L.T = q; q += M;
+    const int search_end = q;
+    q = U;
+    L.vrow = q; q += 5 * ns;
+    L.wrow = q; q += ns;
+    L.bv = q; q += 5 * Kp;
+    L.colk = q; q += ns;
+    L.Yk = q; q += Kp;
+    L.dq = q; q += 4 * ns;
+    L.kp = q; q += 6 * (N + n_nuc);
+    const int loop_end = cmax(q, search_end);
+    // generation-start view
+    q = U;
+    L.G = q; q += 2 * ns * 2 * ns;
+    L.piv = q; q += 2 * 2 * 2 * ns;
+    L.fac = q; q += 2 * ns;
+    L.bvb = q;
+    const int fixed_end = q;
+    int EB = 1;
+    const int base_total = cmax(loop_end, fixed_end + 5 * Kp);
+    const size_t limit = target > (size_t)base_total * sizeof(double) ? target : (size_t)base_total * sizeof(double);
+    while (EB < N && (size_t)cmax(loop_end, fixed_end + (EB + 1) * 5 * Kp) * sizeof(double) <= limit) ++EB;
+    L.EB = EB;
+    L.total = cmax(loop_end, fixed_end + EB * 5 * Kp);
+    return L;
+}
+
 // Basis functions are ordered group by group (s, then p x y z, then the five
 // d), groups by nucleus and exponent.  A chain is a run of groups on one
 // nucleus whose exponents grow by one constant ratio beta (see basis_dot2).
@@ -102,6 +163,7 @@ static_assert(sizeof(FnDesc) == 48, "basis function descriptor size");
 struct KArgs {
     // system
     int N, n_up, n_dn, ns, K, Kp, n_nuc, n_heavy, M;
+    int nt;                        // threads per workgroup
     const double *Znuc, *Rnuc;     // [n_nuc], [n_nuc][3]
     const double *Rheavy;          // [n_heavy][3] nuclei with Z >= z_heavy
     const FnDesc *fns;             // [K]
@@ -321,7 +383,7 @@ template <bool W, typename Store>
 __device__ __forceinline__ void contract(const KArgs &A, const double *b, int ne, int n, const double *yrow,
                                          Store store)
 {
-    const int K = A.K, Kp = A.Kp, NT = blockDim.x, ng = ne * n;
+    const int K = A.K, Kp = A.Kp, NT = A.nt, ng = ne * n;
     int lgP = 4;
     while (lgP > 0 && (ng << lgP) > NT) --lgP;
     const int P = 1 << lgP, Q = (K + P - 1) >> lgP;
@@ -481,8 +543,8 @@ __device__ double jastrow_setup(const KArgs &A, double *lds)
     double *gJ = lds + L.gJ, *Jo = lds + L.Jo;
     const int N = A.N;
     int seg = 64;
-    while (seg > 1 && seg * N > (int)blockDim.x) seg >>= 1;
-    const int per_pass = blockDim.x / seg;
+    while (seg > 1 && seg * N > A.nt) seg >>= 1;
+    const int per_pass = A.nt / seg;
     double vsum = 0.0;
     for (int base = 0; base < N; base += per_pass) {
         const int i = base + threadIdx.x / seg, sub = threadIdx.x % seg;
@@ -528,7 +590,7 @@ __device__ __forceinline__ void det_derivs_all(const KArgs &A, const double *Ain
                                                double *gD)
 {
     const int ns = A.ns;
-    for (int t = threadIdx.x; t < 4 * A.N; t += blockDim.x) {
+    for (int t = threadIdx.x; t < 4 * A.N; t += A.nt) {
         const int i = t >> 2, c = t & 3;
         const int s = spin_of(A, i), n = s ? A.n_dn : A.n_up, il = s ? i - A.n_up : i;
         const double *inv = Ainv + s * ns * ns;
@@ -552,7 +614,7 @@ __device__ int walker_setup(const KArgs &A, double *lds, double *dphi, int *sfla
                             double &V)
 {
     const Layout &L = A.L;
-    const int N = A.N, ns = A.ns, K = A.K, Kp = A.Kp, tid = threadIdx.x, NT = blockDim.x;
+    const int N = A.N, ns = A.ns, K = A.K, Kp = A.Kp, tid = threadIdx.x, NT = A.nt;
     double *pos = lds + L.pos, *G = lds + L.G, *bvb = lds + L.bvb;
     double *Ainv = lds + L.Ainv;
     const int two = 2 * ns;
@@ -799,7 +861,7 @@ __device__ void accept_move(const KArgs &A, double *lds, double *dphi, int k, co
                             const double rnew[3])
 {
     const Layout &L = A.L;
-    const int N = A.N, ns = A.ns, K = A.K, Kp = A.Kp, tid = threadIdx.x, NT = blockDim.x;
+    const int N = A.N, ns = A.ns, K = A.K, Kp = A.Kp, tid = threadIdx.x, NT = A.nt;
     const int s = spin_of(A, k), n = s ? A.n_dn : A.n_up, kl = s ? k - A.n_up : k, i0 = s ? A.n_up : 0;
     const int np = N + A.n_nuc;
     double *pos = lds + L.pos, *bv = lds + L.bv, *vrow = lds + L.vrow, *wrow = lds + L.wrow;
@@ -933,12 +995,12 @@ __device__ __forceinline__ double local_energy(const KArgs &A, const double *lds
 
 // One workgroup per walker slot: a generation of continuous-time projection,
 // or (eval != 0) the move table at frozen positions.
-__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) project_kernel(KArgs A)
+__device__ __forceinline__ void project_body(const KArgs &A)
 {
     extern __shared__ double lds[];
     __shared__ int sflag[8];   // 2-3: pivots of the generation start, 5: stop, 6: bad input, 7: last move
     const Layout &L = A.L;
-    const int tid = threadIdx.x, NT = blockDim.x, slot = blockIdx.x, N = A.N, M = A.M;
+    const int tid = threadIdx.x, NT = A.nt, slot = blockIdx.x, N = A.N, M = A.M;
     const int lane = tid & 63, wv = tid >> 6, nw = NT >> 6;
     double *pos = lds + L.pos, *T = lds + L.T, *rng = lds + L.rng, *red = lds + L.red, *xs = lds + L.xs;
 
@@ -1127,6 +1189,35 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
     }
 }
 
+// The projection kernel for any system: sizes and LDS offsets come from the
+// arguments.
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) project_kernel(KArgs A)
+{
+    project_body(A);
+}
+
+// The same kernel built for one system size: electron counts, basis size and
+// nucleus count (hence thread count and every LDS offset) are compile-time
+// constants, so loops over electrons and basis functions have fixed trip
+// counts and addresses fold into immediates.  The host takes it only when its
+// own layout for the context is this one.
+template <int NUP, int NDN, int KB, int NNUC>
+struct FixedShape {
+    static constexpr int N = NUP + NDN, ns = NUP > NDN ? NUP : NDN, M = 12 * N, Kp = KB | 1;
+    static constexpr int NT = threads_for(M);
+};
+
+template <int NUP, int NDN, int KB, int NNUC>
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4)))
+project_kernel_fixed(KArgs A)
+{
+    using S = FixedShape<NUP, NDN, KB, NNUC>;
+    constexpr Layout L = make_layout(S::N, S::ns, KB, S::Kp, S::M, NNUC, S::NT, 0);
+    A.N = S::N; A.n_up = NUP; A.n_dn = NDN; A.ns = S::ns; A.K = KB; A.Kp = S::Kp; A.M = S::M;
+    A.n_nuc = NNUC; A.nt = S::NT; A.L = L;
+    project_body(A);
+}
+
 // Fixed-population reconfiguration of W walkers by systematic resampling
 // (one workgroup).  cw: W-double scratch for the cumulative weights.
 __global__ void __launch_bounds__(1024) reconfigure_kernel(const double *logw, const double *el,
@@ -1220,6 +1311,22 @@ __global__ void gather_kernel(const double *pos, const double *el, const int *id
 
 std::string g_error;  // last failure without a context
 
+// Projection kernels built for fixed system sizes (n_up, n_dn, basis
+// functions, nuclei).  The list can be set at build time through
+// LRDMC_FIXED_SHAPES.  By default it holds the Ar-like (18 electrons, 64
+// functions) and Be-like (4 electrons, 8 functions) atoms; for the 40-electron
+// molecule with 256 functions the fully unrolled kernel spills registers and
+// runs slower than the general one, so it is left out.
+#define LRDMC_SHAPE(u, d, k, z) {u, d, k, z, (const void *)project_kernel_fixed<u, d, k, z>},
+#ifndef LRDMC_FIXED_SHAPES
+#define LRDMC_FIXED_SHAPES LRDMC_SHAPE(9, 9, 64, 1) LRDMC_SHAPE(2, 2, 8, 1)
+#endif
+struct FixedKernel {
+    int n_up, n_dn, K, n_nuc;
+    const void *fn;
+};
+const FixedKernel kFixedKernels[] = {LRDMC_FIXED_SHAPES};
+
 }  // namespace
 
 struct lrdmc_ctx {
@@ -1243,6 +1350,8 @@ struct lrdmc_ctx {
     int nt = 64;
     size_t lds_bytes = 0;
     Layout L{};
+    const void *fixed_fn = nullptr;  // kernel built for this system's sizes, if any
+    bool force_generic = false;
     std::string err;
     // event timing
     bool timing = false;
@@ -1270,63 +1379,11 @@ int fail(lrdmc_ctx *ctx, int code, const std::string &msg)
                         std::string(#expr) + ": " + hipGetErrorString(e_));                         \
     } while (0)
 
-// LDS layout of one walker.  The electron batch of the generation start grows until the block reaches
-// `target` bytes (or all electrons fit), never below one electron.
-Layout make_layout(int N, int ns, int K, int Kp, int M, int n_nuc, int NT, size_t target)
-{
-    Layout L{};
-    int o = 0;
-    auto take = [&](int n) { int r = o; o += n; return r; };
-    L.pos = take(3 * N);
-    L.Y = take(N * Kp);
-    L.Ainv = take(2 * ns * ns);
-    L.dld = 4 * ns + 1;
-    L.gD = take(4 * N);
-    L.gJ = take(4 * N);
-    L.Jo = take(N);
-    L.red = take(16);
-    L.sc = take(8);
-    L.rng = take(8 * 12);
-    const int U = o;
-    // move-loop view.  The prefix sums and weights live from the table to
-    // the search, which some wavefronts finish while others already write
-    // the first-phase temporaries of the accepted move; only the second-phase
-    // outputs (vrow, wrow) may share their space.
-    int q = U;
-    L.xs = q; q += NT;
-    L.T = q; q += M;
-    const int search_end = q;
-    q = U;
-    L.vrow = q; q += 5 * ns;
-    L.wrow = q; q += ns;
-    L.bv = q; q += 5 * Kp;
-    L.colk = q; q += ns;
-    L.Yk = q; q += Kp;
-    L.dq = q; q += 4 * ns;
-    L.kp = q; q += 6 * (N + n_nuc);
-    const int loop_end = std::max(q, search_end);
-    // generation-start view
-    q = U;
-    L.G = q; q += 2 * ns * 2 * ns;
-    L.piv = q; q += 2 * 2 * 2 * ns;
-    L.fac = q; q += 2 * ns;
-    L.bvb = q;
-    const int fixed_end = q;
-    int EB = 1;
-    const int base_total = std::max(loop_end, fixed_end + 5 * Kp);
-    while (EB < N && (size_t)std::max(loop_end, fixed_end + (EB + 1) * 5 * Kp) * sizeof(double) <=
-                         std::max(target, (size_t)base_total * sizeof(double)))
-        ++EB;
-    L.EB = EB;
-    L.total = std::max(loop_end, fixed_end + EB * 5 * Kp);
-    return L;
-}
-
 KArgs base_args(const lrdmc_ctx *c)
 {
     KArgs A{};
     A.N = c->N; A.n_up = c->n_up; A.n_dn = c->n_dn; A.ns = c->ns; A.K = c->K; A.Kp = c->Kp;
-    A.n_nuc = c->n_nuc; A.n_heavy = c->n_heavy; A.M = c->M;
+    A.n_nuc = c->n_nuc; A.n_heavy = c->n_heavy; A.M = c->M; A.nt = c->nt;
     A.Znuc = c->d_Z; A.Rnuc = c->d_R; A.Rheavy = c->d_Rheavy; A.moT = c->d_mo;
     A.n_chain = c->n_chain; A.chains = c->d_chain; A.fns = c->d_fn;
     A.b_ee = c->b_ee; A.b_en = c->b_en; A.v_nn = c->v_nn;
@@ -1428,8 +1485,9 @@ int launch_project(lrdmc_ctx *c, hipStream_t st, const double *pos_in, const int
     A.k_out = k;
     A.diag_out = diag;
     const int ev = eval ? -1 : timing_begin(c, st, 0);
-    hipLaunchKernelGGL(project_kernel, dim3(c->W), dim3(c->nt), c->lds_bytes, st, A);
-    HIP_TRY(c, hipGetLastError());
+    const void *fn = (c->fixed_fn && !c->force_generic) ? c->fixed_fn : (const void *)project_kernel;
+    void *args[] = {&A};
+    HIP_TRY(c, hipLaunchKernel(fn, dim3(c->W), dim3(c->nt), args, c->lds_bytes, st));
     timing_end(c, st, ev);
     return LRDMC_OK;
 }
@@ -1654,8 +1712,14 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
             vnn += sys->Z[I] * sys->Z[J] / std::sqrt(dx * dx + dy * dy + dz * dz);
         }
     c->v_nn = vnn;
-    c->nt = std::min(kMaxThreads, std::max(64, ((c->M / 2 + 63) / 64) * 64));
+    c->nt = threads_for(c->M);
     c->L = make_layout(N, ns, K, c->Kp, c->M, sys->n_nuc, c->nt, prm->refresh > 1 ? 0 : 38 * 1024);
+    // a kernel built for these sizes serves the context if its layout is this one
+    for (const FixedKernel &F : kFixedKernels) {
+        if (F.n_up != sys->n_up || F.n_dn != sys->n_dn || F.K != K || F.n_nuc != sys->n_nuc) continue;
+        const Layout Lf = make_layout(N, ns, K, c->Kp, c->M, sys->n_nuc, c->nt, 0);
+        if (std::memcmp(&Lf, &c->L, sizeof(Layout)) == 0) c->fixed_fn = F.fn;
+    }
     c->lds_bytes = sizeof(double) * (size_t)c->L.total;
     c->dphi_at = (c->L.Jo + N - c->L.Y) + 2;
     c->state_len = c->dphi_at + N * c->L.dld;
@@ -1670,10 +1734,12 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
         return cleanup(LRDMC_EDEVICE, "lrdmc_create: no HIP device");
     if (c->lds_bytes > (size_t)prop.sharedMemPerBlock)
         return cleanup(LRDMC_EINVAL, "lrdmc_create: walker state does not fit in LDS");
-    if (c->lds_bytes > 65536 &&
-        hipFuncSetAttribute((const void *)project_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)c->lds_bytes) != hipSuccess)
-        return cleanup(LRDMC_EDEVICE, "lrdmc_create: cannot raise the LDS limit");
+    if (c->lds_bytes > 65536) {
+        for (const void *fn : {(const void *)project_kernel, c->fixed_fn})
+            if (fn && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_bytes) !=
+                          hipSuccess)
+                return cleanup(LRDMC_EDEVICE, "lrdmc_create: cannot raise the LDS limit");
+    }
 
     const size_t W = n_walkers, s3 = 3 * (size_t)N;
     std::vector<double> moT((size_t)ns * K);   // occupied block, orbital-major, renumbered functions
@@ -1824,6 +1890,18 @@ int lrdmc_reconfigure(const double *log_w, const double *e_loc, int32_t W, doubl
                                                 hipGetErrorString(le != hipSuccess ? le : se));
     if (e[0]) return fail(nullptr, LRDMC_ENONFINITE, "lrdmc_reconfigure: non-finite weights");
     return LRDMC_OK;
+}
+
+int lrdmc_use_generic(lrdmc_ctx *c, int32_t enable)
+{
+    if (!c) return fail(nullptr, LRDMC_EINVAL, "lrdmc_use_generic: NULL context");
+    c->force_generic = enable != 0;
+    return LRDMC_OK;
+}
+
+int32_t lrdmc_is_specialized(const lrdmc_ctx *c)
+{
+    return (c && c->fixed_fn && !c->force_generic) ? 1 : 0;
 }
 
 int lrdmc_set_timing(lrdmc_ctx *c, int32_t enable)

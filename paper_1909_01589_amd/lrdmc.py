@@ -54,7 +54,8 @@ class lrdmc_params(C.Structure):
 _lib = None
 EXPORTS = ("lrdmc_spacing", "lrdmc_create", "lrdmc_set_walkers", "lrdmc_project", "lrdmc_branch",
            "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure",
-           "lrdmc_set_timing", "lrdmc_timing", "lrdmc_generation", "lrdmc_last_error", "lrdmc_destroy")
+           "lrdmc_use_generic", "lrdmc_is_specialized", "lrdmc_set_timing", "lrdmc_timing", "lrdmc_generation",
+           "lrdmc_last_error", "lrdmc_destroy")
 
 
 def load():
@@ -75,6 +76,9 @@ def load():
     lib.lrdmc_get_walkers.argtypes = [P, P, P, P, P, P]
     lib.lrdmc_eval_moves.argtypes = [P, P, P, P, P, P]
     lib.lrdmc_reconfigure.argtypes = [P, P, I32, D, P, P, P]
+    lib.lrdmc_use_generic.argtypes = [P, I32]
+    lib.lrdmc_is_specialized.argtypes = [P]
+    lib.lrdmc_is_specialized.restype = I32
     lib.lrdmc_set_timing.argtypes = [P, I32]
     lib.lrdmc_timing.argtypes = [P, P]
     lib.lrdmc_generation.argtypes = [P]
@@ -85,7 +89,7 @@ def load():
     lib.lrdmc_destroy.restype = None
     for name in ("lrdmc_spacing", "lrdmc_create", "lrdmc_set_walkers", "lrdmc_project", "lrdmc_branch",
                  "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure",
-                 "lrdmc_set_timing", "lrdmc_timing"):
+                 "lrdmc_use_generic", "lrdmc_set_timing", "lrdmc_timing"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -184,6 +188,14 @@ def lrdmc_reconfigure(log_w, e_loc, xi: float, idx, stats=None, stream=None):
     _check(load().lrdmc_reconfigure(_dptr(log_w, torch.float64), _dptr(e_loc, torch.float64),
                                     int(log_w.shape[0]), float(xi), _dptr(idx, torch.int32),
                                     _dptr(stats, torch.float64), _stream(stream)))
+
+
+def lrdmc_use_generic(ctx, enable: bool = True):
+    _check(load().lrdmc_use_generic(ctx, 1 if enable else 0), ctx)
+
+
+def lrdmc_is_specialized(ctx) -> bool:
+    return bool(load().lrdmc_is_specialized(ctx))
 
 
 def lrdmc_set_timing(ctx, enable: bool = True):

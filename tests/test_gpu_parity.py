@@ -142,3 +142,55 @@ def test_run_matches_oracle(name, W, n_gen, refresh):
         assert np.allclose(e, -2.0, rtol=1e-12)
         assert np.all(out["idx"].cpu().numpy() == np.arange(W)[None, :])
     gpu.close()
+
+
+@pytest.mark.parametrize("name,W,specialized", [("ar", 8, True), ("be", 16, True), ("tiny", 8, False),
+                                                ("molecule", 2, False)])
+def test_kernel_selection(name, W, specialized):
+    """Systems with a built-in fixed-size kernel run it; the rest run the
+    general kernel; lrdmc_use_generic switches back to the general one."""
+    from paper_1909_01589_amd.lrdmc import lrdmc_is_specialized, lrdmc_use_generic
+    s, gpu, _ = _pair(name, W, refresh=4)
+    assert lrdmc_is_specialized(gpu.ctx) == specialized
+    lrdmc_use_generic(gpu.ctx, True)
+    assert not lrdmc_is_specialized(gpu.ctx)
+    gpu.close()
+
+
+@pytest.mark.parametrize("name,W", [("ar", 6), ("be", 16)])
+def test_fixed_and_general_kernels_agree(name, W):
+    """Move tables of the fixed-size and general kernels on the same walkers:
+    ratios and coefficients agree to rounding, diagnostics within the parity
+    bars."""
+    from paper_1909_01589_amd.lrdmc import lrdmc_use_generic
+    s, gpu, _ = _pair(name, W)
+    pos = inputs.initial_walkers(s, W, 13)
+    r1, k1, d1 = (x.cpu().numpy() for x in gpu.eval_moves(pos))
+    lrdmc_use_generic(gpu.ctx, True)
+    r2, k2, d2 = (x.cpu().numpy() for x in gpu.eval_moves(pos))
+    scale = np.max(np.abs(r2), axis=1, keepdims=True)
+    assert np.all(np.abs(r1 - r2) <= 1e-12 * (np.abs(r2) + scale))
+    assert np.allclose(k1, k2, rtol=1e-14, atol=0)
+    assert np.allclose(d1, d2, rtol=1e-11, atol=1e-11)
+    gpu.close()
+
+
+@pytest.mark.parametrize("name,W,n_gen,refresh", [("ar", 16, 5, 2), ("be", 64, 6, 3)])
+def test_run_matches_oracle_general_kernel(name, W, n_gen, refresh):
+    """Whole projections through the general kernel on systems that have a
+    fixed-size one (the fixed-size path is covered by test_run_matches_oracle)."""
+    from paper_1909_01589_amd.lrdmc import lrdmc_use_generic
+    s, gpu, orc = _pair(name, W, seed=9, refresh=refresh)
+    lrdmc_use_generic(gpu.ctx, True)
+    pos = inputs.initial_walkers(s, W, 2)
+    gpu.set_walkers(pos, 0)
+    out = gpu.run(n_gen, want_idx=True)
+    ref = orc.run(pos, n_gen, gen0=0)
+    print(f"run general case={name}", flush=True)
+    assert np.array_equal(out["n_moves"].cpu().numpy(), ref["n_moves"])
+    assert np.array_equal(out["idx"].cpu().numpy(), ref["idx"])
+    e = out["ebar"].cpu().numpy()
+    assert np.all(np.abs(e - ref["ebar"]) <= 1e-10 + 1e-12 * np.abs(ref["ebar"]))
+    fin = gpu.get_walkers()["pos"].cpu().numpy()
+    assert np.allclose(fin, ref["pos"], rtol=0, atol=1e-11)
+    gpu.close()
