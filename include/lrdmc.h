@@ -90,7 +90,8 @@ typedef struct {
 
 /* Lattice and projection parameters.
  * a: small (core) spacing; a_prime: large spacing, a_prime >= a;
- * r_c: width of the switch p (main text Eq. (3)); nuclei with Z >= z_heavy
+ * r_c: parameter of the switch p (main text Eq. (3): width of the Gaussian;
+ * Eq. (2): inverse length of the Pade form); nuclei with Z >= z_heavy
  * define R_c; tau: projection time per generation (1/Ha); seed: Philox key;
  * rotate: random lattice orientation per move (0 = fixed x, y, z axes);
  * refresh: generations between recomputations of a walker's inverse Slater
@@ -103,6 +104,11 @@ typedef struct {
     uint64_t seed;
     int32_t rotate;
     int32_t refresh;
+    int32_t switch_form;        /* 0: Gaussian p of Eq. (3) (this paper's     */
+                                /* scheme); 1: Pade p of Eq. (2) (the earlier */
+                                /* scheme, with lrdmc_spacing_pade)           */
+    int32_t grids;              /* 2 (or 0): double grid, 12N moves; 1: single */
+                                /* grid of spacing a, p = 1, 6N moves          */
 } lrdmc_params;
 
 /* Host-side parameter choice of the paper for heaviest charge Z and small
@@ -114,6 +120,12 @@ typedef struct {
  * Errors: LRDMC_EINVAL for Z < 1, Z > 86, a <= 0, beta <= 0 or kappa <= 0. */
 int lrdmc_spacing(double Z, double a, double beta, double kappa,
                   double *r_c, double *a_prime, double *n_core);
+
+/* The earlier parametrization the paper compares against, for use with the
+ * Pade switch (switch_form = 1): r_c = Z/2 in Eq. (2) and
+ * a'/a = sqrt(Z^2/4 + 1) (main text Eq. (4)).  Host pointers.
+ * Errors: LRDMC_EINVAL for Z <= 0 or a <= 0. */
+int lrdmc_spacing_pade(double Z, double a, double *r_c, double *a_prime);
 
 /* Create a context for n_walkers walkers on the current HIP device.
  * Deep-copies sys and prm to the device and allocates the walker state.

@@ -51,7 +51,8 @@ class _Prm(C.Structure):
     _fields_ = [
         ("a", C.c_double), ("a_prime", C.c_double), ("r_c", C.c_double),
         ("z_heavy", C.c_double), ("tau", C.c_double),
-        ("seed", C.c_uint64), ("rotate", C.c_int32), ("pad", C.c_int32),
+        ("seed", C.c_uint64), ("rotate", C.c_int32),
+        ("switch_form", C.c_int32), ("grids", C.c_int32), ("pad", C.c_int32),
     ]
 
 
@@ -122,7 +123,7 @@ class Oracle:
 
     def __init__(self, system, a: float, a_prime: float, r_c: float,
                  z_heavy: Optional[float] = None, tau: float = 0.01,
-                 seed: int = 0, rotate: int = 1):
+                 seed: int = 0, rotate: int = 1, switch_form: int = 0, grids: int = 2):
         self.lib = load()
         self.system = system
         # keep arrays alive for the lifetime of the struct
@@ -133,9 +134,11 @@ class Oracle:
                         _ptr(system.shell_l), _ptr(system.shell_alpha), system.n_orb,
                         _ptr(system.mo), system.b_ee, system.b_en)
         zh = float(np.max(system.Z)) if z_heavy is None else float(z_heavy)
-        self.prm = _Prm(a, a_prime, r_c, zh, tau, seed, rotate, 0)
+        if switch_form not in (0, 1) or grids not in (1, 2):
+            raise ValueError("switch_form must be 0 (Gaussian) or 1 (Pade), grids 1 or 2")
+        self.prm = _Prm(a, a_prime, r_c, zh, tau, seed, rotate, switch_form, grids, 0)
         self.N = system.n_elec
-        self.M = 12 * self.N
+        self.M = (12 if grids == 2 else 6) * self.N
         self.K = self.lib.orc_nbasis(C.byref(self.sys))
 
     # -- parameters -------------------------------------------------------
@@ -143,7 +146,7 @@ class Oracle:
         d = {f: getattr(self.prm, f) for f, _ in _Prm._fields_ if f != "pad"}
         d.update(kw)
         return Oracle(self.system, d["a"], d["a_prime"], d["r_c"], d["z_heavy"],
-                      d["tau"], d["seed"], d["rotate"])
+                      d["tau"], d["seed"], d["rotate"], d["switch_form"], d["grids"])
 
     # -- random numbers ---------------------------------------------------
     def philox(self, ctr, key) -> np.ndarray:

@@ -50,8 +50,13 @@ typedef struct {
     double a, a_prime, r_c, z_heavy, tau;
     uint64_t seed;
     int32_t rotate;
+    int32_t switch_form;      /* 0: Gaussian switch, Eq. (3); 1: Pade switch, Eq. (2) */
+    int32_t grids;            /* 2: double grid (Eq. (1)); 1: single grid of spacing a */
     int32_t pad;
 } orc_params;
+
+/* Moves per electron: two grids x three axes x two signs, or one grid. */
+static int moves_per_electron(const orc_params *p) { return p->grids == 1 ? 6 : 12; }
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ESINGULAR = -2, ORC_ENONFINITE = -3, ORC_ENOMEM = -4 };
 
@@ -446,8 +451,10 @@ int orc_local_energy(const orc_system *s, const double *pos, double *e_l, double
 /* ------------------------------------------------------------------------ */
 /* Lattice moves (main text Eq. (1) and Eq. (3))                              */
 
-/* Switch p at point x: Gaussian of the distance to the nearest nucleus with
- * Z_I >= z_heavy (lowest index wins a tie). */
+/* Switch p at point x as a function of the squared distance d2 to the nearest
+ * nucleus with Z_I >= z_heavy (lowest index wins a tie): the Gaussian
+ * exp(-d2 / (2 r_c^2)) of Eq. (3), or the Pade form 1 / (1 + r_c^2 d2) of
+ * Eq. (2), whose r_c multiplies the distance. */
 double orc_p_switch(const orc_system *s, const orc_params *p, const double x[3])
 {
     int best = -1;
@@ -459,17 +466,20 @@ double orc_p_switch(const orc_system *s, const orc_params *p, const double x[3])
         if (best < 0 || d2 < bd2) { best = I; bd2 = d2; }
     }
     if (best < 0) return 0.0;
+    if (p->switch_form == 1) return 1.0 / (1.0 + p->r_c * p->r_c * bd2);
     return exp(-bd2 / (2.0 * p->r_c * p->r_c));
 }
 
 /* Move m = 12 i + 6 g + dir of electron i: grid g (0: spacing a weighted by
  * p, 1: spacing a' weighted by 1-p), axis dir/2, sign + for even dir.
  * New position r' = r_i + sign h e_axis; p is taken at the midpoint
- * r_i + sign (h/2) e_axis; coefficient k = p/a^2 or (1-p)/a'^2. */
+ * r_i + sign (h/2) e_axis; coefficient k = p/a^2 or (1-p)/a'^2.
+ * Single grid: m = 6 i + dir, spacing a, k = 1/a^2 (p = 1 everywhere). */
 void orc_move(const orc_system *s, const orc_params *p, const double *pos, const double Rm[9],
               int m, double rp[3], double *k)
 {
-    int i = m / 12, g = (m / 6) % 2, dir = m % 6, ax = dir / 2;
+    const int mpe = moves_per_electron(p);
+    int i = m / mpe, g = mpe == 12 ? (m / 6) % 2 : 0, dir = m % 6, ax = dir / 2;
     double sgn = (dir % 2 == 0) ? 1.0 : -1.0;
     double h = (g == 0) ? p->a : p->a_prime;
     double e[3] = {Rm[ax], Rm[3 + ax], Rm[6 + ax]};
@@ -477,6 +487,10 @@ void orc_move(const orc_system *s, const orc_params *p, const double *pos, const
     for (int c = 0; c < 3; ++c) {
         rp[c] = pos[3 * i + c] + sgn * h * e[c];
         mid[c] = pos[3 * i + c] + sgn * (0.5 * h) * e[c];
+    }
+    if (mpe == 6) {
+        *k = 1.0 / (p->a * p->a);
+        return;
     }
     double pv = orc_p_switch(s, p, mid);
     *k = (g == 0) ? pv / (p->a * p->a) : (1.0 - pv) / (p->a_prime * p->a_prime);
@@ -514,7 +528,7 @@ static int ratio_full(const orc_system *s, const double *pos, int i, const doubl
 int orc_eval_moves(const orc_system *s, const orc_params *p, const double *pos, const double Rm[9],
                    double *rho, double *kout, double *diag)
 {
-    int N = s->n_up + s->n_dn, K = orc_nbasis(s), M = 12 * N;
+    int N = s->n_up + s->n_dn, K = orc_nbasis(s), M = moves_per_electron(p) * N;
     int nmax = s->n_up > s->n_dn ? s->n_up : s->n_dn;
     size_t n2 = (size_t)nmax * nmax;
     double *w = (double *)malloc(sizeof(double) * (5 * (size_t)K + 3 * n2 + 3 * (size_t)N + 1));
@@ -538,7 +552,7 @@ int orc_eval_moves(const orc_system *s, const orc_params *p, const double *pos, 
     double sumk = 0, La = 0, Vsf = 0, Delta = 0;
     for (int m = 0; m < M; ++m) {
         double rp[3], k;
-        int i = m / 12, sg = spin_of(s, i);
+        int i = m / moves_per_electron(p), sg = spin_of(s, i);
         orc_move(s, p, pos, Rm, m, rp, &k);
         double r;
         ratio_full(s, pos, i, rp, A[sg], ld[sg], sgn[sg], J, pos_tmp, Atmp, w, &r);
@@ -597,7 +611,7 @@ int orc_select(const double *T, int M, double u2)
 int orc_generation(const orc_system *s, const orc_params *p, uint64_t slot, uint64_t gen,
                    double *pos, double *log_w, double *e_l, int64_t *n_moves)
 {
-    int N = s->n_up + s->n_dn, M = 12 * N;
+    int N = s->n_up + s->n_dn, M = moves_per_electron(p) * N;
     double *rho = (double *)malloc(sizeof(double) * 3 * M);
     if (!rho) return ORC_ENOMEM;
     double *k = rho + M, *T = k + M;
@@ -626,7 +640,7 @@ int orc_generation(const orc_system *s, const orc_params *p, uint64_t slot, uint
         int ms = orc_select(T, M, u[1]);
         double rp[3], kk;
         orc_move(s, p, pos, Rm, ms, rp, &kk);
-        int i = ms / 12;
+        int i = ms / moves_per_electron(p);
         pos[3 * i] = rp[0]; pos[3 * i + 1] = rp[1]; pos[3 * i + 2] = rp[2];
         ++moves;
         rc = orc_local_energy(s, pos, &EL, &lap, &V);

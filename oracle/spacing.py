@@ -118,3 +118,10 @@ def spacing(Z: int, a: float, beta: float = BETA, kappa: float = KAPPA):
     rc = rc_of_a(a, Z, beta, kappa)
     nc = n_core(Z, rc)
     return rc, a * math.sqrt((Z - nc) / nc), nc
+
+
+def spacing_pade(Z: float, a: float):
+    """(r_c, a') of the earlier parametrization the paper compares against:
+    r_c = Z/2 in the Pade switch of main text Eq. (2), and
+    a'/a = sqrt(Z^2/4 + 1) (main text Eq. (4))."""
+    return 0.5 * Z, a * math.sqrt(Z * Z / 4.0 + 1.0)

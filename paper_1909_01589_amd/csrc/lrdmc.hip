@@ -172,7 +172,10 @@ struct KArgs {
     const double *moT;             // [ns][K]: occupied MO coefficients, orbital-major
     double b_ee, b_en, v_nn;
     // lattice
-    double a, ap, inv_a2, inv_ap2, inv_2rc2, tau;
+    double a, ap, inv_a2, inv_ap2, tau;
+    double sw_c;                   // 1 / (2 r_c^2) (Gaussian switch) or r_c^2 (Pade switch)
+    int sw_pade;                   // 1: Pade switch of Eq. (2); 0: Gaussian of Eq. (3)
+    int mpe;                       // moves per electron: 12 (double grid) or 6 (single grid, p = 1)
     uint64_t seed;
     int rotate;
     // walkers
@@ -355,7 +358,19 @@ __device__ __forceinline__ void basis_dot2(const KArgs &A, const double ra[3], c
     out_b = acc_b;
 }
 
-// Switch p at x: Gaussian of the distance to the nearest heavy nucleus.
+__device__ __forceinline__ double rcp_nr(double a);
+
+// Spacing of grid g (0: a, 1: a').  Both fields are read before the select:
+// a select between the two field addresses keeps a modified argument copy
+// (the fixed-size kernels) in scratch memory.
+__device__ __forceinline__ double grid_spacing(const KArgs &A, int g)
+{
+    const double a = A.a, ap = A.ap;
+    return g ? ap : a;
+}
+
+// Switch p at x from the squared distance d2 to the nearest heavy nucleus:
+// exp(-d2 / (2 r_c^2)) (Eq. (3)) or 1 / (1 + r_c^2 d2) (Eq. (2)).
 __device__ __forceinline__ double p_switch(const KArgs &A, const double x[3])
 {
     double best = 0.0;
@@ -366,7 +381,8 @@ __device__ __forceinline__ double p_switch(const KArgs &A, const double x[3])
         const double d2 = dx * dx + dy * dy + dz * dz;
         if (h == 0 || d2 < best) best = d2;
     }
-    return exp(-best * A.inv_2rc2);
+    if (A.sw_pade) return rcp_nr(1.0 + A.sw_c * best);
+    return exp(-best * A.sw_c);
 }
 
 // -- per-walker state ------------------------------------------------------
@@ -528,15 +544,15 @@ __device__ __forceinline__ void jastrow_point2(const KArgs &A, const double *pos
 __device__ __forceinline__ void move_position(const KArgs &A, const double *pos, const double *Rm, int m,
                                               double rp[3])
 {
-    const int i = m / 12, g = (m / 6) & 1, dir = m % 6, ax = dir >> 1;
-    const double h = g ? A.ap : A.a;
+    const int i = m / A.mpe, g = A.mpe == 12 ? (m / 6) & 1 : 0, dir = m % 6, ax = dir >> 1;
+    const double h = grid_spacing(A, g);
     const double t = (dir & 1) ? -h : h;
     for (int c = 0; c < 3; ++c) rp[c] = pos[3 * i + c] + t * Rm[3 * c + ax];
 }
 
 // Jastrow gradient/Laplacian and own sum of every electron; returns the total
 // potential to every thread.  Segments of `seg` lanes per electron.
-__device__ double jastrow_setup(const KArgs &A, double *lds)
+__device__ __forceinline__ double jastrow_setup(const KArgs &A, double *lds)
 {
     const Layout &L = A.L;
     const double *pos = lds + L.pos;
@@ -610,7 +626,7 @@ __device__ __forceinline__ double psi_lap_term(const double *d, const double *j)
 // Gauss-Jordan inversion with partial pivoting, Y = C Ainv, determinant and
 // Jastrow derivatives, local energy.  Returns an error code (uniform);
 // EL, LAP (sum_i lap_i Psi/Psi) and V reach every thread.
-__device__ int walker_setup(const KArgs &A, double *lds, double *dphi, int *sflag, double &EL, double &LAP,
+__device__ __forceinline__ int walker_setup(const KArgs &A, double *lds, double *dphi, int *sflag, double &EL, double &LAP,
                             double &V)
 {
     const Layout &L = A.L;
@@ -763,8 +779,8 @@ __device__ __forceinline__ double move_table(const KArgs &A, double *lds, const 
     double *T = lds + L.T;
     double part = 0.0;
     for (int m = c0; m < c1; m += 2) {
-        const int i = m / 12, g = (m / 6) & 1, ax = (m % 6) >> 1;
-        const double h = g ? A.ap : A.a;
+        const int i = m / A.mpe, g = A.mpe == 12 ? (m / 6) & 1 : 0, ax = (m % 6) >> 1;
+        const double h = grid_spacing(A, g);
         const double e[3] = {Rm[ax], Rm[3 + ax], Rm[6 + ax]};
         double ra[3], rb[3], ma[3], mb[3];
         for (int c = 0; c < 3; ++c) {
@@ -774,9 +790,12 @@ __device__ __forceinline__ double move_table(const KArgs &A, double *lds, const 
             ma[c] = r + (0.5 * h) * e[c];
             mb[c] = r + (-0.5 * h) * e[c];
         }
-        const double pa = p_switch(A, ma), pb = p_switch(A, mb);
-        const double ka = g ? (1.0 - pa) * A.inv_ap2 : pa * A.inv_a2;
-        const double kb = g ? (1.0 - pb) * A.inv_ap2 : pb * A.inv_a2;
+        double ka = A.inv_a2, kb = A.inv_a2;   // single grid: p = 1
+        if (A.mpe == 12) {
+            const double pa = p_switch(A, ma), pb = p_switch(A, mb);
+            ka = g ? (1.0 - pa) * A.inv_ap2 : pa * A.inv_a2;
+            kb = g ? (1.0 - pb) * A.inv_ap2 : pb * A.inv_a2;
+        }
         double rda, rdb, ja, jb;
         basis_dot2(A, ra, rb, Y + i * A.Kp, rda, rdb);
         jastrow_point2(A, pos, i, ra, rb, ja, jb);
@@ -857,7 +876,7 @@ __device__ __forceinline__ double seq_dot(const double *x, const double *y, int 
 //     of kp (Jastrow gradient, Laplacian and own sum of k; the potential
 //     change into the block scalars).
 // Item ranges of different cost start on wavefront boundaries.
-__device__ void accept_move(const KArgs &A, double *lds, double *dphi, int k, const double rold[3],
+__device__ __forceinline__ void accept_move(const KArgs &A, double *lds, double *dphi, int k, const double rold[3],
                             const double rnew[3])
 {
     const Layout &L = A.L;
@@ -1154,7 +1173,7 @@ __device__ __forceinline__ void project_body(const KArgs &A)
             return;
         }
         {
-            const int k = ms / 12;
+            const int k = ms / A.mpe;
             double rnew[3];
             move_position(A, pos, R, ms, rnew);
             for (int c = 0; c < 3; ++c) rnew[c] = uni(rnew[c]);
@@ -1214,7 +1233,7 @@ project_kernel_fixed(KArgs A)
     using S = FixedShape<NUP, NDN, KB, NNUC>;
     constexpr Layout L = make_layout(S::N, S::ns, KB, S::Kp, S::M, NNUC, S::NT, 0);
     A.N = S::N; A.n_up = NUP; A.n_dn = NDN; A.ns = S::ns; A.K = KB; A.Kp = S::Kp; A.M = S::M;
-    A.n_nuc = NNUC; A.nt = S::NT; A.L = L;
+    A.n_nuc = NNUC; A.nt = S::NT; A.mpe = 12; A.L = L;
     project_body(A);
 }
 
@@ -1390,7 +1409,9 @@ KArgs base_args(const lrdmc_ctx *c)
     A.a = c->prm.a; A.ap = c->prm.a_prime;
     A.inv_a2 = 1.0 / (c->prm.a * c->prm.a);
     A.inv_ap2 = 1.0 / (c->prm.a_prime * c->prm.a_prime);
-    A.inv_2rc2 = 1.0 / (2.0 * c->prm.r_c * c->prm.r_c);
+    A.sw_pade = c->prm.switch_form == 1;
+    A.sw_c = A.sw_pade ? c->prm.r_c * c->prm.r_c : 1.0 / (2.0 * c->prm.r_c * c->prm.r_c);
+    A.mpe = c->M / c->N;
     A.tau = c->prm.tau; A.seed = c->prm.seed; A.rotate = c->prm.rotate;
     A.W = c->W; A.gen = c->gen; A.err = c->d_err; A.L = c->L;
     return A;
@@ -1586,6 +1607,15 @@ int lrdmc_spacing(double Z, double a, double beta, double kappa, double *r_c, do
     return LRDMC_OK;
 }
 
+int lrdmc_spacing_pade(double Z, double a, double *r_c, double *a_prime)
+{
+    if (!(Z > 0.0) || !(a > 0.0) || !r_c || !a_prime)
+        return fail(nullptr, LRDMC_EINVAL, "lrdmc_spacing_pade: need Z > 0, a > 0 and output pointers");
+    *r_c = 0.5 * Z;
+    *a_prime = a * std::sqrt(0.25 * Z * Z + 1.0);
+    return LRDMC_OK;
+}
+
 int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_walkers, lrdmc_ctx **out)
 {
     if (!sys || !prm || !out) return fail(nullptr, LRDMC_EINVAL, "lrdmc_create: NULL argument");
@@ -1596,7 +1626,8 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
         !sys->shell_l || !sys->shell_alpha || !sys->mo)
         return fail(nullptr, LRDMC_EINVAL, "lrdmc_create: invalid system sizes or pointers");
     if (!(prm->a > 0.0) || !(prm->a_prime >= prm->a) || !(prm->r_c > 0.0) || !(prm->tau > 0.0) ||
-        !std::isfinite(prm->a_prime) || !std::isfinite(prm->tau) || prm->refresh < 0)
+        !std::isfinite(prm->a_prime) || !std::isfinite(prm->tau) || prm->refresh < 0 ||
+        prm->switch_form < 0 || prm->switch_form > 1 || prm->grids < 0 || prm->grids > 2)
         return fail(nullptr, LRDMC_EINVAL, "lrdmc_create: invalid lattice parameters (need a > 0, a' >= a, r_c > 0, tau > 0)");
     int K = 0;
     for (int q = 0; q < sys->n_shell; ++q) {
@@ -1703,7 +1734,7 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
     if (!c) return fail(nullptr, LRDMC_ENOMEM, "lrdmc_create: host allocation");
     c->W = n_walkers; c->N = N; c->n_up = sys->n_up; c->n_dn = sys->n_dn; c->ns = ns; c->K = K;
     c->Kp = K | 1; c->n_nuc = sys->n_nuc;
-    c->n_heavy = (int)heavy.size(); c->M = 12 * N; c->n_chain = (int)chains.size(); c->b_ee = sys->b_ee; c->b_en = sys->b_en; c->prm = *prm;
+    c->n_heavy = (int)heavy.size(); c->M = (prm->grids == 1 ? 6 : 12) * N; c->n_chain = (int)chains.size(); c->b_ee = sys->b_ee; c->b_en = sys->b_en; c->prm = *prm;
     double vnn = 0.0;
     for (int I = 0; I < sys->n_nuc; ++I)
         for (int J = I + 1; J < sys->n_nuc; ++J) {
@@ -1716,7 +1747,8 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
     c->L = make_layout(N, ns, K, c->Kp, c->M, sys->n_nuc, c->nt, prm->refresh > 1 ? 0 : 38 * 1024);
     // a kernel built for these sizes serves the context if its layout is this one
     for (const FixedKernel &F : kFixedKernels) {
-        if (F.n_up != sys->n_up || F.n_dn != sys->n_dn || F.K != K || F.n_nuc != sys->n_nuc) continue;
+        if (F.n_up != sys->n_up || F.n_dn != sys->n_dn || F.K != K || F.n_nuc != sys->n_nuc || c->M != 12 * N)
+            continue;
         const Layout Lf = make_layout(N, ns, K, c->Kp, c->M, sys->n_nuc, c->nt, 0);
         if (std::memcmp(&Lf, &c->L, sizeof(Layout)) == 0) c->fixed_fn = F.fn;
     }

@@ -48,11 +48,12 @@ class lrdmc_params(C.Structure):
         ("a", C.c_double), ("a_prime", C.c_double), ("r_c", C.c_double),
         ("z_heavy", C.c_double), ("tau", C.c_double),
         ("seed", C.c_uint64), ("rotate", C.c_int32), ("refresh", C.c_int32),
+        ("switch_form", C.c_int32), ("grids", C.c_int32),
     ]
 
 
 _lib = None
-EXPORTS = ("lrdmc_spacing", "lrdmc_create", "lrdmc_set_walkers", "lrdmc_project", "lrdmc_branch",
+EXPORTS = ("lrdmc_spacing", "lrdmc_spacing_pade", "lrdmc_create", "lrdmc_set_walkers", "lrdmc_project", "lrdmc_branch",
            "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure",
            "lrdmc_use_generic", "lrdmc_is_specialized", "lrdmc_set_timing", "lrdmc_timing", "lrdmc_generation",
            "lrdmc_last_error", "lrdmc_destroy")
@@ -68,6 +69,7 @@ def load():
     lib = C.CDLL(LIB_PATH)
     P, I32, I64, U64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
     lib.lrdmc_spacing.argtypes = [D, D, D, D, P, P, P]
+    lib.lrdmc_spacing_pade.argtypes = [D, D, P, P]
     lib.lrdmc_create.argtypes = [P, P, I32, P]
     lib.lrdmc_set_walkers.argtypes = [P, P, U64, P]
     lib.lrdmc_project.argtypes = [P, P]
@@ -87,7 +89,7 @@ def load():
     lib.lrdmc_last_error.restype = C.c_char_p
     lib.lrdmc_destroy.argtypes = [P]
     lib.lrdmc_destroy.restype = None
-    for name in ("lrdmc_spacing", "lrdmc_create", "lrdmc_set_walkers", "lrdmc_project", "lrdmc_branch",
+    for name in ("lrdmc_spacing", "lrdmc_spacing_pade", "lrdmc_create", "lrdmc_set_walkers", "lrdmc_project", "lrdmc_branch",
                  "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure",
                  "lrdmc_use_generic", "lrdmc_set_timing", "lrdmc_timing"):
         getattr(lib, name).restype = C.c_int
@@ -127,6 +129,13 @@ def lrdmc_spacing(Z: float, a: float, beta: float = 0.75, kappa: float = 2.5) ->
     return rc.value, ap.value, nc.value
 
 
+def lrdmc_spacing_pade(Z: float, a: float) -> Tuple[float, float]:
+    """Earlier parametrization (Eq. (2) switch with r_c = Z/2, Eq. (4) a'/a)."""
+    rc, ap = C.c_double(), C.c_double()
+    _check(load().lrdmc_spacing_pade(float(Z), float(a), C.byref(rc), C.byref(ap)))
+    return rc.value, ap.value
+
+
 def _pack_system(system):
     keep = [np.ascontiguousarray(system.Z, dtype=np.float64),
             np.ascontiguousarray(system.R, dtype=np.float64).reshape(-1),
@@ -142,10 +151,11 @@ def _pack_system(system):
 
 
 def lrdmc_create(system, a: float, a_prime: float, r_c: float, tau: float, n_walkers: int,
-                 z_heavy: Optional[float] = None, seed: int = 0, rotate: int = 1, refresh: int = 1) -> int:
+                 z_heavy: Optional[float] = None, seed: int = 0, rotate: int = 1, refresh: int = 1,
+                 switch_form: int = 0, grids: int = 2) -> int:
     s, keep = _pack_system(system)
     zh = float(np.max(system.Z)) if z_heavy is None else float(z_heavy)
-    p = lrdmc_params(a, a_prime, r_c, zh, tau, seed, rotate, refresh)
+    p = lrdmc_params(a, a_prime, r_c, zh, tau, seed, rotate, refresh, switch_form, grids)
     ctx = C.c_void_p()
     _check(load().lrdmc_create(C.byref(s), C.byref(p), int(n_walkers), C.byref(ctx)))
     del keep
@@ -229,7 +239,7 @@ class LRDMC:
 
     def __init__(self, system, a: float, a_prime: float, r_c: float, tau: float, n_walkers: int,
                  z_heavy: Optional[float] = None, seed: int = 0, rotate: int = 1, refresh: int = 1,
-                 device: str = "cuda:0"):
+                 device: str = "cuda:0", switch_form: int = 0, grids: int = 2):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the LRDMC projection runs only on the HIP device")
         self.device = torch.device(device)
@@ -239,8 +249,9 @@ class LRDMC:
         self.system = system
         self.W = int(n_walkers)
         self.N = system.n_elec
-        self.M = 12 * self.N
-        self.ctx = lrdmc_create(system, a, a_prime, r_c, tau, n_walkers, z_heavy, seed, rotate, refresh)
+        self.M = (6 if grids == 1 else 12) * self.N
+        self.ctx = lrdmc_create(system, a, a_prime, r_c, tau, n_walkers, z_heavy, seed, rotate, refresh,
+                                switch_form, grids)
 
     def close(self):
         if self.ctx:
