@@ -58,6 +58,95 @@ def _traffic_record(workload: str):
     return float(m.group(1)) if m else None
 
 
+HE_EXACT = -2.903724        # nonrelativistic He ground state, the value the paper quotes
+
+
+def _switch_sum(pos, R, r_c, form):
+    """Sum over electrons of the switch p at the electrons, averaged over
+    walkers (the sampled N_core of Eq. (7))."""
+    d2 = ((pos - R[None, None, :]) ** 2).sum(axis=2)
+    p = 1.0 / (1.0 + r_c * r_c * d2) if form == 1 else np.exp(-d2 / (2.0 * r_c * r_c))
+    return float(p.sum(axis=1).mean())
+
+
+def _fit_e0(a, E, sig):
+    """Weighted least squares E(a) = E0 + k1 a^2 + k2 a^4; (E0, sigma E0,
+    chi^2 per degree of freedom)."""
+    a, E, sig = (np.asarray(x, dtype=np.float64) for x in (a, E, sig))
+    X = np.stack([np.ones_like(a), a ** 2, a ** 4], axis=1) / sig[:, None]
+    y = E / sig
+    coef, *_ = np.linalg.lstsq(X, y, rcond=None)
+    cov = np.linalg.inv(X.T @ X)
+    chi2 = float(((X @ coef - y) ** 2).sum()) / max(1, len(a) - 3)
+    return float(coef[0]), float(np.sqrt(cov[0, 0])), chi2
+
+
+def ascan(walkers=16384, t_equil=5.0, t_prod=20.0, alphas=(1.0, 1.25, 1.5, 1.75, 2.0, 2.5, 3.0, 3.5), seed=0,
+          moves_per_electron=4.0):
+    """The paper's spacing scan on helium with a nodeless trial function
+    (fixed node exact): for the double grid of this paper (Gaussian switch,
+    r_c from Eq. (S-13), a' from Eq. (6)), the earlier double grid (Pade
+    switch, r_c = Z/2, a' from Eq. (4)) and the single grid, at
+    a = 1/(alpha Z): LRDMC energies, moves per unit projection time, the
+    single/double move-rate ratio beside Eq. (5) with the sampled N_core,
+    and E0 from the fit E0 + k1 a^2 + k2 a^4.  Each run equilibrates for
+    projection time t_equil and averages over t_prod (1/Ha), with tau per
+    generation set for about `moves_per_electron` moves per electron."""
+    import torch
+    from paper_1909_01589_amd import inputs, stats
+    from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_spacing, lrdmc_spacing_pade
+    s = inputs.helium_nodeless()
+    Z, N = float(s.Z[0]), s.n_elec
+    pos0 = inputs.initial_walkers(s, walkers, seed)
+    modes = {"double_grid": (0, 2), "double_grid_previous": (1, 2), "single_grid": (0, 1)}
+    res = {}
+    t0 = time.perf_counter()
+    for mode, (form, grids) in modes.items():
+        rows = []
+        for al in alphas:
+            a = 1.0 / (al * Z)
+            if form == 1:
+                rc, ap = lrdmc_spacing_pade(Z, a)
+            elif grids == 2:
+                rc, ap, _ = lrdmc_spacing(Z, a)
+                ap = max(ap, a)    # Eq. (6) gives a'/a < 1 when N_core > Z/2
+            else:
+                rc, ap = 1.0, a
+            kw = dict(seed=seed, switch_form=form, grids=grids, refresh=8)
+            g = LRDMC(s, a, ap, rc, 1.0, walkers, **kw)
+            delta = float(g.eval_moves(pos0)[2][:, 6].mean())
+            g.close()
+            tau = moves_per_electron * N / delta
+            equil, gens = int(np.ceil(t_equil / tau)), int(np.ceil(t_prod / tau))
+            g = LRDMC(s, a, ap, rc, tau, walkers, **kw)
+            g.set_walkers(pos0, 0)
+            g.run(equil)
+            out = g.run(gens)
+            torch.cuda.synchronize()
+            lwb, eb = out["log_wbar"].cpu().numpy(), out["ebar"].cpu().numpy()
+            E, sig = stats.estimate(lwb, eb, p=None)
+            moves = int(out["n_moves"].sum())
+            nc = _switch_sum(g.get_walkers()["pos"].cpu().numpy(), s.R[0], rc, form) if grids == 2 else float(N)
+            g.close()
+            rows.append(dict(alpha=al, a=a, a_prime=ap, r_c=rc, tau=tau, generations=gens, E=E, sigma=sig,
+                             move_rate=moves / (walkers * tau * gens), n_core=nc))
+        E0, s0, chi2 = _fit_e0([r["a"] for r in rows], [r["E"] for r in rows], [r["sigma"] for r in rows])
+        res[mode] = dict(rows=rows, E0=E0, sigma_E0=s0, chi2_dof=chi2)
+    speed = {}
+    for mode in ("double_grid", "double_grid_previous"):
+        lst = []
+        for r1, r2 in zip(res["single_grid"]["rows"], res[mode]["rows"]):
+            nc, ratio = r2["n_core"], r2["a_prime"] / r2["a"]
+            lst.append(dict(alpha=r2["alpha"], measured=r1["move_rate"] / r2["move_rate"],
+                            eq5=1.0 / (nc / N + (N - nc) / N * ratio ** -2)))
+        speed[mode] = lst
+    return {"ascan": {"system": "He, nodeless s orbital x Pade Jastrow (fixed node exact)",
+                      "walkers": walkers, "equilibration_time": t_equil, "production_time": t_prod,
+                      "energy": "mean of the generation energies, reblocked error",
+                      "reference_E": HE_EXACT, "modes": res, "speedup": speed,
+                      "wall_s": time.perf_counter() - t0}}
+
+
 def copy_probe():
     """A plain device copy of 512 MiB: the reference for scaling the HBM byte
     counters (FETCH_SIZE, WRITE_SIZE) of a profiled run."""
@@ -163,6 +252,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device copy (counter calibration) and exit")
     ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
+    ap.add_argument("--ascan", action="store_true",
+                    help="only run the spacing scan on helium for the three lattice schemes and exit")
     args = ap.parse_args()
     if args.source_hash:
         print(kernel_source_hash())
@@ -180,6 +271,9 @@ def main():
         sys.exit(1)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.ascan:
+        print(json.dumps(ascan()), flush=True)
         return
 
     cfg, main_res = run_workload(args.workload, args.steps, args.warmup, not args.no_cpu_baseline,

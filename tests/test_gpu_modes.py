@@ -119,3 +119,26 @@ def test_exact_hydrogenic_trial_function(mode):
     assert np.allclose(out["ebar"].cpu().numpy(), -Z * Z / 2, rtol=1e-12)
     assert np.all(out["idx"].cpu().numpy() == np.arange(W)[None, :])
     gpu.close()
+
+
+def test_spacing_scan_on_helium():
+    """The paper's spacing scan through the GPU path on helium with a nodeless
+    trial function (fixed node exact), for the three lattice schemes:
+    * the single/double move-rate ratio follows Eq. (5) with the sampled
+      N_core = <sum_i p(r_i)> (within 5 %; O(a) terms from rho != 1);
+    * E0 of the fit E0 + k1 a^2 + k2 a^4 agrees with the exact helium energy
+      within 4 sigma in every scheme."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    res = bench.ascan()["ascan"]
+    for mode, lst in res["speedup"].items():
+        for x in lst:
+            print(f"ascan speedup {mode} alpha={x['alpha']} measured={x['measured']:.4f} eq5={x['eq5']:.4f}",
+                  flush=True)
+            assert x["measured"] == pytest.approx(x["eq5"], rel=0.05)
+    for mode, v in res["modes"].items():
+        print(f"ascan {mode} E0={v['E0']:.6f} +- {v['sigma_E0']:.6f}", flush=True)
+        assert abs(v["E0"] - bench.HE_EXACT) <= 4 * v["sigma_E0"]
+        assert v["sigma_E0"] < 2e-3
