@@ -82,6 +82,8 @@ def load():
         lib.orc_potential.restype = C.c_double
         lib.orc_local_energy.argtypes = [P, P, P, P, P]
         lib.orc_local_energy.restype = C.c_int
+        lib.orc_jastrow_param_grad.argtypes = [P, P, P, P]
+        lib.orc_jastrow_param_grad.restype = C.c_int
         lib.orc_p_switch.argtypes = [P, P, P]
         lib.orc_p_switch.restype = C.c_double
         lib.orc_move.argtypes = [P, P, P, P, C.c_int, P, P]
@@ -193,6 +195,13 @@ class Oracle:
 
     def jastrow(self, pos) -> float:
         return float(self.lib.orc_jastrow(C.byref(self.sys), _ptr(_f64(pos))))
+
+    def jastrow_param_grad(self, pos) -> Tuple[np.ndarray, np.ndarray]:
+        """(dJ/dtheta, dE_L/dtheta) for theta = (b_ee, b_en) at fixed positions."""
+        dJ, dE = np.zeros(2), np.zeros(2)
+        rc = self.lib.orc_jastrow_param_grad(C.byref(self.sys), _ptr(_f64(pos)), _ptr(dJ), _ptr(dE))
+        _check(rc, "jastrow_param_grad")
+        return dJ, dE
 
     def potential(self, pos) -> float:
         return float(self.lib.orc_potential(C.byref(self.sys), _ptr(_f64(pos))))

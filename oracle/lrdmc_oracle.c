@@ -448,6 +448,77 @@ int orc_local_energy(const orc_system *s, const double *pos, double *e_l, double
     return isfinite(*e_l) ? ORC_OK : ORC_ENONFINITE;
 }
 
+/* Derivatives of the Jastrow exponent J and of the local energy with respect
+ * to the two Pade parameters theta = (b_ee, b_en) at fixed positions (the
+ * cusp coefficients stay fixed).  For one pair term u = c r / (1 + b r):
+ *   du/db   = -c r^2 / (1 + b r)^2,
+ *   du'/db  = -2 c r / (1 + b r)^3,  with u' = c / (1 + b r)^2,
+ *   du''/db = -2 c / (1 + b r)^3 + 6 c b r / (1 + b r)^4,  with u'' = -2 c b / (1 + b r)^3;
+ * grad_i J collects u'(r) d/r and lap_i J collects u'' + 2 u'/r over the
+ * partners of electron i, and E_L = -1/2 sum_i [lap_i D/D + 2 grad_i D/D .
+ * grad_i J + lap_i J + |grad_i J|^2] + V, where only the J terms depend on
+ * theta.  Outputs dJ[2] and dEL[2] in the order (b_ee, b_en). */
+int orc_jastrow_param_grad(const orc_system *s, const double *pos, double dJ[2], double dEL[2])
+{
+    int N = s->n_up + s->n_dn, K = orc_nbasis(s), nmax = s->n_up > s->n_dn ? s->n_up : s->n_dn;
+    if (nmax > 64) return ORC_EINVAL;
+    size_t n2 = (size_t)nmax * nmax;
+    double *w = (double *)malloc(sizeof(double) * (5 * (size_t)K + 7 * n2 + 1));
+    if (!w) return ORC_ENOMEM;
+    double *A = w + 5 * K, *Ai = A + n2, *LUw = Ai + n2, *dA = LUw + n2, *lA = dA + 3 * n2;
+    int perm[64];
+    dJ[0] = dJ[1] = dEL[0] = dEL[1] = 0.0;
+    int rc = ORC_OK;
+    for (int sg = 0; sg < 2 && rc == ORC_OK; ++sg) {
+        int n = nspin(s, sg), i0 = first_of(s, sg);
+        if (n == 0) continue;
+        for (int i = 0; i < n; ++i)
+            orbitals_at(s, pos + 3 * (i0 + i), n, A + i * n, dA + 3 * i * n, lA + i * n, w);
+        rc = lu_inverse(A, n, Ai, LUw, perm);
+        if (rc) break;
+        for (int il = 0; il < n; ++il) {
+            int i = i0 + il;
+            double gD[3] = {0, 0, 0};
+            for (int j = 0; j < n; ++j)
+                for (int k = 0; k < 3; ++k) gD[k] += dA[3 * (il * n + j) + k] * Ai[j * n + il];
+            double gJ[3], lJ;
+            jastrow_derivs(s, pos, i, gJ, &lJ);
+            /* theta-derivatives of grad_i J and lap_i J, one parameter at a time */
+            for (int t = 0; t < 2; ++t) {
+                double dg[3] = {0, 0, 0}, dl = 0.0;
+                int np = t == 0 ? N : s->n_nuc;
+                for (int q = 0; q < np; ++q) {
+                    const double *other;
+                    double c, b;
+                    if (t == 0) {
+                        if (q == i) continue;
+                        other = pos + 3 * q;
+                        c = (spin_of(s, i) == spin_of(s, q)) ? 0.25 : 0.5;
+                        b = s->b_ee;
+                    } else {
+                        other = s->R + 3 * q;
+                        c = -s->Z[q];
+                        b = s->b_en;
+                    }
+                    double d[3] = {pos[3 * i] - other[0], pos[3 * i + 1] - other[1], pos[3 * i + 2] - other[2]};
+                    double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                    double den = 1.0 + b * r;
+                    double dup = -2.0 * c * r / (den * den * den);
+                    double dupp = -2.0 * c / (den * den * den) + 6.0 * c * b * r / (den * den * den * den);
+                    for (int k = 0; k < 3; ++k) dg[k] += dup * d[k] / r;
+                    dl += dupp + 2.0 * dup / r;
+                    /* the pair's u once: electron pairs at q > i, every nucleus */
+                    if (t == 1 || q > i) dJ[t] += -c * r * r / (den * den);
+                }
+                double term = 2.0 * ((gD[0] + gJ[0]) * dg[0] + (gD[1] + gJ[1]) * dg[1] + (gD[2] + gJ[2]) * dg[2]) + dl;
+                dEL[t] += -0.5 * term;
+            }
+        }
+    }
+    free(w);
+    return rc;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Lattice moves (main text Eq. (1) and Eq. (3))                              */
 
