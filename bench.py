@@ -147,6 +147,32 @@ def ascan(walkers=16384, t_equil=5.0, t_prod=20.0, alphas=(1.0, 1.25, 1.5, 1.75,
                       "wall_s": time.perf_counter() - t0}}
 
 
+def jastrow_grad_bench(name="ar_a0.1", reps=50):
+    """Throughput of the Jastrow-parameter gradient kernel on the walkers of a
+    workload (one call = E_L, J and both parameter derivatives of every
+    walker), timed with device synchronization around `reps` calls."""
+    import torch
+    from paper_1909_01589_amd import inputs
+    from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_spacing
+    cfg = inputs.get_config(name)
+    s = cfg.system
+    rc, ap, _ = lrdmc_spacing(s.z_max, cfg.a)
+    g = LRDMC(s, cfg.a, ap, rc, cfg.tau, cfg.walkers, seed=cfg.seed, refresh=cfg.refresh)
+    g.set_walkers(inputs.initial_walkers(s, cfg.walkers, cfg.seed), 0)
+    g.run(20)
+    pos = g.get_walkers()["pos"].clone()
+    g.jastrow_grad(pos)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.jastrow_grad(pos)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    g.close()
+    return {"jastrow_grad": {"workload": name, "walkers": cfg.walkers, "ms_per_call": 1e3 * dt,
+                             "walker_gradients_per_s": cfg.walkers / dt}}
+
+
 def copy_probe():
     """A plain device copy of 512 MiB: the reference for scaling the HBM byte
     counters (FETCH_SIZE, WRITE_SIZE) of a profiled run."""
@@ -252,6 +278,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device copy (counter calibration) and exit")
     ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
+    ap.add_argument("--jastrow-grad", action="store_true",
+                    help="only time the Jastrow-parameter gradient kernel and exit")
     ap.add_argument("--ascan", action="store_true",
                     help="only run the spacing scan on helium for the three lattice schemes and exit")
     args = ap.parse_args()
@@ -274,6 +302,9 @@ def main():
         return
     if args.ascan:
         print(json.dumps(ascan()), flush=True)
+        return
+    if args.jastrow_grad:
+        print(json.dumps(jastrow_grad_bench()), flush=True)
         return
 
     cfg, main_res = run_workload(args.workload, args.steps, args.warmup, not args.no_cpu_baseline,

@@ -206,6 +206,21 @@ int lrdmc_reconfigure(const double *log_w, const double *e_loc, int32_t W, doubl
 int lrdmc_set_timing(lrdmc_ctx *ctx, int32_t enable);
 int lrdmc_timing(const lrdmc_ctx *ctx, double *out);
 
+/* Derivatives of the trial function's Jastrow exponent J (Pade e-e and e-n
+ * terms, cusp coefficients fixed) and of the local energy with respect to the
+ * two Pade parameters theta = (b_ee, b_en), at the W walker configurations
+ * pos (device [W][N][3], walker-major): the gradients that optimize the trial
+ * function by variance minimisation before the projection.
+ * out (device [W][6]): {E_L, J, dJ/db_ee, dJ/db_en, dE_L/db_ee, dE_L/db_en}.
+ * Synchronizes the stream.  Errors: LRDMC_EINVAL (NULL), LRDMC_ESINGULAR,
+ * LRDMC_ENONFINITE (walker slot in lrdmc_last_error), LRDMC_EDEVICE. */
+int lrdmc_jastrow_grad(lrdmc_ctx *ctx, const double *pos, double *out, void *stream);
+
+/* Replace the Pade parameters of ctx's Jastrow factor (finite, >= 0).  Later
+ * projections, evaluations and gradients use them; walker states stored from
+ * earlier projections are recomputed.  Errors: LRDMC_EINVAL. */
+int lrdmc_set_jastrow(lrdmc_ctx *ctx, double b_ee, double b_en);
+
 /* Kernel selection.  The library carries, besides the projection kernel for
  * any system, kernels built for fixed system sizes (electrons per spin, basis
  * functions, nuclei; see LRDMC_FIXED_SHAPES in the kernel source).

@@ -1237,6 +1237,95 @@ project_kernel_fixed(KArgs A)
     project_body(A);
 }
 
+// Derivatives with respect to the Pade parameters theta = (b_ee, b_en) of
+// the Jastrow exponent J and of the local energy, for the walkers at pos_in
+// (one workgroup per walker; the cusp coefficients c stay fixed).  With
+// q = 1 / (1 + b r) a pair term u = c r q has du/db = -c r^2 q^2; its part
+// u'(r) d / r of grad_i J changes by -2 c q^3 d and its part u'' + 2 u'/r of
+// lap_i J by -6 c q^4.  E_L depends on theta through
+// -1/2 sum_i [2 (grad_i D/D + grad_i J) . d grad_i J + d lap_i J].
+// out[slot][6] = {E_L, J, dJ/db_ee, dJ/db_en, dE_L/db_ee, dE_L/db_en}.
+__global__ void __launch_bounds__(kMaxThreads) jastrow_grad_kernel(KArgs A, double *out)
+{
+    extern __shared__ double lds[];
+    __shared__ int sflag[8];
+    const Layout &L = A.L;
+    const int tid = threadIdx.x, NT = A.nt, slot = blockIdx.x, N = A.N;
+    double *pos = lds + L.pos;
+    if (tid == 0) sflag[6] = 0;
+    __syncthreads();
+    for (int t = tid; t < 3 * N; t += NT) {
+        const double v = A.pos_in[(size_t)slot * 3 * N + t];
+        pos[t] = v;
+        if (!isfinite(v)) sflag[6] = 1;
+    }
+    __syncthreads();
+    if (sflag[6]) {
+        if (tid == 0) report(A.err, kErrNonFinite, slot);
+        return;
+    }
+    double EL, LAP = 0.0, V;
+    double *dphi = A.state_out + (size_t)slot * A.state_len + A.dphi_at;
+    const int rc = walker_setup(A, lds, dphi, sflag, EL, LAP, V);
+    if (rc) {
+        if (tid == 0) report(A.err, rc, slot);
+        return;
+    }
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // J, dJ/db_ee, dJ/db_en, dE/db_ee, dE/db_en
+    for (int i = tid; i < N; i += NT) {
+        const double *gD = lds + L.gD + 4 * i, *gJ = lds + L.gJ + 4 * i;
+        const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+        const bool up = i < A.n_up;
+        for (int t = 0; t < 2; ++t) {
+            double dg[3] = {0.0, 0.0, 0.0}, dl = 0.0, dj = 0.0, jv = 0.0;
+            const int np = t == 0 ? N : A.n_nuc;
+            for (int q = 0; q < np; ++q) {
+                double dx, dy, dz, c, b;
+                if (t == 0) {
+                    if (q == i) continue;
+                    dx = xi - pos[3 * q]; dy = yi - pos[3 * q + 1]; dz = zi - pos[3 * q + 2];
+                    c = ((q < A.n_up) == up) ? 0.25 : 0.5;
+                    b = A.b_ee;
+                } else {
+                    const auto *R = cst(A.Rnuc) + 3 * q;
+                    dx = xi - R[0]; dy = yi - R[1]; dz = zi - R[2];
+                    c = -cst(A.Znuc)[q];
+                    b = A.b_en;
+                }
+                const double r = sqrt(dx * dx + dy * dy + dz * dz);
+                const double qq = 1.0 / (1.0 + b * r), q2 = qq * qq, q3 = q2 * qq;
+                dg[0] += -2.0 * c * q3 * dx;
+                dg[1] += -2.0 * c * q3 * dy;
+                dg[2] += -2.0 * c * q3 * dz;
+                dl += -6.0 * c * q2 * q2;
+                if (t == 1 || q > i) {
+                    dj += -c * r * r * q2;
+                    jv += c * r * qq;
+                }
+            }
+            acc[0] += jv;
+            acc[1 + t] += dj;
+            acc[3 + t] += -0.5 * (2.0 * ((gD[0] + gJ[0]) * dg[0] + (gD[1] + gJ[1]) * dg[1] +
+                                         (gD[2] + gJ[2]) * dg[2]) + dl);
+        }
+    }
+    // the table region is free after the walker setup (at least 76 doubles:
+    // 16 per summed value)
+    double s3[3] = {acc[0], acc[1], acc[2]}, s2[2] = {acc[3], acc[4]};
+    block_sum<3>(s3, lds + L.xs);
+    block_sum<2>(s2, lds + L.xs);   // its first barrier ends the reads of the first sum
+    if (tid == 0) {
+        double *o = out + (size_t)slot * 6;
+        o[0] = EL;
+        o[1] = s3[0];
+        o[2] = s3[1];
+        o[3] = s3[2];
+        o[4] = s2[0];
+        o[5] = s2[1];
+        if (!isfinite(EL)) report(A.err, kErrNonFinite, slot);
+    }
+}
+
 // Fixed-population reconfiguration of W walkers by systematic resampling
 // (one workgroup).  cw: W-double scratch for the cumulative weights.
 __global__ void __launch_bounds__(1024) reconfigure_kernel(const double *logw, const double *el,
@@ -1895,6 +1984,34 @@ int lrdmc_eval_moves(lrdmc_ctx *c, const double *pos, double *rho, double *k, do
     int rc = launch_project(c, st, pos, nullptr, nullptr, 1, rho, k, diag);
     if (rc) return rc;
     return check_kernel_error(c, st);
+}
+
+int lrdmc_jastrow_grad(lrdmc_ctx *c, const double *pos, double *out, void *stream)
+{
+    if (!c || !pos || !out) return fail(c, LRDMC_EINVAL, "lrdmc_jastrow_grad: NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    KArgs A = base_args(c);
+    A.pos_in = pos;
+    A.state_len = c->state_len;
+    A.dphi_at = c->dphi_at;
+    A.state_out = c->d_state[c->cur ^ 1];   // derivative rows as scratch, as in lrdmc_eval_moves
+    if (c->lds_bytes > 65536)
+        HIP_TRY(c, hipFuncSetAttribute((const void *)jastrow_grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)c->lds_bytes));
+    hipLaunchKernelGGL(jastrow_grad_kernel, dim3(c->W), dim3(c->nt), c->lds_bytes, st, A, out);
+    HIP_TRY(c, hipGetLastError());
+    return check_kernel_error(c, st);
+}
+
+int lrdmc_set_jastrow(lrdmc_ctx *c, double b_ee, double b_en)
+{
+    if (!c) return fail(nullptr, LRDMC_EINVAL, "lrdmc_set_jastrow: NULL context");
+    if (!(b_ee >= 0.0) || !(b_en >= 0.0) || !std::isfinite(b_ee) || !std::isfinite(b_en))
+        return fail(c, LRDMC_EINVAL, "lrdmc_set_jastrow: need finite b_ee >= 0 and b_en >= 0");
+    c->b_ee = b_ee;
+    c->b_en = b_en;
+    c->state_ok = false;   // stored Jastrow sums belong to the old parameters
+    return LRDMC_OK;
 }
 
 int lrdmc_reconfigure(const double *log_w, const double *e_loc, int32_t W, double xi, int32_t *idx, double *stats,

@@ -55,7 +55,7 @@ class lrdmc_params(C.Structure):
 _lib = None
 EXPORTS = ("lrdmc_spacing", "lrdmc_spacing_pade", "lrdmc_create", "lrdmc_set_walkers", "lrdmc_project", "lrdmc_branch",
            "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure",
-           "lrdmc_use_generic", "lrdmc_is_specialized", "lrdmc_set_timing", "lrdmc_timing", "lrdmc_generation",
+           "lrdmc_jastrow_grad", "lrdmc_set_jastrow", "lrdmc_use_generic", "lrdmc_is_specialized", "lrdmc_set_timing", "lrdmc_timing", "lrdmc_generation",
            "lrdmc_last_error", "lrdmc_destroy")
 
 
@@ -78,6 +78,8 @@ def load():
     lib.lrdmc_get_walkers.argtypes = [P, P, P, P, P, P]
     lib.lrdmc_eval_moves.argtypes = [P, P, P, P, P, P]
     lib.lrdmc_reconfigure.argtypes = [P, P, I32, D, P, P, P]
+    lib.lrdmc_jastrow_grad.argtypes = [P, P, P, P]
+    lib.lrdmc_set_jastrow.argtypes = [P, D, D]
     lib.lrdmc_use_generic.argtypes = [P, I32]
     lib.lrdmc_is_specialized.argtypes = [P]
     lib.lrdmc_is_specialized.restype = I32
@@ -91,7 +93,8 @@ def load():
     lib.lrdmc_destroy.restype = None
     for name in ("lrdmc_spacing", "lrdmc_spacing_pade", "lrdmc_create", "lrdmc_set_walkers", "lrdmc_project", "lrdmc_branch",
                  "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure",
-                 "lrdmc_use_generic", "lrdmc_set_timing", "lrdmc_timing"):
+                 "lrdmc_jastrow_grad", "lrdmc_set_jastrow", "lrdmc_use_generic", "lrdmc_set_timing",
+                 "lrdmc_timing"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -200,6 +203,15 @@ def lrdmc_reconfigure(log_w, e_loc, xi: float, idx, stats=None, stream=None):
                                     _dptr(stats, torch.float64), _stream(stream)))
 
 
+def lrdmc_jastrow_grad(ctx, pos, out, stream=None):
+    _check(load().lrdmc_jastrow_grad(ctx, _dptr(pos, torch.float64), _dptr(out, torch.float64),
+                                     _stream(stream)), ctx)
+
+
+def lrdmc_set_jastrow(ctx, b_ee: float, b_en: float):
+    _check(load().lrdmc_set_jastrow(ctx, float(b_ee), float(b_en)), ctx)
+
+
 def lrdmc_use_generic(ctx, enable: bool = True):
     _check(load().lrdmc_use_generic(ctx, 1 if enable else 0), ctx)
 
@@ -302,6 +314,18 @@ class LRDMC:
         nm = torch.empty(self.W, dtype=torch.int32, device=self.device)
         lrdmc_get_walkers(self.ctx, pos, lw, el, nm)
         return dict(pos=pos, log_w=lw, e_l=el, n_moves=nm)
+
+    def set_jastrow(self, b_ee: float, b_en: float):
+        lrdmc_set_jastrow(self.ctx, b_ee, b_en)
+
+    def jastrow_grad(self, pos):
+        """[W][6]: E_L, J, dJ/db_ee, dJ/db_en, dE_L/db_ee, dE_L/db_en."""
+        t = torch.as_tensor(pos, dtype=torch.float64).to(self.device).contiguous()
+        if tuple(t.shape) != (self.W, self.N, 3):
+            raise ValueError(f"positions must be [{self.W}, {self.N}, 3]")
+        out = self._f64(self.W, 6)
+        lrdmc_jastrow_grad(self.ctx, t, out)
+        return out
 
     def eval_moves(self, pos):
         t = torch.as_tensor(pos, dtype=torch.float64).to(self.device).contiguous()
