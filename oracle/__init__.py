@@ -44,6 +44,7 @@ class _Sys(C.Structure):
         ("shell_alpha", C.c_void_p),
         ("n_orb", C.c_int32), ("mo", C.c_void_p),
         ("b_ee", C.c_double), ("b_en", C.c_double),
+        ("ftab", C.c_void_p), ("ftab_n", C.c_int32), ("ftab_rcut", C.c_double),
     ]
 
 
@@ -83,6 +84,8 @@ def load():
         lib.orc_local_energy.argtypes = [P, P, P, P, P]
         lib.orc_local_energy.restype = C.c_int
         lib.orc_jastrow_param_grad.argtypes = [P, P, P, P]
+        lib.orc_corr.argtypes = [P, C.c_int, C.c_double, P]
+        lib.orc_corr.restype = None
         lib.orc_jastrow_param_grad.restype = C.c_int
         lib.orc_p_switch.argtypes = [P, P, P]
         lib.orc_p_switch.restype = C.c_double
@@ -125,16 +128,27 @@ class Oracle:
 
     def __init__(self, system, a: float, a_prime: float, r_c: float,
                  z_heavy: Optional[float] = None, tau: float = 0.01,
-                 seed: int = 0, rotate: int = 1, switch_form: int = 0, grids: int = 2):
+                 seed: int = 0, rotate: int = 1, switch_form: int = 0, grids: int = 2,
+                 ftab: Optional[np.ndarray] = None, ftab_rcut: float = 0.0):
+        """ftab: optional learned Jastrow correction, [2][G][3] = {F, F', F''}
+        at G nodes on [0, ftab_rcut] (type 0: electron pairs, 1: electron-
+        nucleus pairs, scaled by Z)."""
         self.lib = load()
         self.system = system
+        self.ftab = None if ftab is None else np.ascontiguousarray(ftab, dtype=np.float64)
+        self.ftab_rcut = float(ftab_rcut)
+        if self.ftab is not None and (self.ftab.ndim != 3 or self.ftab.shape[0] != 2 or self.ftab.shape[2] != 3
+                                      or self.ftab.shape[1] < 2 or not self.ftab_rcut > 0):
+            raise ValueError("ftab must be [2][G>=2][3] with ftab_rcut > 0")
         # keep arrays alive for the lifetime of the struct
         self._keep = [system.Z, system.R, system.shell_nuc, system.shell_l,
-                      system.shell_alpha, system.mo]
+                      system.shell_alpha, system.mo, self.ftab]
         self.sys = _Sys(system.n_nuc, _ptr(system.Z), _ptr(system.R), system.n_up,
                         system.n_dn, system.n_shell, _ptr(system.shell_nuc),
                         _ptr(system.shell_l), _ptr(system.shell_alpha), system.n_orb,
-                        _ptr(system.mo), system.b_ee, system.b_en)
+                        _ptr(system.mo), system.b_ee, system.b_en,
+                        None if self.ftab is None else self.ftab.ctypes.data,
+                        0 if self.ftab is None else self.ftab.shape[1], self.ftab_rcut)
         zh = float(np.max(system.Z)) if z_heavy is None else float(z_heavy)
         if switch_form not in (0, 1) or grids not in (1, 2):
             raise ValueError("switch_form must be 0 (Gaussian) or 1 (Pade), grids 1 or 2")
@@ -148,7 +162,14 @@ class Oracle:
         d = {f: getattr(self.prm, f) for f, _ in _Prm._fields_ if f != "pad"}
         d.update(kw)
         return Oracle(self.system, d["a"], d["a_prime"], d["r_c"], d["z_heavy"],
-                      d["tau"], d["seed"], d["rotate"], d["switch_form"], d["grids"])
+                      d["tau"], d["seed"], d["rotate"], d["switch_form"], d["grids"],
+                      self.ftab, self.ftab_rcut)
+
+    def corr(self, kind: int, r: float) -> np.ndarray:
+        """Learned correction of type kind (0 e-e, 1 e-n) at r: (F, F', F'')."""
+        out = np.zeros(3)
+        self.lib.orc_corr(C.byref(self.sys), int(kind), C.c_double(r), _ptr(out))
+        return out
 
     # -- random numbers ---------------------------------------------------
     def philox(self, ctr, key) -> np.ndarray:

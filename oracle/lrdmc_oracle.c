@@ -44,6 +44,14 @@ typedef struct {
     int32_t n_orb;
     const double *mo;         /* [K][n_orb] */
     double b_ee, b_en;
+    /* optional learned Jastrow correction (NULL: Pade only): F_ee(r) is added
+     * to every electron pair term, Z_I F_en(r) to every electron-nucleus
+     * term, for r < ftab_rcut; F is the piecewise quintic Hermite
+     * interpolant of the table ftab[2][ftab_n][3] = {F, F', F''} at the
+     * nodes r_k = k ftab_rcut / (ftab_n - 1) (type 0: e-e, 1: e-n). */
+    const double *ftab;
+    int32_t ftab_n;
+    double ftab_rcut;
 } orc_system;
 
 typedef struct {
@@ -287,6 +295,56 @@ static int lu_inverse(const double *A, int n, double *X, double *work, int *perm
 
 static int spin_of(const orc_system *s, int i) { return i < s->n_up ? 0 : 1; }
 
+/* The quintic Hermite basis on t in [0, 1] that matches value, first and
+ * second derivative at both ends (the interpolant is C^2 across nodes):
+ * p(t) = f0 H0 + f0' H1 + f0'' H2 + f1 H3 + f1' H4 + f1'' H5 in units of
+ * the interval (derivatives scaled by h, h^2).  Also its first and second
+ * t-derivatives. */
+static void hermite5(double t, double H[6], double dH[6], double d2H[6])
+{
+    double t2 = t * t, t3 = t2 * t, t4 = t3 * t, t5 = t4 * t;
+    H[0] = 1.0 - 10.0 * t3 + 15.0 * t4 - 6.0 * t5;
+    H[1] = t - 6.0 * t3 + 8.0 * t4 - 3.0 * t5;
+    H[2] = 0.5 * (t2 - 3.0 * t3 + 3.0 * t4 - t5);
+    H[3] = 10.0 * t3 - 15.0 * t4 + 6.0 * t5;
+    H[4] = -4.0 * t3 + 7.0 * t4 - 3.0 * t5;
+    H[5] = 0.5 * (t3 - 2.0 * t4 + t5);
+    dH[0] = -30.0 * t2 + 60.0 * t3 - 30.0 * t4;
+    dH[1] = 1.0 - 18.0 * t2 + 32.0 * t3 - 15.0 * t4;
+    dH[2] = 0.5 * (2.0 * t - 9.0 * t2 + 12.0 * t3 - 5.0 * t4);
+    dH[3] = 30.0 * t2 - 60.0 * t3 + 30.0 * t4;
+    dH[4] = -12.0 * t2 + 28.0 * t3 - 15.0 * t4;
+    dH[5] = 0.5 * (3.0 * t2 - 8.0 * t3 + 5.0 * t4);
+    d2H[0] = -60.0 * t + 180.0 * t2 - 120.0 * t3;
+    d2H[1] = -36.0 * t + 96.0 * t2 - 60.0 * t3;
+    d2H[2] = 0.5 * (2.0 - 18.0 * t + 36.0 * t2 - 20.0 * t3);
+    d2H[3] = 60.0 * t - 180.0 * t2 + 120.0 * t3;
+    d2H[4] = -24.0 * t + 84.0 * t2 - 60.0 * t3;
+    d2H[5] = 0.5 * (6.0 * t - 24.0 * t2 + 20.0 * t3);
+}
+
+/* Learned correction of table type (0: e-e, 1: e-n) at distance r, with its
+ * first and second r-derivatives; zero without a table or beyond the cutoff. */
+void orc_corr(const orc_system *s, int type, double r, double out[3])
+{
+    out[0] = out[1] = out[2] = 0.0;
+    if (!s->ftab || s->ftab_n < 2 || !(r < s->ftab_rcut)) return;
+    double h = s->ftab_rcut / (s->ftab_n - 1);
+    double x = r / h;
+    int k = (int)floor(x);
+    if (k > s->ftab_n - 2) k = s->ftab_n - 2;
+    double t = x - k;
+    const double *a = s->ftab + 3 * ((size_t)type * s->ftab_n + k), *b = a + 3;
+    double c[6] = {a[0], h * a[1], h * h * a[2], b[0], h * b[1], h * h * b[2]};
+    double H[6], dH[6], d2H[6];
+    hermite5(t, H, dH, d2H);
+    for (int q = 0; q < 6; ++q) {
+        out[0] += c[q] * H[q];
+        out[1] += c[q] * dH[q] / h;
+        out[2] += c[q] * d2H[q] / (h * h);
+    }
+}
+
 static double dist(const double *a, const double *b)
 {
     double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
@@ -301,11 +359,16 @@ double orc_jastrow(const orc_system *s, const double *pos)
         for (int j = i + 1; j < N; ++j) {
             double c = (spin_of(s, i) == spin_of(s, j)) ? 0.25 : 0.5;
             double r = dist(pos + 3 * i, pos + 3 * j);
-            J += c * r / (1.0 + s->b_ee * r);
+            double F[3];
+            orc_corr(s, 0, r, F);
+            J += c * r / (1.0 + s->b_ee * r) + F[0];
         }
         for (int I = 0; I < s->n_nuc; ++I) {
             double r = dist(pos + 3 * i, s->R + 3 * I);
+            double F[3];
+            orc_corr(s, 1, r, F);
             J -= s->Z[I] * r / (1.0 + s->b_en * r);
+            J += s->Z[I] * F[0];
         }
     }
     return J;
@@ -323,8 +386,10 @@ static void jastrow_derivs(const orc_system *s, const double *pos, int i, double
         double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1], pos[3 * i + 2] - pos[3 * j + 2]};
         double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         double q = 1.0 + s->b_ee * r;
-        double up = c / (q * q);                 /* u'(r)  */
-        double upp = -2.0 * c * s->b_ee / (q * q * q); /* u''(r) */
+        double F[3];
+        orc_corr(s, 0, r, F);
+        double up = c / (q * q) + F[1];                       /* u'(r)  */
+        double upp = -2.0 * c * s->b_ee / (q * q * q) + F[2]; /* u''(r) */
         for (int k = 0; k < 3; ++k) g[k] += up * d[k] / r;
         L += upp + 2.0 * up / r;
     }
@@ -333,8 +398,10 @@ static void jastrow_derivs(const orc_system *s, const double *pos, int i, double
         double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         double q = 1.0 + s->b_en * r;
         double Z = s->Z[I];
-        double up = -Z / (q * q);
-        double upp = 2.0 * Z * s->b_en / (q * q * q);
+        double F[3];
+        orc_corr(s, 1, r, F);
+        double up = -Z / (q * q) + Z * F[1];
+        double upp = 2.0 * Z * s->b_en / (q * q * q) + Z * F[2];
         for (int k = 0; k < 3; ++k) g[k] += up * d[k] / r;
         L += upp + 2.0 * up / r;
     }

@@ -279,3 +279,22 @@ CONFIGS = _configs()
 def get_config(name: str, **overrides) -> Config:
     c = CONFIGS[name]
     return replace(c, **overrides) if overrides else c
+
+
+def neural_weights(seed: int = 0, hidden: int = 64, out_scale: float = 0.1) -> dict:
+    """Seeded weights of the two correction networks (electron pairs "ee",
+    electron-nucleus pairs "en"), each 1 -> hidden -> hidden -> 1: W1[h],
+    b1[h], W2[h][h], b2[h], w3[h], b3 (float64 arrays; scaled normal draws,
+    the output layer damped by out_scale)."""
+    rng = np.random.default_rng([seed, 77])
+    out = {}
+    for kind in ("ee", "en"):
+        out[kind] = {
+            "W1": rng.normal(size=hidden) * 2.0,
+            "b1": rng.normal(size=hidden) * 0.5,
+            "W2": rng.normal(size=(hidden, hidden)) / np.sqrt(hidden),
+            "b2": rng.normal(size=hidden) * 0.1,
+            "w3": rng.normal(size=hidden) / np.sqrt(hidden) * out_scale,
+            "b3": np.array(0.0),
+        }
+    return out
