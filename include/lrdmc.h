@@ -221,6 +221,38 @@ int lrdmc_jastrow_grad(lrdmc_ctx *ctx, const double *pos, double *out, void *str
  * earlier projections are recomputed.  Errors: LRDMC_EINVAL. */
 int lrdmc_set_jastrow(lrdmc_ctx *ctx, double b_ee, double b_en);
 
+/* Learned correction of the Jastrow factor.  The supplement's computational
+ * details use Jastrow-Slater trial functions whose Jastrow parameters are all
+ * optimized; this adds a radial function learned by variance minimisation to
+ * each pair term: J += sum_{i<j} F_ee(r_ij) + sum_{i,I} Z_I F_en(r_iI), with
+ * F = 0 from r_cut on.  F is given by its node table
+ * tab[2][n_nodes][3] = {F, F', F''} at r_k = k r_cut / (n_nodes - 1)
+ * (type 0: electron pairs, 1: electron-nucleus) and is, between nodes, the
+ * quintic that matches value, first and second derivative at both ends
+ * (twice continuously differentiable).  The Pade cusps stay exact when
+ * F'(0) = 0.  tab is a host array (on_device = 0, copied) or a device
+ * array (on_device = 1, read on `stream`); the call synchronizes the stream.
+ * tab = NULL or n_nodes = 0 removes the correction.  Later projections,
+ * evaluations and gradients use the table; stored walker states are
+ * recomputed.  Errors: LRDMC_EINVAL (2 <= n_nodes <= LRDMC_MAX_TABLE_NODES,
+ * finite r_cut > 0, every entry finite; after a non-finite entry the
+ * correction is removed), LRDMC_ENOMEM, LRDMC_EDEVICE. */
+#define LRDMC_MAX_TABLE_NODES 4096
+int lrdmc_set_jastrow_table(lrdmc_ctx *ctx, const double *tab, int32_t n_nodes, double r_cut,
+                            int32_t on_device, void *stream);
+
+/* Gradient with respect to the node table of the learned correction:
+ * gtab (device [2][n_nodes][3], overwritten) = d/dtab sum_w (c_j[w] J_w +
+ * c_e[w] E_L,w) over the W walker configurations pos (device [W][N][3]);
+ * c_j, c_e are device [W] (either may be NULL for zero).  J and E_L are the
+ * values lrdmc_jastrow_grad returns; the backward pass of a loss on them.
+ * Accumulated with floating-point atomics: the summation order varies from
+ * call to call (differences at rounding level).  Synchronizes the stream.
+ * Errors: LRDMC_EINVAL (NULL, no table set), LRDMC_ESINGULAR,
+ * LRDMC_ENONFINITE, LRDMC_EDEVICE. */
+int lrdmc_jastrow_table_grad(lrdmc_ctx *ctx, const double *pos, const double *c_j, const double *c_e,
+                             double *gtab, void *stream);
+
 /* Kernel selection.  The library carries, besides the projection kernel for
  * any system, kernels built for fixed system sizes (electrons per spin, basis
  * functions, nuclei; see LRDMC_FIXED_SHAPES in the kernel source).

@@ -171,6 +171,11 @@ struct KArgs {
     const ChainDesc *chains;       // [n_chain]
     const double *moT;             // [ns][K]: occupied MO coefficients, orbital-major
     double b_ee, b_en, v_nn;
+    // learned pair correction (kernels built with CORR): on interval k of
+    // width 1 / f_hinv, F = sum_p fcoef[type][k][p] t^p with t in [0, 1)
+    const double *fcoef;           // [2][f_nint][6], type 0 e-e, 1 e-n
+    int f_nint;
+    double f_hinv, f_rcut;
     // lattice
     double a, ap, inv_a2, inv_ap2, tau;
     double sw_c;                   // 1 / (2 r_c^2) (Gaussian switch) or r_c^2 (Pade switch)
@@ -467,14 +472,24 @@ __device__ __forceinline__ double rsqrt_nr(double a)
 // u(r) for the move table: one Newton-Raphson step on each hardware estimate
 // (estimates within 2^-24 on gfx950, so about 5e-15 relative after the
 // step), enough for the ratio exp(dJ).
-__device__ __forceinline__ double pade_u(double c, double b, double d2)
+__device__ __forceinline__ double rsqrt_move(double d2)
 {
-    double y = __builtin_amdgcn_rsq(d2);
-    y = fma(y, fma(-0.5 * d2 * y, y, 0.5), y);
+    const double y = __builtin_amdgcn_rsq(d2);
+    return fma(y, fma(-0.5 * d2 * y, y, 0.5), y);
+}
+
+// u = c / (1 / r + b) from y = 1 / r.
+__device__ __forceinline__ double pade_u_y(double c, double b, double y)
+{
     const double a = y + b;
     double x = __builtin_amdgcn_rcp(a);
     x = fma(x, fma(-a, x, 1.0), x);
     return c * x;
+}
+
+__device__ __forceinline__ double pade_u(double c, double b, double d2)
+{
+    return pade_u_y(c, b, rsqrt_move(d2));
 }
 
 struct PairD {
@@ -498,8 +513,61 @@ __device__ __forceinline__ PairD pade_d(double c, double b, double d2)
     return p;
 }
 
+// The learned correction F of pair type `type` at distance r (zero from
+// f_rcut on): the quintic of r's interval in Horner form, with F' and F''
+// when D asks for them.
+template <int D>
+__device__ __forceinline__ void corr_eval(const KArgs &A, int type, double r, double F[3])
+{
+    F[0] = F[1] = F[2] = 0.0;
+    if (r < A.f_rcut) {
+        const double x = r * A.f_hinv;
+        const int k = min((int)x, A.f_nint - 1);
+        const double t = x - (double)k;
+        const double2 *p = reinterpret_cast<const double2 *>(A.fcoef + 6 * (type * A.f_nint + k));
+        const double2 q0 = p[0], q1 = p[1], q2 = p[2];
+        const double c0 = q0.x, c1 = q0.y, c2 = q1.x, c3 = q1.y, c4 = q2.x, c5 = q2.y;
+        F[0] = fma(t, fma(t, fma(t, fma(t, fma(t, c5, c4), c3), c2), c1), c0);
+        if (D >= 1)
+            F[1] = fma(t, fma(t, fma(t, fma(t, 5.0 * c5, 4.0 * c4), 3.0 * c3), 2.0 * c2), c1) * A.f_hinv;
+        if (D >= 2)
+            F[2] = fma(t, fma(t, fma(t, 20.0 * c5, 12.0 * c4), 6.0 * c3), 2.0 * c2) * (A.f_hinv * A.f_hinv);
+    }
+}
+
+// u of a pair with the correction scaled by s (1 for electron pairs, Z for
+// an electron and a nucleus; 0 drops the pair).
+template <bool CORR>
+__device__ __forceinline__ double pair_u(const KArgs &A, double c, double b, double d2, int type, double s)
+{
+    if constexpr (CORR) {
+        const double y = rsqrt_move(d2);
+        double F[3];
+        corr_eval<0>(A, type, d2 * y, F);
+        return fma(s, F[0], pade_u_y(c, b, y));
+    } else {
+        return pade_u(c, b, d2);
+    }
+}
+
+template <bool CORR>
+__device__ __forceinline__ PairD pair_d(const KArgs &A, double c, double b, double d2, int type, double s)
+{
+    PairD p = pade_d(c, b, d2);
+    if constexpr (CORR) {
+        double F[3];
+        corr_eval<2>(A, type, d2 * p.y, F);
+        const double f1 = s * F[1] * p.y;
+        p.u = fma(s, F[0], p.u);
+        p.f += f1;
+        p.lap += fma(s, F[2], 2.0 * f1);
+    }
+    return p;
+}
+
 // Jastrow terms containing electron i when it sits at ra and at rb (the two
 // points of a +/- move pair; the other electrons fixed).
+template <bool CORR>
 __device__ __forceinline__ void jastrow_point2(const KArgs &A, const double *pos, int i, const double ra[3],
                                                const double rb[3], double &out_a, double &out_b)
 {
@@ -509,32 +577,34 @@ __device__ __forceinline__ void jastrow_point2(const KArgs &A, const double *pos
     for (; j + 1 < A.N; j += 2) {
         const double c0 = j == i ? 0.0 : (((j < A.n_up) == up) ? 0.25 : 0.5);
         const double c1 = j + 1 == i ? 0.0 : (((j + 1 < A.n_up) == up) ? 0.25 : 0.5);
+        const double s0 = j == i ? 0.0 : 1.0, s1 = j + 1 == i ? 0.0 : 1.0;
         const double x0 = pos[3 * j], y0 = pos[3 * j + 1], z0 = pos[3 * j + 2];
         const double x1 = pos[3 * j + 3], y1 = pos[3 * j + 4], z1 = pos[3 * j + 5];
         double dx = ra[0] - x0, dy = ra[1] - y0, dz = ra[2] - z0;
-        a0 += pade_u(c0, A.b_ee, dx * dx + dy * dy + dz * dz);
+        a0 += pair_u<CORR>(A, c0, A.b_ee, dx * dx + dy * dy + dz * dz, 0, s0);
         dx = rb[0] - x0; dy = rb[1] - y0; dz = rb[2] - z0;
-        b0 += pade_u(c0, A.b_ee, dx * dx + dy * dy + dz * dz);
+        b0 += pair_u<CORR>(A, c0, A.b_ee, dx * dx + dy * dy + dz * dz, 0, s0);
         dx = ra[0] - x1; dy = ra[1] - y1; dz = ra[2] - z1;
-        a1 += pade_u(c1, A.b_ee, dx * dx + dy * dy + dz * dz);
+        a1 += pair_u<CORR>(A, c1, A.b_ee, dx * dx + dy * dy + dz * dz, 0, s1);
         dx = rb[0] - x1; dy = rb[1] - y1; dz = rb[2] - z1;
-        b1 += pade_u(c1, A.b_ee, dx * dx + dy * dy + dz * dz);
+        b1 += pair_u<CORR>(A, c1, A.b_ee, dx * dx + dy * dy + dz * dz, 0, s1);
     }
     if (j < A.N) {
         const double c0 = j == i ? 0.0 : (((j < A.n_up) == up) ? 0.25 : 0.5);
+        const double s0 = j == i ? 0.0 : 1.0;
         const double x0 = pos[3 * j], y0 = pos[3 * j + 1], z0 = pos[3 * j + 2];
         double dx = ra[0] - x0, dy = ra[1] - y0, dz = ra[2] - z0;
-        a0 += pade_u(c0, A.b_ee, dx * dx + dy * dy + dz * dz);
+        a0 += pair_u<CORR>(A, c0, A.b_ee, dx * dx + dy * dy + dz * dz, 0, s0);
         dx = rb[0] - x0; dy = rb[1] - y0; dz = rb[2] - z0;
-        b0 += pade_u(c0, A.b_ee, dx * dx + dy * dy + dz * dz);
+        b0 += pair_u<CORR>(A, c0, A.b_ee, dx * dx + dy * dy + dz * dz, 0, s0);
     }
     for (int I = 0; I < A.n_nuc; ++I) {
         const auto *R = cst(A.Rnuc) + 3 * I;
         const double c = -cst(A.Znuc)[I];
         double dx = ra[0] - R[0], dy = ra[1] - R[1], dz = ra[2] - R[2];
-        a1 += pade_u(c, A.b_en, dx * dx + dy * dy + dz * dz);
+        a1 += pair_u<CORR>(A, c, A.b_en, dx * dx + dy * dy + dz * dz, 1, -c);
         dx = rb[0] - R[0]; dy = rb[1] - R[1]; dz = rb[2] - R[2];
-        b1 += pade_u(c, A.b_en, dx * dx + dy * dy + dz * dz);
+        b1 += pair_u<CORR>(A, c, A.b_en, dx * dx + dy * dy + dz * dz, 1, -c);
     }
     out_a = a0 + a1;
     out_b = b0 + b1;
@@ -552,6 +622,7 @@ __device__ __forceinline__ void move_position(const KArgs &A, const double *pos,
 
 // Jastrow gradient/Laplacian and own sum of every electron; returns the total
 // potential to every thread.  Segments of `seg` lanes per electron.
+template <bool CORR>
 __device__ __forceinline__ double jastrow_setup(const KArgs &A, double *lds)
 {
     const Layout &L = A.L;
@@ -571,17 +642,20 @@ __device__ __forceinline__ double jastrow_setup(const KArgs &A, double *lds)
             for (int j = sub; j < N + A.n_nuc; j += seg) {
                 if (j == i) continue;
                 double dx, dy, dz, c, b;
+                int type;
                 if (j < N) {
                     dx = xi - pos[3 * j]; dy = yi - pos[3 * j + 1]; dz = zi - pos[3 * j + 2];
                     c = (spin_of(A, j) == si) ? 0.25 : 0.5;
                     b = A.b_ee;
+                    type = 0;
                 } else {
                     const double *R = A.Rnuc + 3 * (j - N);
                     dx = xi - R[0]; dy = yi - R[1]; dz = zi - R[2];
                     c = -A.Znuc[j - N];
                     b = A.b_en;
+                    type = 1;
                 }
-                const PairD pr = pade_d(c, b, dx * dx + dy * dy + dz * dz);
+                const PairD pr = pair_d<CORR>(A, c, b, dx * dx + dy * dy + dz * dz, type, type ? -c : 1.0);
                 g0 += pr.f * dx; g1 += pr.f * dy; g2 += pr.f * dz;
                 lap += pr.lap;
                 jo += pr.u;
@@ -626,6 +700,7 @@ __device__ __forceinline__ double psi_lap_term(const double *d, const double *j)
 // Gauss-Jordan inversion with partial pivoting, Y = C Ainv, determinant and
 // Jastrow derivatives, local energy.  Returns an error code (uniform);
 // EL, LAP (sum_i lap_i Psi/Psi) and V reach every thread.
+template <bool CORR>
 __device__ __forceinline__ int walker_setup(const KArgs &A, double *lds, double *dphi, int *sflag, double &EL, double &LAP,
                             double &V)
 {
@@ -724,7 +799,7 @@ __device__ __forceinline__ int walker_setup(const KArgs &A, double *lds, double 
         Y[i * Kp + mu] = acc;
     }
     det_derivs_all(A, Ainv, dphi, lds + L.gD);
-    V = uni(jastrow_setup(A, lds));     // ends with workgroup barriers
+    V = uni(jastrow_setup<CORR>(A, lds));     // ends with workgroup barriers
     double v[1] = {0.0};
     for (int i = tid; i < N; i += NT) v[0] += psi_lap_term(lds + L.gD + 4 * i, lds + L.gJ + 4 * i);
     block_sum<1>(v, lds + L.red);
@@ -771,6 +846,7 @@ __device__ __forceinline__ void wave_sync()
 // each step evaluates the +/- pair (m, m + 1) along one axis of one grid of
 // one electron.  Returns the sum of the weights; with diag, stores rho and k
 // and accumulates sum k, L^a and V_sf.
+template <bool CORR>
 __device__ __forceinline__ double move_table(const KArgs &A, double *lds, const double *Rm, int c0, int c1,
                                              int *last, double *rho_g, double *k_g, double acc[3], bool diag)
 {
@@ -798,7 +874,7 @@ __device__ __forceinline__ double move_table(const KArgs &A, double *lds, const 
         }
         double rda, rdb, ja, jb;
         basis_dot2(A, ra, rb, Y + i * A.Kp, rda, rdb);
-        jastrow_point2(A, pos, i, ra, rb, ja, jb);
+        jastrow_point2<CORR>(A, pos, i, ra, rb, ja, jb);
         const double jo = Jo[i];
         const double rhoa = rda * exp(ja - jo), rhob = rdb * exp(jb - jo);
         const double ta = 0.5 * ka * (rhoa > 0.0 ? rhoa : 0.0);
@@ -876,6 +952,7 @@ __device__ __forceinline__ double seq_dot(const double *x, const double *y, int 
 //     of kp (Jastrow gradient, Laplacian and own sum of k; the potential
 //     change into the block scalars).
 // Item ranges of different cost start on wavefront boundaries.
+template <bool CORR>
 __device__ __forceinline__ void accept_move(const KArgs &A, double *lds, double *dphi, int k, const double rold[3],
                             const double rnew[3])
 {
@@ -903,8 +980,8 @@ __device__ __forceinline__ void accept_move(const KArgs &A, double *lds, double 
                         const double xi = pos[3 * p], yi = pos[3 * p + 1], zi = pos[3 * p + 2];
                         const double ax = xi - rnew[0], ay = yi - rnew[1], az = zi - rnew[2];
                         const double bx = xi - rold[0], by = yi - rold[1], bz = zi - rold[2];
-                        const PairD pn = pade_d(c, A.b_ee, ax * ax + ay * ay + az * az);
-                        const PairD po = pade_d(c, A.b_ee, bx * bx + by * by + bz * bz);
+                        const PairD pn = pair_d<CORR>(A, c, A.b_ee, ax * ax + ay * ay + az * az, 0, 1.0);
+                        const PairD po = pair_d<CORR>(A, c, A.b_ee, bx * bx + by * by + bz * bz, 0, 1.0);
                         gJ[4 * p] += pn.f * ax - po.f * bx;
                         gJ[4 * p + 1] += pn.f * ay - po.f * by;
                         gJ[4 * p + 2] += pn.f * az - po.f * bz;
@@ -918,7 +995,7 @@ __device__ __forceinline__ void accept_move(const KArgs &A, double *lds, double 
                     const double c = -A.Znuc[p - N];
                     const double dx = rnew[0] - R[0], dy = rnew[1] - R[1], dz = rnew[2] - R[2];
                     const double ex = rold[0] - R[0], ey = rold[1] - R[1], ez = rold[2] - R[2];
-                    const PairD pr = pade_d(c, A.b_en, dx * dx + dy * dy + dz * dz);
+                    const PairD pr = pair_d<CORR>(A, c, A.b_en, dx * dx + dy * dy + dz * dz, 1, -c);
                     o[0] = pr.f * dx; o[1] = pr.f * dy; o[2] = pr.f * dz;
                     o[3] = pr.lap; o[4] = pr.u; o[5] = c * (pr.y - rsqrt_nr(ex * ex + ey * ey + ez * ez));
                 }
@@ -1014,6 +1091,7 @@ __device__ __forceinline__ double local_energy(const KArgs &A, const double *lds
 
 // One workgroup per walker slot: a generation of continuous-time projection,
 // or (eval != 0) the move table at frozen positions.
+template <bool CORR>
 __device__ __forceinline__ void project_body(const KArgs &A)
 {
     extern __shared__ double lds[];
@@ -1053,7 +1131,7 @@ __device__ __forceinline__ void project_body(const KArgs &A)
         V = uni(sb[blob + 1]);
         __syncthreads();
     } else {
-        int rc = walker_setup(A, lds, dphi, sflag, EL, LAP, V);
+        int rc = walker_setup<CORR>(A, lds, dphi, sflag, EL, LAP, V);
         if (rc) {
             if (tid == 0) report(A.err, rc, slot);
             return;
@@ -1067,7 +1145,7 @@ __device__ __forceinline__ void project_body(const KArgs &A)
     if (A.eval) {
         double acc[3] = {0.0, 0.0, 0.0};
         int last = -1;
-        const double part = move_table(A, lds, rng_slot(rng, 0), c0, c1, &last,
+        const double part = move_table<CORR>(A, lds, rng_slot(rng, 0), c0, c1, &last,
                                        A.rho_out ? A.rho_out + (size_t)slot * M : nullptr,
                                        A.k_out ? A.k_out + (size_t)slot * M : nullptr, acc, true);
         double v[4] = {acc[0], acc[1], acc[2], part};
@@ -1094,7 +1172,7 @@ __device__ __forceinline__ void project_body(const KArgs &A)
         const double *R = rng_slot(rng, it);
         int last = -1;
         double dummy[3];
-        const double part = move_table(A, lds, R, c0, c1, &last, nullptr, nullptr, dummy, false);
+        const double part = move_table<CORR>(A, lds, R, c0, c1, &last, nullptr, nullptr, dummy, false);
 
         // inclusive prefix of the per-thread sums within each wavefront; the
         // wavefront totals go to LDS
@@ -1179,7 +1257,7 @@ __device__ __forceinline__ void project_body(const KArgs &A)
             for (int c = 0; c < 3; ++c) rnew[c] = uni(rnew[c]);
             const double rold[3] = {uni(pos[3 * k]), uni(pos[3 * k + 1]), uni(pos[3 * k + 2])};
             __syncthreads();   // every wavefront is done with T and xs
-            accept_move(A, lds, dphi, k, rold, rnew);
+            accept_move<CORR>(A, lds, dphi, k, rold, rnew);
             if (((it + 1) & 7) == 0) refill_rng(A, rng, slot, it + 1);
         }
         __syncthreads();
@@ -1210,9 +1288,10 @@ __device__ __forceinline__ void project_body(const KArgs &A)
 
 // The projection kernel for any system: sizes and LDS offsets come from the
 // arguments.
+template <bool CORR>
 __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) project_kernel(KArgs A)
 {
-    project_body(A);
+    project_body<CORR>(A);
 }
 
 // The same kernel built for one system size: electron counts, basis size and
@@ -1226,7 +1305,7 @@ struct FixedShape {
     static constexpr int NT = threads_for(M);
 };
 
-template <int NUP, int NDN, int KB, int NNUC>
+template <int NUP, int NDN, int KB, int NNUC, bool CORR>
 __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4)))
 project_kernel_fixed(KArgs A)
 {
@@ -1234,7 +1313,7 @@ project_kernel_fixed(KArgs A)
     constexpr Layout L = make_layout(S::N, S::ns, KB, S::Kp, S::M, NNUC, S::NT, 0);
     A.N = S::N; A.n_up = NUP; A.n_dn = NDN; A.ns = S::ns; A.K = KB; A.Kp = S::Kp; A.M = S::M;
     A.n_nuc = NNUC; A.nt = S::NT; A.mpe = 12; A.L = L;
-    project_body(A);
+    project_body<CORR>(A);
 }
 
 // Derivatives with respect to the Pade parameters theta = (b_ee, b_en) of
@@ -1244,7 +1323,10 @@ project_kernel_fixed(KArgs A)
 // u'(r) d / r of grad_i J changes by -2 c q^3 d and its part u'' + 2 u'/r of
 // lap_i J by -6 c q^4.  E_L depends on theta through
 // -1/2 sum_i [2 (grad_i D/D + grad_i J) . d grad_i J + d lap_i J].
-// out[slot][6] = {E_L, J, dJ/db_ee, dJ/db_en, dE_L/db_ee, dE_L/db_en}.
+// out[slot][6] = {E_L, J, dJ/db_ee, dJ/db_en, dE_L/db_ee, dE_L/db_en}.  With
+// CORR, J and E_L include the learned correction (which does not depend on
+// theta).
+template <bool CORR>
 __global__ void __launch_bounds__(kMaxThreads) jastrow_grad_kernel(KArgs A, double *out)
 {
     extern __shared__ double lds[];
@@ -1266,7 +1348,7 @@ __global__ void __launch_bounds__(kMaxThreads) jastrow_grad_kernel(KArgs A, doub
     }
     double EL, LAP = 0.0, V;
     double *dphi = A.state_out + (size_t)slot * A.state_len + A.dphi_at;
-    const int rc = walker_setup(A, lds, dphi, sflag, EL, LAP, V);
+    const int rc = walker_setup<CORR>(A, lds, dphi, sflag, EL, LAP, V);
     if (rc) {
         if (tid == 0) report(A.err, rc, slot);
         return;
@@ -1301,6 +1383,11 @@ __global__ void __launch_bounds__(kMaxThreads) jastrow_grad_kernel(KArgs A, doub
                 if (t == 1 || q > i) {
                     dj += -c * r * r * q2;
                     jv += c * r * qq;
+                    if constexpr (CORR) {
+                        double F[3];
+                        corr_eval<0>(A, t, r, F);
+                        jv += (t ? -c : 1.0) * F[0];
+                    }
                 }
             }
             acc[0] += jv;
@@ -1324,6 +1411,138 @@ __global__ void __launch_bounds__(kMaxThreads) jastrow_grad_kernel(KArgs A, doub
         o[5] = s2[1];
         if (!isfinite(EL)) report(A.err, kErrNonFinite, slot);
     }
+}
+
+// Gradient of sum_w (cJ[w] J_w + cE[w] E_L,w) with respect to the node
+// table {F, F', F''} of the learned correction (adjoint of the Hermite data
+// to interval-polynomial conversion of corr_coef_kernel), accumulated into
+// gtab[2][f_nint + 1][3] with atomic adds.  J is linear in the table: a pair
+// of scale s at distance r adds s F(r).  E_L depends on it through
+// -1/2 sum_i [2 G_i . d grad_i J + d lap_i J] with G_i = grad_i D/D +
+// grad_i J: an electron pair (i, j) along d = (r_i - r_j) / r carries
+// -[(G_i - G_j) . d + 2 / r] dF' - dF'', an electron and a nucleus of charge
+// Z carry -Z [(G_i . d + 1 / r) dF' + dF'' / 2].
+__device__ __forceinline__ void corr_adjoint(const KArgs &A, int type, double r, double wv, double w1, double w2,
+                                             double *gtab)
+{
+    if (!(r < A.f_rcut)) return;
+    const double hinv = A.f_hinv, h = 1.0 / hinv;
+    const double x = r * hinv;
+    const int k = min((int)x, A.f_nint - 1);
+    const double t = x - (double)k;
+    // dL/dm_p for F = sum_p m_p t^p, F' = hinv sum_p p m_p t^(p-1), F'' = hinv^2 ...
+    double tp[6];
+    tp[0] = 1.0;
+    for (int q = 1; q < 6; ++q) tp[q] = tp[q - 1] * t;
+    const double u1 = w1 * hinv, u2 = w2 * hinv * hinv;
+    double mb[6];
+    mb[0] = wv;
+    mb[1] = wv * t + u1;
+    for (int q = 2; q < 6; ++q) mb[q] = wv * tp[q] + u1 * q * tp[q - 1] + u2 * q * (q - 1) * tp[q - 2];
+    const double e0 = 10.0 * mb[3] - 15.0 * mb[4] + 6.0 * mb[5];
+    const double e1 = -4.0 * mb[3] + 7.0 * mb[4] - 3.0 * mb[5];
+    const double e2 = 0.5 * mb[3] - mb[4] + 0.5 * mb[5];
+    double *g = gtab + 3 * (type * (A.f_nint + 1) + k);
+    unsafeAtomicAdd(g + 0, mb[0] - e0);
+    unsafeAtomicAdd(g + 1, (mb[1] - e0 - e1) * h);
+    unsafeAtomicAdd(g + 2, (0.5 * mb[2] - 0.5 * e0 - e1 - e2) * h * h);
+    unsafeAtomicAdd(g + 3, e0);
+    unsafeAtomicAdd(g + 4, e1 * h);
+    unsafeAtomicAdd(g + 5, e2 * h * h);
+}
+
+__global__ void __launch_bounds__(kMaxThreads) jastrow_table_grad_kernel(KArgs A, const double *cJ,
+                                                                         const double *cE, double *gtab)
+{
+    extern __shared__ double lds[];
+    __shared__ int sflag[8];
+    const Layout &L = A.L;
+    const int tid = threadIdx.x, NT = A.nt, slot = blockIdx.x, N = A.N;
+    double *pos = lds + L.pos;
+    if (tid == 0) sflag[6] = 0;
+    __syncthreads();
+    for (int t = tid; t < 3 * N; t += NT) {
+        const double v = A.pos_in[(size_t)slot * 3 * N + t];
+        pos[t] = v;
+        if (!isfinite(v)) sflag[6] = 1;
+    }
+    __syncthreads();
+    if (sflag[6]) {
+        if (tid == 0) report(A.err, kErrNonFinite, slot);
+        return;
+    }
+    double EL, LAP = 0.0, V;
+    double *dphi = A.state_out + (size_t)slot * A.state_len + A.dphi_at;
+    const int rc = walker_setup<true>(A, lds, dphi, sflag, EL, LAP, V);
+    if (rc) {
+        if (tid == 0) report(A.err, rc, slot);
+        return;
+    }
+    const double aj = cJ ? cJ[slot] : 0.0, ae = cE ? cE[slot] : 0.0;
+    const double *gD = lds + L.gD, *gJ = lds + L.gJ;
+    // items: electron pairs i < j (row-major over the strict upper triangle), then (i, I)
+    const int n_ee = N * (N - 1) / 2, n_items = n_ee + N * A.n_nuc;
+    for (int u = tid; u < n_items; u += NT) {
+        int i, j = -1, I = -1;
+        if (u < n_ee) {
+            i = 0;
+            int rem = u;
+            while (rem >= N - 1 - i) { rem -= N - 1 - i; ++i; }
+            j = i + 1 + rem;
+        } else {
+            i = (u - n_ee) / A.n_nuc;
+            I = (u - n_ee) - i * A.n_nuc;
+        }
+        const double *pj = j >= 0 ? pos + 3 * j : A.Rnuc + 3 * I;
+        const double d0 = pos[3 * i] - pj[0], d1 = pos[3 * i + 1] - pj[1], d2 = pos[3 * i + 2] - pj[2];
+        const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2), ir = 1.0 / r;
+        const double Gi0 = gD[4 * i] + gJ[4 * i], Gi1 = gD[4 * i + 1] + gJ[4 * i + 1], Gi2 = gD[4 * i + 2] + gJ[4 * i + 2];
+        if (j >= 0) {
+            const double G0 = Gi0 - gD[4 * j] - gJ[4 * j], G1 = Gi1 - gD[4 * j + 1] - gJ[4 * j + 1],
+                         G2 = Gi2 - gD[4 * j + 2] - gJ[4 * j + 2];
+            const double gd = (G0 * d0 + G1 * d1 + G2 * d2) * ir;
+            corr_adjoint(A, 0, r, aj, -ae * (gd + 2.0 * ir), -ae, gtab);
+        } else {
+            const double Z = A.Znuc[I];
+            const double gd = (Gi0 * d0 + Gi1 * d1 + Gi2 * d2) * ir;
+            corr_adjoint(A, 1, r, aj * Z, -ae * Z * (gd + ir), -0.5 * ae * Z, gtab);
+        }
+    }
+    if (tid == 0 && !isfinite(EL)) report(A.err, kErrNonFinite, slot);
+}
+
+// Interval polynomials of the learned correction from its node table
+// tab[2][G][3] = {F, F', F''} at r_k = k h: on [r_k, r_k+1] the quintic in
+// t = (r - r_k) / h that matches value, first and second derivative at both
+// ends (so F is C^2 across nodes).  With the t-derivatives A1 = h F'_k,
+// A2 = h^2 F''_k (B1, B2 at k + 1) the low coefficients are F_k, A1, A2 / 2,
+// and the top three solve the end conditions
+//   m3 + m4 + m5 = e0,  3 m3 + 4 m4 + 5 m5 = e1,  6 m3 + 12 m4 + 20 m5 = e2
+// with e0 = F_k+1 - F_k - A1 - A2 / 2, e1 = B1 - A1 - A2, e2 = B2 - A2.
+__global__ void corr_coef_kernel(const double *tab, int G, double h, double *coef, int *bad)
+{
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= 2 * (G - 1)) return;
+    const int type = u / (G - 1), k = u - type * (G - 1);
+    const double *a = tab + 3 * (type * G + k), *b = a + 3;
+    const double A1 = h * a[1], A2 = h * h * a[2], B1 = h * b[1], B2 = h * h * b[2];
+    const double e0 = b[0] - a[0] - A1 - 0.5 * A2, e1 = B1 - A1 - A2, e2 = B2 - A2;
+    double *m = coef + 6 * u;
+    m[0] = a[0];
+    m[1] = A1;
+    m[2] = 0.5 * A2;
+    m[3] = 10.0 * e0 - 4.0 * e1 + 0.5 * e2;
+    m[4] = -15.0 * e0 + 7.0 * e1 - e2;
+    m[5] = 6.0 * e0 - 3.0 * e1 + 0.5 * e2;
+    bool ok = true;
+    for (int q = 0; q < 6; ++q) ok = ok && isfinite(m[q]);
+    if (!ok) atomicExch(bad, 1);
+}
+
+__global__ void fill_kernel(double *p, size_t n, double v)
+{
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        p[t] = v;
 }
 
 // Fixed-population reconfiguration of W walkers by systematic resampling
@@ -1425,13 +1644,14 @@ std::string g_error;  // last failure without a context
 // functions) and Be-like (4 electrons, 8 functions) atoms; for the 40-electron
 // molecule with 256 functions the fully unrolled kernel spills registers and
 // runs slower than the general one, so it is left out.
-#define LRDMC_SHAPE(u, d, k, z) {u, d, k, z, (const void *)project_kernel_fixed<u, d, k, z>},
+#define LRDMC_SHAPE(u, d, k, z) \
+    {u, d, k, z, {(const void *)project_kernel_fixed<u, d, k, z, false>, (const void *)project_kernel_fixed<u, d, k, z, true>}},
 #ifndef LRDMC_FIXED_SHAPES
 #define LRDMC_FIXED_SHAPES LRDMC_SHAPE(9, 9, 64, 1) LRDMC_SHAPE(2, 2, 8, 1)
 #endif
 struct FixedKernel {
     int n_up, n_dn, K, n_nuc;
-    const void *fn;
+    const void *fn[2];   // without, with the learned correction
 };
 const FixedKernel kFixedKernels[] = {LRDMC_FIXED_SHAPES};
 
@@ -1458,8 +1678,14 @@ struct lrdmc_ctx {
     int nt = 64;
     size_t lds_bytes = 0;
     Layout L{};
-    const void *fixed_fn = nullptr;  // kernel built for this system's sizes, if any
+    const void *fixed_fn[2] = {nullptr, nullptr};  // kernels built for this system's sizes, if any
     bool force_generic = false;
+    // learned Jastrow correction
+    bool corr = false;
+    int f_G = 0;
+    double f_rcut = 0.0;
+    double *d_fcoef = nullptr, *d_ftab = nullptr;   // [2][kMaxNodes - 1][6], staging [2][kMaxNodes][3]
+    int *d_fbad = nullptr;
     std::string err;
     // event timing
     bool timing = false;
@@ -1503,6 +1729,12 @@ KArgs base_args(const lrdmc_ctx *c)
     A.mpe = c->M / c->N;
     A.tau = c->prm.tau; A.seed = c->prm.seed; A.rotate = c->prm.rotate;
     A.W = c->W; A.gen = c->gen; A.err = c->d_err; A.L = c->L;
+    if (c->corr) {
+        A.fcoef = c->d_fcoef;
+        A.f_nint = c->f_G - 1;
+        A.f_hinv = (c->f_G - 1) / c->f_rcut;
+        A.f_rcut = c->f_rcut;
+    }
     return A;
 }
 
@@ -1595,7 +1827,9 @@ int launch_project(lrdmc_ctx *c, hipStream_t st, const double *pos_in, const int
     A.k_out = k;
     A.diag_out = diag;
     const int ev = eval ? -1 : timing_begin(c, st, 0);
-    const void *fn = (c->fixed_fn && !c->force_generic) ? c->fixed_fn : (const void *)project_kernel;
+    const void *fn = (c->fixed_fn[c->corr] && !c->force_generic)
+                         ? c->fixed_fn[c->corr]
+                         : (c->corr ? (const void *)project_kernel<true> : (const void *)project_kernel<false>);
     void *args[] = {&A};
     HIP_TRY(c, hipLaunchKernel(fn, dim3(c->W), dim3(c->nt), args, c->lds_bytes, st));
     timing_end(c, st, ev);
@@ -1839,7 +2073,10 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
         if (F.n_up != sys->n_up || F.n_dn != sys->n_dn || F.K != K || F.n_nuc != sys->n_nuc || c->M != 12 * N)
             continue;
         const Layout Lf = make_layout(N, ns, K, c->Kp, c->M, sys->n_nuc, c->nt, 0);
-        if (std::memcmp(&Lf, &c->L, sizeof(Layout)) == 0) c->fixed_fn = F.fn;
+        if (std::memcmp(&Lf, &c->L, sizeof(Layout)) == 0) {
+            c->fixed_fn[0] = F.fn[0];
+            c->fixed_fn[1] = F.fn[1];
+        }
     }
     c->lds_bytes = sizeof(double) * (size_t)c->L.total;
     c->dphi_at = (c->L.Jo + N - c->L.Y) + 2;
@@ -1856,7 +2093,9 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
     if (c->lds_bytes > (size_t)prop.sharedMemPerBlock)
         return cleanup(LRDMC_EINVAL, "lrdmc_create: walker state does not fit in LDS");
     if (c->lds_bytes > 65536) {
-        for (const void *fn : {(const void *)project_kernel, c->fixed_fn})
+        for (const void *fn : {(const void *)project_kernel<false>, (const void *)project_kernel<true>, c->fixed_fn[0],
+                               c->fixed_fn[1], (const void *)jastrow_grad_kernel<false>,
+                               (const void *)jastrow_grad_kernel<true>, (const void *)jastrow_table_grad_kernel})
             if (fn && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_bytes) !=
                           hipSuccess)
                 return cleanup(LRDMC_EDEVICE, "lrdmc_create: cannot raise the LDS limit");
@@ -1995,10 +2234,73 @@ int lrdmc_jastrow_grad(lrdmc_ctx *c, const double *pos, double *out, void *strea
     A.state_len = c->state_len;
     A.dphi_at = c->dphi_at;
     A.state_out = c->d_state[c->cur ^ 1];   // derivative rows as scratch, as in lrdmc_eval_moves
-    if (c->lds_bytes > 65536)
-        HIP_TRY(c, hipFuncSetAttribute((const void *)jastrow_grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)c->lds_bytes));
-    hipLaunchKernelGGL(jastrow_grad_kernel, dim3(c->W), dim3(c->nt), c->lds_bytes, st, A, out);
+    if (c->corr)
+        hipLaunchKernelGGL(jastrow_grad_kernel<true>, dim3(c->W), dim3(c->nt), c->lds_bytes, st, A, out);
+    else
+        hipLaunchKernelGGL(jastrow_grad_kernel<false>, dim3(c->W), dim3(c->nt), c->lds_bytes, st, A, out);
+    HIP_TRY(c, hipGetLastError());
+    return check_kernel_error(c, st);
+}
+
+int lrdmc_set_jastrow_table(lrdmc_ctx *c, const double *tab, int32_t n_nodes, double r_cut, int32_t on_device,
+                            void *stream)
+{
+    if (!c) return fail(nullptr, LRDMC_EINVAL, "lrdmc_set_jastrow_table: NULL context");
+    hipStream_t st = (hipStream_t)stream;
+    if (!tab || n_nodes == 0) {
+        c->corr = false;
+        c->state_ok = false;
+        return LRDMC_OK;
+    }
+    if (n_nodes < 2 || n_nodes > LRDMC_MAX_TABLE_NODES || !(r_cut > 0.0) || !std::isfinite(r_cut))
+        return fail(c, LRDMC_EINVAL, "lrdmc_set_jastrow_table: need 2 <= n_nodes <= LRDMC_MAX_TABLE_NODES and "
+                                     "finite r_cut > 0");
+    if (!c->d_fcoef) {
+        const size_t nc = 2 * (size_t)(LRDMC_MAX_TABLE_NODES - 1) * 6, nt = 2 * (size_t)LRDMC_MAX_TABLE_NODES * 3;
+        HIP_TRY(c, hipMalloc((void **)&c->d_fcoef, sizeof(double) * nc));
+        HIP_TRY(c, hipMalloc((void **)&c->d_ftab, sizeof(double) * nt));
+        HIP_TRY(c, hipMalloc((void **)&c->d_fbad, sizeof(int)));
+    }
+    const size_t bytes = sizeof(double) * 2 * (size_t)n_nodes * 3;
+    const double *src = tab;
+    if (!on_device) {
+        HIP_TRY(c, hipMemcpyAsync(c->d_ftab, tab, bytes, hipMemcpyHostToDevice, st));
+        src = c->d_ftab;
+    }
+    HIP_TRY(c, hipMemsetAsync(c->d_fbad, 0, sizeof(int), st));
+    const int n_int = 2 * (n_nodes - 1);
+    hipLaunchKernelGGL(corr_coef_kernel, dim3((n_int + 255) / 256), dim3(256), 0, st, src, (int)n_nodes,
+                       r_cut / (n_nodes - 1), c->d_fcoef, c->d_fbad);
+    HIP_TRY(c, hipGetLastError());
+    int bad = 0;
+    HIP_TRY(c, hipMemcpyAsync(&bad, c->d_fbad, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    if (bad) {
+        c->corr = false;
+        c->state_ok = false;
+        return fail(c, LRDMC_EINVAL, "lrdmc_set_jastrow_table: non-finite table entry (correction removed)");
+    }
+    c->corr = true;
+    c->f_G = n_nodes;
+    c->f_rcut = r_cut;
+    c->state_ok = false;   // stored Jastrow sums belong to the old trial function
+    return LRDMC_OK;
+}
+
+int lrdmc_jastrow_table_grad(lrdmc_ctx *c, const double *pos, const double *c_j, const double *c_e, double *gtab,
+                             void *stream)
+{
+    if (!c || !pos || !gtab) return fail(c, LRDMC_EINVAL, "lrdmc_jastrow_table_grad: NULL argument");
+    if (!c->corr) return fail(c, LRDMC_EINVAL, "lrdmc_jastrow_table_grad: no correction table is set");
+    hipStream_t st = (hipStream_t)stream;
+    KArgs A = base_args(c);
+    A.pos_in = pos;
+    A.state_len = c->state_len;
+    A.dphi_at = c->dphi_at;
+    A.state_out = c->d_state[c->cur ^ 1];
+    const size_t n = 2 * (size_t)c->f_G * 3;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, gtab, n, 0.0);
+    hipLaunchKernelGGL(jastrow_table_grad_kernel, dim3(c->W), dim3(c->nt), c->lds_bytes, st, A, c_j, c_e, gtab);
     HIP_TRY(c, hipGetLastError());
     return check_kernel_error(c, st);
 }
@@ -2050,7 +2352,7 @@ int lrdmc_use_generic(lrdmc_ctx *c, int32_t enable)
 
 int32_t lrdmc_is_specialized(const lrdmc_ctx *c)
 {
-    return (c && c->fixed_fn && !c->force_generic) ? 1 : 0;
+    return (c && c->fixed_fn[c->corr] && !c->force_generic) ? 1 : 0;
 }
 
 int lrdmc_set_timing(lrdmc_ctx *c, int32_t enable)
@@ -2082,7 +2384,8 @@ void lrdmc_destroy(lrdmc_ctx *c)
 {
     if (!c) return;
     void *ptrs[] = {c->d_Z,      c->d_R,        c->d_mo,       c->d_chain,    c->d_fn,   c->d_Rheavy, c->d_pos[0], c->d_state[0], c->d_state[1],
-                    c->d_pos[1], c->d_logw, c->d_el, c->d_cw,     c->d_nmov, c->d_idx,  c->d_err};
+                    c->d_pos[1], c->d_logw, c->d_el, c->d_cw,     c->d_nmov, c->d_idx,  c->d_err,
+                    c->d_fcoef, c->d_ftab, c->d_fbad};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);

@@ -298,3 +298,19 @@ def neural_weights(seed: int = 0, hidden: int = 64, out_scale: float = 0.1) -> d
             "b3": np.array(0.0),
         }
     return out
+
+
+def jastrow_table(seed: int = 0, n_nodes: int = 33, r_cut: float = 4.0, scale: float = 0.2) -> np.ndarray:
+    """Node table [2][n_nodes][3] = {F, F', F''} at r_k = k r_cut / (n_nodes - 1)
+    of a smooth random radial function per pair type (0: electron pairs,
+    1: electron-nucleus): F(r) = scale r^2 (1 - r/r_cut)^3 P(r/r_cut) with P
+    a random cubic; values and derivatives exact (numpy polynomials)."""
+    P = np.polynomial.Polynomial
+    rng = np.random.default_rng([seed, 91])
+    r = np.linspace(0.0, r_cut, n_nodes)
+    env = P([0.0, 0.0, 1.0]) * P([1.0, -1.0 / r_cut]) ** 3
+    tab = np.zeros((2, n_nodes, 3))
+    for t in range(2):
+        f = scale * env * P(rng.normal(size=4))(P([0.0, 1.0 / r_cut]))
+        tab[t, :, 0], tab[t, :, 1], tab[t, :, 2] = f(r), f.deriv(1)(r), f.deriv(2)(r)
+    return tab

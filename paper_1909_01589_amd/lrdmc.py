@@ -55,7 +55,8 @@ class lrdmc_params(C.Structure):
 _lib = None
 EXPORTS = ("lrdmc_spacing", "lrdmc_spacing_pade", "lrdmc_create", "lrdmc_set_walkers", "lrdmc_project", "lrdmc_branch",
            "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure",
-           "lrdmc_jastrow_grad", "lrdmc_set_jastrow", "lrdmc_use_generic", "lrdmc_is_specialized", "lrdmc_set_timing", "lrdmc_timing", "lrdmc_generation",
+           "lrdmc_jastrow_grad", "lrdmc_set_jastrow", "lrdmc_set_jastrow_table", "lrdmc_jastrow_table_grad",
+           "lrdmc_use_generic", "lrdmc_is_specialized", "lrdmc_set_timing", "lrdmc_timing", "lrdmc_generation",
            "lrdmc_last_error", "lrdmc_destroy")
 
 
@@ -80,6 +81,8 @@ def load():
     lib.lrdmc_reconfigure.argtypes = [P, P, I32, D, P, P, P]
     lib.lrdmc_jastrow_grad.argtypes = [P, P, P, P]
     lib.lrdmc_set_jastrow.argtypes = [P, D, D]
+    lib.lrdmc_set_jastrow_table.argtypes = [P, P, I32, D, I32, P]
+    lib.lrdmc_jastrow_table_grad.argtypes = [P, P, P, P, P, P]
     lib.lrdmc_use_generic.argtypes = [P, I32]
     lib.lrdmc_is_specialized.argtypes = [P]
     lib.lrdmc_is_specialized.restype = I32
@@ -93,7 +96,8 @@ def load():
     lib.lrdmc_destroy.restype = None
     for name in ("lrdmc_spacing", "lrdmc_spacing_pade", "lrdmc_create", "lrdmc_set_walkers", "lrdmc_project", "lrdmc_branch",
                  "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure",
-                 "lrdmc_jastrow_grad", "lrdmc_set_jastrow", "lrdmc_use_generic", "lrdmc_set_timing",
+                 "lrdmc_jastrow_grad", "lrdmc_set_jastrow", "lrdmc_set_jastrow_table",
+                 "lrdmc_jastrow_table_grad", "lrdmc_use_generic", "lrdmc_set_timing",
                  "lrdmc_timing"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -212,6 +216,32 @@ def lrdmc_set_jastrow(ctx, b_ee: float, b_en: float):
     _check(load().lrdmc_set_jastrow(ctx, float(b_ee), float(b_en)), ctx)
 
 
+MAX_TABLE_NODES = 4096
+
+
+def lrdmc_set_jastrow_table(ctx, tab, r_cut: float = 0.0, stream=None):
+    """tab: [2][G][3] float64 (host array or device tensor), or None to remove."""
+    if tab is None:
+        _check(load().lrdmc_set_jastrow_table(ctx, None, 0, 0.0, 0, _stream(stream)), ctx)
+        return
+    if isinstance(tab, torch.Tensor) and tab.is_cuda:
+        if tab.dim() != 3 or tab.shape[0] != 2 or tab.shape[2] != 3:
+            raise ValueError("table must be [2][n_nodes][3]")
+        _check(load().lrdmc_set_jastrow_table(ctx, _dptr(tab, torch.float64), int(tab.shape[1]), float(r_cut), 1,
+                                              _stream(stream)), ctx)
+        return
+    a = np.ascontiguousarray(np.asarray(tab, dtype=np.float64))
+    if a.ndim != 3 or a.shape[0] != 2 or a.shape[2] != 3:
+        raise ValueError("table must be [2][n_nodes][3]")
+    _check(load().lrdmc_set_jastrow_table(ctx, a.ctypes.data, int(a.shape[1]), float(r_cut), 0, _stream(stream)), ctx)
+
+
+def lrdmc_jastrow_table_grad(ctx, pos, c_j, c_e, gtab, stream=None):
+    _check(load().lrdmc_jastrow_table_grad(ctx, _dptr(pos, torch.float64), _dptr(c_j, torch.float64),
+                                           _dptr(c_e, torch.float64), _dptr(gtab, torch.float64),
+                                           _stream(stream)), ctx)
+
+
 def lrdmc_use_generic(ctx, enable: bool = True):
     _check(load().lrdmc_use_generic(ctx, 1 if enable else 0), ctx)
 
@@ -262,6 +292,7 @@ class LRDMC:
         self.W = int(n_walkers)
         self.N = system.n_elec
         self.M = (6 if grids == 1 else 12) * self.N
+        self.table_nodes = 0
         self.ctx = lrdmc_create(system, a, a_prime, r_c, tau, n_walkers, z_heavy, seed, rotate, refresh,
                                 switch_form, grids)
 
@@ -317,6 +348,27 @@ class LRDMC:
 
     def set_jastrow(self, b_ee: float, b_en: float):
         lrdmc_set_jastrow(self.ctx, b_ee, b_en)
+
+    def set_jastrow_table(self, tab, r_cut: float = 0.0):
+        """Learned correction from its node table [2][G][3] (None removes it)."""
+        lrdmc_set_jastrow_table(self.ctx, tab, r_cut)
+        self.table_nodes = 0 if tab is None else int(tab.shape[1])
+
+    def jastrow_table_grad(self, pos, c_j=None, c_e=None):
+        """[2][G][3]: d/dtab sum_w (c_j[w] J_w + c_e[w] E_L,w)."""
+        t = torch.as_tensor(pos, dtype=torch.float64).to(self.device).contiguous()
+        if tuple(t.shape) != (self.W, self.N, 3):
+            raise ValueError(f"positions must be [{self.W}, {self.N}, 3]")
+        cj = None if c_j is None else torch.as_tensor(c_j, dtype=torch.float64).to(self.device).contiguous()
+        ce = None if c_e is None else torch.as_tensor(c_e, dtype=torch.float64).to(self.device).contiguous()
+        for c in (cj, ce):
+            if c is not None and tuple(c.shape) != (self.W,):
+                raise ValueError(f"coefficients must be [{self.W}]")
+        if not getattr(self, "table_nodes", 0):
+            raise ValueError("no correction table is set")
+        g = self._f64(2, self.table_nodes, 3)
+        lrdmc_jastrow_table_grad(self.ctx, t, cj, ce, g)
+        return g
 
     def jastrow_grad(self, pos):
         """[W][6]: E_L, J, dJ/db_ee, dJ/db_en, dE_L/db_ee, dE_L/db_en."""
