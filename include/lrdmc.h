@@ -253,6 +253,35 @@ int lrdmc_set_jastrow_table(lrdmc_ctx *ctx, const double *tab, int32_t n_nodes, 
 int lrdmc_jastrow_table_grad(lrdmc_ctx *ctx, const double *pos, const double *c_j, const double *c_e,
                              double *gtab, void *stream);
 
+/* The network that produces the correction's node table (the trial
+ * function's learned Jastrow part; parameters optimized by the caller, as the
+ * supplement's computational details optimize every Jastrow parameter).  Per
+ * pair type (0: electron pairs, 1: electron-nucleus) a network 1 -> H -> H
+ * -> 1 with SiLU activations silu(z) = z / (1 + exp(-z)):
+ * g(x) = w3 . silu(W2 silu(W1 x + b1) + b2) + b3 at x = r / r_cut, and
+ * f(r) = r^2 (1 - r/r_cut)^3 g(r/r_cut), so that f(0) = f'(0) = 0 (cusps of
+ * the Pade part stay exact) and f, f', f'' vanish at r_cut.
+ * params (device [2][P], P = lrdmc_net_param_count(H) = H^2 + 4H + 1), per
+ * network in this order: W1[H], b1[H], W2[H][H] (row-major, row = output
+ * unit), b2[H], w3[H], b3.
+ * lrdmc_net_tabulate writes tab (device [2][n_nodes][3]) = {f, f', f''} at
+ * r_k = k r_cut / (n_nodes - 1): the input of lrdmc_set_jastrow_table.
+ * lrdmc_net_tabulate_backward writes gparams (device [2][P], overwritten) =
+ * sum over the table of gtab * d tab / d params, given gtab (device
+ * [2][n_nodes][3]); work is device scratch of lrdmc_net_workspace_size(H,
+ * n_nodes) doubles.  Both are asynchronous on `stream` (no host
+ * synchronization); the reduction order is fixed (deterministic).
+ * lrdmc_net_param_count and lrdmc_net_workspace_size return 0 for sizes out
+ * of range.  Errors: LRDMC_EINVAL (NULL, 1 <= H <= 256,
+ * 2 <= n_nodes <= LRDMC_MAX_TABLE_NODES, finite r_cut > 0), LRDMC_EDEVICE
+ * (launch failure); message in lrdmc_last_error(NULL). */
+int32_t lrdmc_net_param_count(int32_t hidden);
+int64_t lrdmc_net_workspace_size(int32_t hidden, int32_t n_nodes);
+int lrdmc_net_tabulate(const double *params, int32_t hidden, int32_t n_nodes, double r_cut, double *tab,
+                       void *stream);
+int lrdmc_net_tabulate_backward(const double *params, int32_t hidden, int32_t n_nodes, double r_cut,
+                                const double *gtab, double *gparams, double *work, void *stream);
+
 /* Kernel selection.  The library carries, besides the projection kernel for
  * any system, kernels built for fixed system sizes (electrons per spin, basis
  * functions, nuclei; see LRDMC_FIXED_SHAPES in the kernel source).

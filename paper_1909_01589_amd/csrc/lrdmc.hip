@@ -1545,6 +1545,203 @@ __global__ void fill_kernel(double *p, size_t n, double v)
         p[t] = v;
 }
 
+// ---------------------------------------------------------------------------
+// The network behind the learned correction.  Per pair type a network
+// 1 -> H -> H -> 1 with SiLU activations, silu(z) = z / (1 + e^-z), gives
+// g(x) = w3 . silu(W2 silu(W1 x + b1) + b2) + b3 at x = r / r_cut, and the
+// correction is f(r) = r^2 (1 - r / r_cut)^3 g(r / r_cut): f and f' vanish at
+// r = 0 (the Pade cusps stay exact), f, f', f'' at r_cut.  Parameters of one
+// network, packed: W1[H], b1[H], W2[H][H] (row = output unit), b2[H], w3[H],
+// b3.  The node table {f, f', f''} is built with the r-derivatives carried
+// through every layer (first and second order forward mode); its reverse pass
+// gives the parameter gradient of a loss on the table.
+
+constexpr int kNetMaxHidden = 256;
+
+__host__ __device__ constexpr int net_param_count(int H) { return H * H + 4 * H + 1; }
+
+// silu and its first three derivatives.
+__device__ __forceinline__ void silu_d3(double z, double &a, double &d1, double &d2, double &d3)
+{
+    const double sg = 1.0 / (1.0 + exp(-z));
+    const double p = sg * (1.0 - sg), om = 1.0 - 2.0 * sg;
+    a = z * sg;
+    d1 = sg + z * p;
+    d2 = p * (2.0 + z * om);
+    d3 = p * (3.0 * om + z * (1.0 - 6.0 * sg + 6.0 * sg * sg));
+}
+
+// w(r) = r^2 (1 - r / rc)^3 and its first two derivatives.
+__device__ __forceinline__ void envelope3(double r, double rc, double &w, double &w1, double &w2)
+{
+    const double q = 1.0 - r / rc, q2 = q * q;
+    w = r * r * q2 * q;
+    w1 = r * q2 * (2.0 * q - 3.0 * r / rc);
+    w2 = q * (2.0 * q2 - 12.0 * r * q / rc + 6.0 * r * r / (rc * rc));
+}
+
+struct NetFwd {
+    double x;                   // input r / rc
+    double s1, s2, s3;          // first to third derivative of silu at this unit's z2
+    double z2[3];               // z2 and its first two r-derivatives
+    double h2[3];               // h2 and its first two r-derivatives
+};
+
+// Forward pass of one node for the unit of this thread (u < H); leaves the
+// first-layer streams in hs[3][H] and returns the second-layer quantities.
+__device__ __forceinline__ NetFwd net_forward(const double *P, int H, double r, double rc, double *hs)
+{
+    const int u = threadIdx.x;
+    const double *W1 = P, *b1 = P + H, *W2 = P + 2 * H, *b2 = P + 2 * H + H * H;
+    NetFwd o{};
+    o.x = r / rc;
+    if (u < H) {
+        double a, d1, d2, d3;
+        const double dz = W1[u] / rc;
+        silu_d3(fma(W1[u], o.x, b1[u]), a, d1, d2, d3);
+        hs[u] = a;
+        hs[H + u] = d1 * dz;
+        hs[2 * H + u] = d2 * dz * dz;
+    }
+    __syncthreads();
+    if (u < H) {
+        double z = b2[u], dz = 0.0, ddz = 0.0;
+        const double *row = W2 + (size_t)u * H;
+        for (int v = 0; v < H; ++v) {
+            const double wv = row[v];
+            z = fma(wv, hs[v], z);
+            dz = fma(wv, hs[H + v], dz);
+            ddz = fma(wv, hs[2 * H + v], ddz);
+        }
+        double a;
+        silu_d3(z, a, o.s1, o.s2, o.s3);
+        o.z2[0] = z; o.z2[1] = dz; o.z2[2] = ddz;
+        o.h2[0] = a;
+        o.h2[1] = o.s1 * dz;
+        o.h2[2] = o.s2 * dz * dz + o.s1 * ddz;
+    }
+    return o;
+}
+
+// Node position r_k = k rc / (G - 1), the last node exactly rc.
+__device__ __forceinline__ double net_node(int k, int G, double rc)
+{
+    return (k == G - 1) ? rc : k * (rc / (G - 1));
+}
+
+// tab[type][k][3] = {f, f', f''} at the nodes; grid (G, 2).
+__global__ void __launch_bounds__(kNetMaxHidden) net_table_kernel(const double *params, int H, int G, double rc,
+                                                                  double *tab)
+{
+    __shared__ double hs[3 * kNetMaxHidden];
+    __shared__ double red[3 * 16];
+    const int k = blockIdx.x, type = blockIdx.y, u = threadIdx.x;
+    const double *P = params + (size_t)type * net_param_count(H);
+    const double r = net_node(k, G, rc);
+    const NetFwd o = net_forward(P, H, r, rc, hs);
+    const double *w3 = P + 3 * H + H * H;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (u < H)
+        for (int c = 0; c < 3; ++c) v[c] = w3[u] * o.h2[c];
+    block_sum<3>(v, red);
+    if (u == 0) {
+        const double g = v[0] + P[4 * H + H * H], dg = v[1], ddg = v[2];
+        double w, w1, w2;
+        envelope3(r, rc, w, w1, w2);
+        double *t = tab + 3 * ((size_t)type * G + k);
+        t[0] = w * g;
+        t[1] = w1 * g + w * dg;
+        t[2] = w2 * g + 2.0 * w1 * dg + w * ddg;
+    }
+}
+
+// Reverse pass, per node: given the table gradient gtab, the node's share of
+// every parameter gradient, in work[type][k][9H + 1]:
+//   [0, 3H)   z2 adjoints (value, d/dr, d2/dr2 streams) of each unit
+//   [3H, 6H)  the first-layer streams h1, dh1, d2h1
+//   [6H, 7H)  W1 share, [7H, 8H) b1 share, [8H, 9H) w3 share, [9H] b3 share
+// (W2 = sum over nodes and streams of z2 adjoint times h1 stream, b2 = sum of
+// the value-stream z2 adjoints).  Grid (G, 2).
+__global__ void __launch_bounds__(kNetMaxHidden) net_table_back_kernel(const double *params, int H, int G, double rc,
+                                                                       const double *gtab, double *work)
+{
+    __shared__ double hs[3 * kNetMaxHidden], zb[3 * kNetMaxHidden];
+    const int k = blockIdx.x, type = blockIdx.y, u = threadIdx.x;
+    const double *P = params + (size_t)type * net_param_count(H);
+    const double *W1 = P, *b1 = P + H, *W2 = P + 2 * H, *w3 = P + 3 * H + H * H;
+    const double r = net_node(k, G, rc);
+    const NetFwd o = net_forward(P, H, r, rc, hs);
+    double w, w1, w2;
+    envelope3(r, rc, w, w1, w2);
+    const double *gt = gtab + 3 * ((size_t)type * G + k);
+    const double gb = w * gt[0] + w1 * gt[1] + w2 * gt[2];   // dL/dg
+    const double dgb = w * gt[1] + 2.0 * w1 * gt[2];          // dL/dg'
+    const double ddgb = w * gt[2];                            // dL/dg''
+    double *out = work + ((size_t)type * G + k) * (9 * H + 1);
+    if (u < H) {
+        const double hb = gb * w3[u], dhb = dgb * w3[u], ddhb = ddgb * w3[u];
+        const double dz = o.z2[1], ddz = o.z2[2];
+        const double zb0 = hb * o.s1 + dhb * o.s2 * dz + ddhb * (o.s3 * dz * dz + o.s2 * ddz);
+        const double zb1 = dhb * o.s1 + 2.0 * ddhb * o.s2 * dz;
+        const double zb2 = ddhb * o.s1;
+        zb[u] = zb0; zb[H + u] = zb1; zb[2 * H + u] = zb2;
+        out[u] = zb0; out[H + u] = zb1; out[2 * H + u] = zb2;
+        out[3 * H + u] = hs[u]; out[4 * H + u] = hs[H + u]; out[5 * H + u] = hs[2 * H + u];
+        out[8 * H + u] = gb * o.h2[0] + dgb * o.h2[1] + ddgb * o.h2[2];
+    }
+    if (u == 0) out[9 * H] = gb;
+    __syncthreads();
+    if (u < H) {
+        // adjoints of the first-layer streams of unit u: W2^T times the z2 adjoints
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int q = 0; q < H; ++q) {
+            const double wq = W2[(size_t)q * H + u];
+            a0 = fma(wq, zb[q], a0);
+            a1 = fma(wq, zb[H + q], a1);
+            a2 = fma(wq, zb[2 * H + q], a2);
+        }
+        double s, t1, t2, t3;
+        const double dz1 = W1[u] / rc;
+        silu_d3(fma(W1[u], o.x, b1[u]), s, t1, t2, t3);
+        const double z1b = a0 * t1 + a1 * t2 * dz1 + a2 * t3 * dz1 * dz1;
+        const double dz1b = a1 * t1 + 2.0 * a2 * t2 * dz1;
+        out[6 * H + u] = z1b * o.x + dz1b / rc;
+        out[7 * H + u] = z1b;
+    }
+}
+
+// Sum of the per-node shares into gparams[type][P]; grid (ceil(P / 256), 2),
+// node order fixed (deterministic).
+__global__ void net_table_reduce_kernel(int H, int G, const double *work, double *gparams)
+{
+    const int PC = net_param_count(H), type = blockIdx.y;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= PC) return;
+    const size_t S = 9 * (size_t)H + 1;
+    const double *base = work + (size_t)type * G * S;
+    double acc = 0.0;
+    if (p < H) {                                   // W1
+        for (int k = 0; k < G; ++k) acc += base[k * S + 6 * H + p];
+    } else if (p < 2 * H) {                        // b1
+        for (int k = 0; k < G; ++k) acc += base[k * S + 7 * H + (p - H)];
+    } else if (p < 2 * H + H * H) {                // W2[u][v]
+        const int u = (p - 2 * H) / H, v = (p - 2 * H) % H;
+        for (int k = 0; k < G; ++k) {
+            const double *o = base + k * S;
+            acc += o[u] * o[3 * H + v] + o[H + u] * o[4 * H + v] + o[2 * H + u] * o[5 * H + v];
+        }
+    } else if (p < 3 * H + H * H) {                // b2
+        const int u = p - 2 * H - H * H;
+        for (int k = 0; k < G; ++k) acc += base[k * S + u];
+    } else if (p < 4 * H + H * H) {                // w3
+        const int u = p - 3 * H - H * H;
+        for (int k = 0; k < G; ++k) acc += base[k * S + 8 * H + u];
+    } else {                                       // b3
+        for (int k = 0; k < G; ++k) acc += base[k * S + 9 * H];
+    }
+    gparams[(size_t)type * PC + p] = acc;
+}
+
 // Fixed-population reconfiguration of W walkers by systematic resampling
 // (one workgroup).  cw: W-double scratch for the cumulative weights.
 __global__ void __launch_bounds__(1024) reconfigure_kernel(const double *logw, const double *el,
@@ -2340,6 +2537,57 @@ int lrdmc_reconfigure(const double *log_w, const double *e_loc, int32_t W, doubl
         return fail(nullptr, LRDMC_EDEVICE, std::string("lrdmc_reconfigure: ") +
                                                 hipGetErrorString(le != hipSuccess ? le : se));
     if (e[0]) return fail(nullptr, LRDMC_ENONFINITE, "lrdmc_reconfigure: non-finite weights");
+    return LRDMC_OK;
+}
+
+int32_t lrdmc_net_param_count(int32_t hidden)
+{
+    return (hidden >= 1 && hidden <= kNetMaxHidden) ? net_param_count(hidden) : 0;
+}
+
+int64_t lrdmc_net_workspace_size(int32_t hidden, int32_t n_nodes)
+{
+    if (hidden < 1 || hidden > kNetMaxHidden || n_nodes < 2 || n_nodes > LRDMC_MAX_TABLE_NODES) return 0;
+    return 2 * (int64_t)n_nodes * (9 * (int64_t)hidden + 1);
+}
+
+static int net_check(int32_t hidden, int32_t n_nodes, double r_cut, const char *who)
+{
+    if (hidden < 1 || hidden > kNetMaxHidden || n_nodes < 2 || n_nodes > LRDMC_MAX_TABLE_NODES || !(r_cut > 0.0) ||
+        !std::isfinite(r_cut))
+        return fail(nullptr, LRDMC_EINVAL, std::string(who) + ": need 1 <= hidden <= 256, 2 <= n_nodes <= "
+                                                              "LRDMC_MAX_TABLE_NODES and finite r_cut > 0");
+    return LRDMC_OK;
+}
+
+int lrdmc_net_tabulate(const double *params, int32_t hidden, int32_t n_nodes, double r_cut, double *tab, void *stream)
+{
+    if (!params || !tab) return fail(nullptr, LRDMC_EINVAL, "lrdmc_net_tabulate: NULL argument");
+    if (int rc = net_check(hidden, n_nodes, r_cut, "lrdmc_net_tabulate")) return rc;
+    const int nt = ((hidden + 63) / 64) * 64;
+    hipLaunchKernelGGL(net_table_kernel, dim3(n_nodes, 2), dim3(nt), 0, (hipStream_t)stream, params, (int)hidden,
+                       (int)n_nodes, r_cut, tab);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(nullptr, LRDMC_EDEVICE, std::string("lrdmc_net_tabulate: ") + hipGetErrorString(e));
+    return LRDMC_OK;
+}
+
+int lrdmc_net_tabulate_backward(const double *params, int32_t hidden, int32_t n_nodes, double r_cut,
+                                const double *gtab, double *gparams, double *work, void *stream)
+{
+    if (!params || !gtab || !gparams || !work)
+        return fail(nullptr, LRDMC_EINVAL, "lrdmc_net_tabulate_backward: NULL argument");
+    if (int rc = net_check(hidden, n_nodes, r_cut, "lrdmc_net_tabulate_backward")) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int nt = ((hidden + 63) / 64) * 64, PC = net_param_count(hidden);
+    hipLaunchKernelGGL(net_table_back_kernel, dim3(n_nodes, 2), dim3(nt), 0, st, params, (int)hidden, (int)n_nodes,
+                       r_cut, gtab, work);
+    hipLaunchKernelGGL(net_table_reduce_kernel, dim3((PC + 255) / 256, 2), dim3(256), 0, st, (int)hidden,
+                       (int)n_nodes, (const double *)work, gparams);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(nullptr, LRDMC_EDEVICE, std::string("lrdmc_net_tabulate_backward: ") + hipGetErrorString(e));
     return LRDMC_OK;
 }
 

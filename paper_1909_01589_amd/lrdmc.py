@@ -56,6 +56,7 @@ _lib = None
 EXPORTS = ("lrdmc_spacing", "lrdmc_spacing_pade", "lrdmc_create", "lrdmc_set_walkers", "lrdmc_project", "lrdmc_branch",
            "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure",
            "lrdmc_jastrow_grad", "lrdmc_set_jastrow", "lrdmc_set_jastrow_table", "lrdmc_jastrow_table_grad",
+           "lrdmc_net_param_count", "lrdmc_net_workspace_size", "lrdmc_net_tabulate", "lrdmc_net_tabulate_backward",
            "lrdmc_use_generic", "lrdmc_is_specialized", "lrdmc_set_timing", "lrdmc_timing", "lrdmc_generation",
            "lrdmc_last_error", "lrdmc_destroy")
 
@@ -83,6 +84,12 @@ def load():
     lib.lrdmc_set_jastrow.argtypes = [P, D, D]
     lib.lrdmc_set_jastrow_table.argtypes = [P, P, I32, D, I32, P]
     lib.lrdmc_jastrow_table_grad.argtypes = [P, P, P, P, P, P]
+    lib.lrdmc_net_param_count.argtypes = [I32]
+    lib.lrdmc_net_param_count.restype = I32
+    lib.lrdmc_net_workspace_size.argtypes = [I32, I32]
+    lib.lrdmc_net_workspace_size.restype = C.c_int64
+    lib.lrdmc_net_tabulate.argtypes = [P, I32, I32, D, P, P]
+    lib.lrdmc_net_tabulate_backward.argtypes = [P, I32, I32, D, P, P, P, P]
     lib.lrdmc_use_generic.argtypes = [P, I32]
     lib.lrdmc_is_specialized.argtypes = [P]
     lib.lrdmc_is_specialized.restype = I32
@@ -97,7 +104,8 @@ def load():
     for name in ("lrdmc_spacing", "lrdmc_spacing_pade", "lrdmc_create", "lrdmc_set_walkers", "lrdmc_project", "lrdmc_branch",
                  "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure",
                  "lrdmc_jastrow_grad", "lrdmc_set_jastrow", "lrdmc_set_jastrow_table",
-                 "lrdmc_jastrow_table_grad", "lrdmc_use_generic", "lrdmc_set_timing",
+                 "lrdmc_jastrow_table_grad", "lrdmc_net_tabulate", "lrdmc_net_tabulate_backward",
+                 "lrdmc_use_generic", "lrdmc_set_timing",
                  "lrdmc_timing"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -240,6 +248,26 @@ def lrdmc_jastrow_table_grad(ctx, pos, c_j, c_e, gtab, stream=None):
     _check(load().lrdmc_jastrow_table_grad(ctx, _dptr(pos, torch.float64), _dptr(c_j, torch.float64),
                                            _dptr(c_e, torch.float64), _dptr(gtab, torch.float64),
                                            _stream(stream)), ctx)
+
+
+def lrdmc_net_param_count(hidden: int) -> int:
+    return int(load().lrdmc_net_param_count(int(hidden)))
+
+
+def lrdmc_net_workspace_size(hidden: int, n_nodes: int) -> int:
+    return int(load().lrdmc_net_workspace_size(int(hidden), int(n_nodes)))
+
+
+def lrdmc_net_tabulate(params, hidden: int, n_nodes: int, r_cut: float, tab, stream=None):
+    _check(load().lrdmc_net_tabulate(_dptr(params, torch.float64), int(hidden), int(n_nodes), float(r_cut),
+                                     _dptr(tab, torch.float64), _stream(stream)))
+
+
+def lrdmc_net_tabulate_backward(params, hidden: int, n_nodes: int, r_cut: float, gtab, gparams, work,
+                                stream=None):
+    _check(load().lrdmc_net_tabulate_backward(_dptr(params, torch.float64), int(hidden), int(n_nodes), float(r_cut),
+                                              _dptr(gtab, torch.float64), _dptr(gparams, torch.float64),
+                                              _dptr(work, torch.float64), _stream(stream)))
 
 
 def lrdmc_use_generic(ctx, enable: bool = True):
