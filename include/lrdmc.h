@@ -40,7 +40,8 @@
  *     random rotation drawn for every move.
  *   - Random numbers: Philox4x64-10 with key (seed, 0) and counter
  *     (slot, generation, iteration, purpose); purpose 0 gives (u1, u2) of a
- *     move, 1 the rotation, 3 the resampling offset at slot 2^64-1.
+ *     move, 1 the rotation, 2 a Metropolis step (lrdmc_vmc), 3 the
+ *     resampling offset at slot 2^64-1.
  *
  * Thread safety: a context may be used by one host thread at a time.
  */
@@ -220,6 +221,21 @@ int lrdmc_jastrow_grad(lrdmc_ctx *ctx, const double *pos, double *out, void *str
  * projections, evaluations and gradients use them; walker states stored from
  * earlier projections are recomputed.  Errors: LRDMC_EINVAL. */
 int lrdmc_set_jastrow(lrdmc_ctx *ctx, double b_ee, double b_en);
+
+/* Variational Monte Carlo sampling of |Psi|^2 (the variational stage the
+ * supplement's computational details run before the projection; Metropolis
+ * algorithm): every walker takes n_steps single-electron moves.  Step t of
+ * generation g of walker slot s draws (u0, u1, u2, u3) from the random
+ * stream at counter (s, g, t, purpose 2): electron i = floor(u0 N) moves by
+ * step * e, e on the unit sphere with cos(theta) = 2 u1 - 1, phi = 2 pi u2
+ * (a symmetric proposal), accepted when u3 < (Psi(x')/Psi(x))^2.  Starts from
+ * the current walkers (after a pending reconfiguration), replaces them,
+ * advances the generation counter by one and sets log w = 0; lrdmc_get_walkers
+ * then returns E_L at the final positions and the accepted count in n_moves.
+ * The trial function includes the learned correction when one is set.
+ * Synchronizes the stream.  Errors: LRDMC_EINVAL (no walkers, n_steps < 0,
+ * step not finite and > 0), LRDMC_ESINGULAR, LRDMC_ENONFINITE, LRDMC_EDEVICE. */
+int lrdmc_vmc(lrdmc_ctx *ctx, int32_t n_steps, double step, void *stream);
 
 /* Learned correction of the Jastrow factor.  The supplement's computational
  * details use Jastrow-Slater trial functions whose Jastrow parameters are all

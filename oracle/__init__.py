@@ -95,6 +95,7 @@ def load():
         lib.orc_select.argtypes = [P, C.c_int, C.c_double]
         lib.orc_select.restype = C.c_int
         lib.orc_generation.argtypes = [P, P, C.c_uint64, C.c_uint64, P, P, P, P]
+        lib.orc_vmc.argtypes = [P, P, C.c_uint64, C.c_uint64, C.c_int, C.c_double, P, P, P]
         lib.orc_generation.restype = C.c_int
         lib.orc_reconfigure.argtypes = [P, P, C.c_int, C.c_double, P, P, P]
         lib.orc_reconfigure.restype = C.c_int
@@ -274,6 +275,16 @@ class Oracle:
                                      _ptr(p), C.byref(lw), C.byref(el), C.byref(nm))
         _check(rc, "generation")
         return p, lw.value, el.value, nm.value
+
+    def vmc(self, pos, slot: int, gen: int, n_steps: int, step: float):
+        """Metropolis chain of n_steps single-electron moves from pos:
+        (pos, accepted steps, E_L at the end)."""
+        p = np.array(pos, dtype=np.float64, copy=True).reshape(self.N, 3)
+        acc, el = C.c_int64(), C.c_double()
+        rc = self.lib.orc_vmc(C.byref(self.sys), C.byref(self.prm), int(slot), int(gen),
+                              int(n_steps), float(step), _ptr(p), C.byref(acc), C.byref(el))
+        _check(rc, "orc_vmc")
+        return p, int(acc.value), float(el.value)
 
     def reconfigure(self, log_w, e_l, xi):
         lw = _f64(log_w)

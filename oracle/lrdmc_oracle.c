@@ -792,6 +792,58 @@ int orc_generation(const orc_system *s, const orc_params *p, uint64_t slot, uint
 }
 
 /* ------------------------------------------------------------------------ */
+/* Variational Monte Carlo: Metropolis sampling of |Psi|^2 (the variational  */
+/* step of the supplement's computational details; Metropolis et al. 1953).  */
+/* Step t of generation gen of slot s draws (u0, u1, u2, u3) from counter    */
+/* (s, gen, t, 2): electron i = floor(u0 N) moves by step * e with e on the  */
+/* unit sphere (cos theta = 2 u1 - 1, phi = 2 pi u2), a proposal symmetric   */
+/* in x and x'; it is accepted when u3 < (Psi(x')/Psi(x))^2, the ratio from  */
+/* log|Psi| and the sign recomputed in full at both points.  pos is updated  */
+/* in place; *n_acc counts accepted steps, *e_l is E_L at the end.           */
+int orc_vmc(const orc_system *s, const orc_params *p, uint64_t slot, uint64_t gen, int n_steps, double step,
+            double *pos, int64_t *n_acc, double *e_l)
+{
+    int N = s->n_up + s->n_dn;
+    double *trial = (double *)malloc(sizeof(double) * 3 * N);
+    if (!trial) return ORC_ENOMEM;
+    double l0;
+    int sg0;
+    int rc = orc_log_psi(s, pos, &l0, &sg0);
+    int64_t acc = 0;
+    for (int t = 0; t < n_steps && rc == ORC_OK; ++t) {
+        double u[4];
+        orc_draw(p->seed, slot, gen, (uint64_t)t, 2, u);
+        int i = (int)(u[0] * N);
+        if (i > N - 1) i = N - 1;
+        double ct = 2.0 * u[1] - 1.0, st = sqrt(fmax(0.0, 1.0 - ct * ct)), ph = 2.0 * M_PI * u[2];
+        memcpy(trial, pos, sizeof(double) * 3 * N);
+        trial[3 * i] += step * st * cos(ph);
+        trial[3 * i + 1] += step * st * sin(ph);
+        trial[3 * i + 2] += step * ct;
+        double l1;
+        int sg1;
+        rc = orc_log_psi(s, trial, &l1, &sg1);
+        if (rc == ORC_ESINGULAR) {   /* on a node: Psi(x') = 0, never accepted */
+            rc = ORC_OK;
+            continue;
+        }
+        if (rc) break;
+        double ratio = (double)(sg0 * sg1) * exp(l1 - l0);
+        if (u[3] < ratio * ratio) {
+            memcpy(pos, trial, sizeof(double) * 3 * N);
+            l0 = l1;
+            sg0 = sg1;
+            ++acc;
+        }
+    }
+    free(trial);
+    double lap, v;
+    if (rc == ORC_OK) rc = orc_local_energy(s, pos, e_l, &lap, &v);
+    *n_acc = acc;
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Reconfiguration at fixed population (systematic resampling).              */
 /* w_j = exp(log_w_j - max); Ws = sum w; ebar = sum w e / Ws;
  * log_wbar = log(Ws/W) + max; t_s = (s + xi) * (Ws/W);

@@ -198,6 +198,9 @@ struct KArgs {
     double *pos_out, *logw, *el;
     int *nmov;
     int *err;
+    // Metropolis sampling
+    int vmc_steps;
+    double vmc_step;
     // evaluation mode
     int eval;
     double *rho_out, *k_out, *diag_out;
@@ -1511,6 +1514,90 @@ __global__ void __launch_bounds__(kMaxThreads) jastrow_table_grad_kernel(KArgs A
     if (tid == 0 && !isfinite(EL)) report(A.err, kErrNonFinite, slot);
 }
 
+// Metropolis sampling of |Psi|^2, one walker per workgroup: vmc_steps
+// single-electron moves.  Step t of generation gen of slot s draws
+// (u0, u1, u2, u3) from counter (s, gen, t, 2): electron i = floor(u0 N)
+// moves by vmc_step * e, e on the unit sphere (cos theta = 2 u1 - 1,
+// phi = 2 pi u2); the proposal is symmetric, so accepting with probability
+// min(1, rho^2), rho = Psi(x') / Psi(x) (one thread evaluates it from the
+// orbital-projected inverse and the Jastrow sums), leaves |Psi|^2
+// invariant.  An accepted step updates the state as an accepted projection
+// move.  Writes positions, E_L at the end and the accepted count; log w = 0.
+template <bool CORR>
+__global__ void __launch_bounds__(kMaxThreads) vmc_kernel(KArgs A)
+{
+    extern __shared__ double lds[];
+    __shared__ int sflag[8];
+    __shared__ double rho_s;
+    const Layout &L = A.L;
+    const int tid = threadIdx.x, NT = A.nt, slot = blockIdx.x, N = A.N;
+    double *pos = lds + L.pos;
+    const int src = A.idx_in ? A.idx_in[slot] : slot;
+    if (tid == 0) {
+        sflag[5] = (A.err[0] != 0);
+        sflag[6] = 0;
+    }
+    __syncthreads();
+    for (int t = tid; t < 3 * N; t += NT) {
+        const double v = A.pos_in[(size_t)src * 3 * N + t];
+        pos[t] = v;
+        if (!isfinite(v)) sflag[6] = 1;
+    }
+    __syncthreads();
+    if (sflag[5]) return;
+    if (sflag[6]) {
+        if (tid == 0) report(A.err, kErrNonFinite, slot);
+        return;
+    }
+    double EL, LAP = 0.0, V;
+    double *dphi = A.state_out + (size_t)slot * A.state_len + A.dphi_at;
+    const int rc = walker_setup<CORR>(A, lds, dphi, sflag, EL, LAP, V);
+    if (rc) {
+        if (tid == 0) report(A.err, rc, slot);
+        return;
+    }
+    const double *Jo = lds + L.Jo, *Y = lds + L.Y;
+    int acc = 0;
+    for (int it = 0; it < A.vmc_steps; ++it) {
+        double u[4];
+        draw4(A.seed, slot, A.gen, (uint64_t)it, 2, u);
+        const int i = min((int)(u[0] * N), N - 1);
+        const double ct = 2.0 * u[1] - 1.0, st = sqrt(fmax(0.0, 1.0 - ct * ct));
+        double sn, cs;
+        sincos(2.0 * M_PI * u[2], &sn, &cs);
+        const double rold[3] = {uni(pos[3 * i]), uni(pos[3 * i + 1]), uni(pos[3 * i + 2])};
+        const double h = A.vmc_step;
+        const double rnew[3] = {uni(rold[0] + h * (st * cs)), uni(rold[1] + h * (st * sn)), uni(rold[2] + h * ct)};
+        if (tid == 0) {
+            double rd, rd2, ja, jb;
+            basis_dot2(A, rnew, rnew, Y + i * A.Kp, rd, rd2);
+            jastrow_point2<CORR>(A, pos, i, rnew, rnew, ja, jb);
+            rho_s = rd * exp(ja - Jo[i]);
+        }
+        __syncthreads();
+        const double rho = uni(rho_s);
+        if (!isfinite(rho)) {
+            if (tid == 0) report(A.err, kErrNonFinite, slot);
+            return;
+        }
+        if (u[3] < rho * rho) {
+            accept_move<CORR>(A, lds, dphi, i, rold, rnew);
+            __syncthreads();
+            V = uni(V + lds[L.sc + SC_DV]);
+            ++acc;
+        }
+        __syncthreads();   // this step's reads of rho_s and pos are done
+    }
+    EL = uni(local_energy(A, lds, V));
+    for (int t = tid; t < 3 * N; t += NT) A.pos_out[(size_t)slot * 3 * N + t] = pos[t];
+    if (tid == 0) {
+        A.logw[slot] = 0.0;
+        A.el[slot] = EL;
+        A.nmov[slot] = acc;
+        if (!isfinite(EL)) report(A.err, kErrNonFinite, slot);
+    }
+}
+
 // Interval polynomials of the learned correction from its node table
 // tab[2][G][3] = {F, F', F''} at r_k = k h: on [r_k, r_k+1] the quintic in
 // t = (r - r_k) / h that matches value, first and second derivative at both
@@ -2292,7 +2379,8 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
     if (c->lds_bytes > 65536) {
         for (const void *fn : {(const void *)project_kernel<false>, (const void *)project_kernel<true>, c->fixed_fn[0],
                                c->fixed_fn[1], (const void *)jastrow_grad_kernel<false>,
-                               (const void *)jastrow_grad_kernel<true>, (const void *)jastrow_table_grad_kernel})
+                               (const void *)jastrow_grad_kernel<true>, (const void *)jastrow_table_grad_kernel,
+                               (const void *)vmc_kernel<false>, (const void *)vmc_kernel<true>})
             if (fn && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_bytes) !=
                           hipSuccess)
                 return cleanup(LRDMC_EDEVICE, "lrdmc_create: cannot raise the LDS limit");
@@ -2589,6 +2677,37 @@ int lrdmc_net_tabulate_backward(const double *params, int32_t hidden, int32_t n_
     if (e != hipSuccess)
         return fail(nullptr, LRDMC_EDEVICE, std::string("lrdmc_net_tabulate_backward: ") + hipGetErrorString(e));
     return LRDMC_OK;
+}
+
+int lrdmc_vmc(lrdmc_ctx *c, int32_t n_steps, double step, void *stream)
+{
+    if (!c || !c->loaded) return fail(c, LRDMC_EINVAL, "lrdmc_vmc: no walkers loaded");
+    if (n_steps < 0 || !(step > 0.0) || !std::isfinite(step))
+        return fail(c, LRDMC_EINVAL, "lrdmc_vmc: need n_steps >= 0 and finite step > 0");
+    hipStream_t st = (hipStream_t)stream;
+    KArgs A = base_args(c);
+    A.pos_in = c->d_pos[c->cur];
+    A.idx_in = c->pending ? c->d_idx : nullptr;
+    A.pos_out = c->d_pos[c->cur ^ 1];
+    A.state_out = c->d_state[c->cur ^ 1];
+    A.state_len = c->state_len;
+    A.dphi_at = c->dphi_at;
+    A.logw = c->d_logw;
+    A.el = c->d_el;
+    A.nmov = c->d_nmov;
+    A.vmc_steps = n_steps;
+    A.vmc_step = step;
+    if (c->corr)
+        hipLaunchKernelGGL(vmc_kernel<true>, dim3(c->W), dim3(c->nt), c->lds_bytes, st, A);
+    else
+        hipLaunchKernelGGL(vmc_kernel<false>, dim3(c->W), dim3(c->nt), c->lds_bytes, st, A);
+    HIP_TRY(c, hipGetLastError());
+    c->cur ^= 1;
+    c->pending = false;
+    c->projected = false;
+    c->state_ok = false;
+    c->gen += 1;
+    return check_kernel_error(c, st);
 }
 
 int lrdmc_use_generic(lrdmc_ctx *c, int32_t enable)

@@ -56,7 +56,7 @@ _lib = None
 EXPORTS = ("lrdmc_spacing", "lrdmc_spacing_pade", "lrdmc_create", "lrdmc_set_walkers", "lrdmc_project", "lrdmc_branch",
            "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure",
            "lrdmc_jastrow_grad", "lrdmc_set_jastrow", "lrdmc_set_jastrow_table", "lrdmc_jastrow_table_grad",
-           "lrdmc_net_param_count", "lrdmc_net_workspace_size", "lrdmc_net_tabulate", "lrdmc_net_tabulate_backward",
+           "lrdmc_vmc", "lrdmc_net_param_count", "lrdmc_net_workspace_size", "lrdmc_net_tabulate", "lrdmc_net_tabulate_backward",
            "lrdmc_use_generic", "lrdmc_is_specialized", "lrdmc_set_timing", "lrdmc_timing", "lrdmc_generation",
            "lrdmc_last_error", "lrdmc_destroy")
 
@@ -84,6 +84,7 @@ def load():
     lib.lrdmc_set_jastrow.argtypes = [P, D, D]
     lib.lrdmc_set_jastrow_table.argtypes = [P, P, I32, D, I32, P]
     lib.lrdmc_jastrow_table_grad.argtypes = [P, P, P, P, P, P]
+    lib.lrdmc_vmc.argtypes = [P, I32, D, P]
     lib.lrdmc_net_param_count.argtypes = [I32]
     lib.lrdmc_net_param_count.restype = I32
     lib.lrdmc_net_workspace_size.argtypes = [I32, I32]
@@ -104,7 +105,7 @@ def load():
     for name in ("lrdmc_spacing", "lrdmc_spacing_pade", "lrdmc_create", "lrdmc_set_walkers", "lrdmc_project", "lrdmc_branch",
                  "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure",
                  "lrdmc_jastrow_grad", "lrdmc_set_jastrow", "lrdmc_set_jastrow_table",
-                 "lrdmc_jastrow_table_grad", "lrdmc_net_tabulate", "lrdmc_net_tabulate_backward",
+                 "lrdmc_jastrow_table_grad", "lrdmc_vmc", "lrdmc_net_tabulate", "lrdmc_net_tabulate_backward",
                  "lrdmc_use_generic", "lrdmc_set_timing",
                  "lrdmc_timing"):
         getattr(lib, name).restype = C.c_int
@@ -250,6 +251,10 @@ def lrdmc_jastrow_table_grad(ctx, pos, c_j, c_e, gtab, stream=None):
                                            _stream(stream)), ctx)
 
 
+def lrdmc_vmc(ctx, n_steps: int, step: float, stream=None):
+    _check(load().lrdmc_vmc(ctx, int(n_steps), float(step), _stream(stream)), ctx)
+
+
 def lrdmc_net_param_count(hidden: int) -> int:
     return int(load().lrdmc_net_param_count(int(hidden)))
 
@@ -376,6 +381,11 @@ class LRDMC:
 
     def set_jastrow(self, b_ee: float, b_en: float):
         lrdmc_set_jastrow(self.ctx, b_ee, b_en)
+
+    def vmc(self, n_steps: int, step: float):
+        """Metropolis sampling of |Psi|^2: n_steps single-electron moves per
+        walker (one generation index); get_walkers() then has the samples."""
+        lrdmc_vmc(self.ctx, n_steps, step)
 
     def set_jastrow_table(self, tab, r_cut: float = 0.0):
         """Learned correction from its node table [2][G][3] (None removes it)."""
