@@ -173,6 +173,110 @@ def jastrow_grad_bench(name="ar_a0.1", reps=50):
                              "walker_gradients_per_s": cfg.walkers / dt}}
 
 
+def neural_bench(system="ar", walkers=16384, rounds=8, train_steps=60, lr=1e-3, gens=1200, seed=0):
+    """Learned Jastrow correction against the Pade trial function alone.
+    Metropolis samples of |Psi_Pade|^2 (lrdmc_vmc), rounds of variance
+    minimisation of the 2 x 64 SiLU networks (tabulated on 257 nodes up to
+    r_cut = 6 bohr) each followed by a fresh sample (the parameters with the
+    lowest fresh-sample variance are kept), then LRDMC with both trial
+    functions at three spacings: energies with reblocked errors, move rates,
+    the time to sigma(E) = 1 mHa extrapolated from each run
+    (wall x (sigma / 1 mHa)^2), and E0 of the fit E0 + k a^2 (the lattice
+    bias of LRDMC depends on the trial function; the fixed-node limits must
+    agree, the determinant and hence the nodes being the same).
+    system "ar": Ar with screened hydrogenic orbitals in the Ar-like basis;
+    "he": He with a nodeless s orbital (fixed node exact)."""
+    import torch
+    from paper_1909_01589_amd import inputs, neural, stats
+    from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_spacing
+    if system == "ar":
+        s, spacings, step, E_ref = inputs.ar_screened(), (0.05, 0.035, 0.025), 0.25, None
+        moves_per_electron, t_equil = 8.0, 2.0
+    elif system == "he":
+        s, spacings, step, E_ref = inputs.helium_nodeless(), (0.25, 0.15, 0.1), 0.6, HE_EXACT
+        moves_per_electron, t_equil = 20.0, 10.0
+    else:
+        raise ValueError(system)
+    Z, N = s.z_max, s.n_elec
+    pos0 = inputs.initial_walkers(s, walkers, seed)
+    t0 = time.perf_counter()
+
+    def note(msg):
+        print(f"[neural {system} {time.perf_counter() - t0:6.1f}s] {msg}", file=sys.stderr, flush=True)
+
+    g = LRDMC(s, spacings[0], spacings[0], 1.0, 0.01, walkers, seed=seed + 3, rotate=1, refresh=8)
+    g.set_walkers(pos0, 0)
+    g.vmc(3000, step)
+    nj = neural.NeuralJastrow(64, 257, 6.0, seed=seed)
+    t_train = time.perf_counter()
+    hist = neural.fit_vmc(nj, g, rounds=rounds, steps=train_steps, lr=lr, vmc_steps=300, step=step,
+                          log=lambda r: note(f"round {r['round']}: VMC E={r['vmc_E']:.4f} var={r['vmc_var']:.3f}"))
+    t_train = time.perf_counter() - t_train
+    g.vmc(300, step)
+    e_n = g.get_walkers()["e_l"]
+    vmc_neural = dict(E=float(e_n.mean()), var=float(e_n.var()))
+    g.close()
+
+    def projection(with_net, a):
+        rc, ap, _ = lrdmc_spacing(Z, a)
+        ap = max(ap, a)
+        g = LRDMC(s, a, ap, rc, 1.0, walkers, seed=seed + 11, rotate=1, refresh=8)
+        if with_net:
+            nj.attach(g)
+        g.set_walkers(pos0, 0)
+        g.vmc(2000, step)
+        p = g.get_walkers()["pos"]
+        delta = float(g.eval_moves(p)[2][:, 6].mean())
+        g.close()
+        tau = moves_per_electron * N / delta
+        g = LRDMC(s, a, ap, rc, tau, walkers, seed=seed + 11, rotate=1, refresh=8)
+        if with_net:
+            nj.attach(g)
+        g.set_walkers(p, 0)
+        g.run(int(t_equil / tau) + 20)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        out = g.run(gens)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        E, sig = stats.estimate(out["log_wbar"].cpu().numpy(), out["ebar"].cpu().numpy(), p=None)
+        moves = int(out["n_moves"].sum())
+        g.close()
+        row = dict(a=a, a_prime=ap, r_c=rc, tau=tau, generations=gens, E=E, sigma=sig, wall_s=dt,
+                   moves_per_s=moves / dt, t_1mHa_s=dt * (sig / 1e-3) ** 2)
+        note(f"{'neural' if with_net else 'pade'} a={a}: E={E:.5f} +- {sig:.5f} t(1mHa)={row['t_1mHa_s']:.1f}s")
+        return row
+
+    res = {}
+    for label, net in (("pade", False), ("neural", True)):
+        rows = [projection(net, a) for a in spacings]
+        E0, s0, chi2 = _fit_e0_linear([r["a"] for r in rows], [r["E"] for r in rows], [r["sigma"] for r in rows])
+        res[label] = dict(rows=rows, E0=E0, sigma_E0=s0, chi2_dof=chi2)
+    ratios = [p["t_1mHa_s"] / q["t_1mHa_s"] for p, q in zip(res["pade"]["rows"], res["neural"]["rows"])]
+    dE0 = res["neural"]["E0"] - res["pade"]["E0"]
+    return {"neural": {
+        "system": s.name, "walkers": walkers, "network": "2 x 64 SiLU per pair type, 257-node table, r_cut 6",
+        "training": dict(rounds=rounds, steps_per_round=train_steps, lr=lr, wall_s=t_train, history=hist),
+        "vmc": dict(pade=dict(E=hist[0]["vmc_E"], var=hist[0]["vmc_var"]), neural=vmc_neural),
+        "lrdmc": res, "time_to_1mHa_ratio_pade_over_neural": ratios,
+        "E0_difference": dE0, "E0_difference_sigma": float(np.hypot(res["pade"]["sigma_E0"],
+                                                                     res["neural"]["sigma_E0"])),
+        "reference_E": E_ref, "wall_s": time.perf_counter() - t0}}
+
+
+def _fit_e0_linear(a, E, sig):
+    """Weighted fit E = E0 + k a^2: (E0, sigma_E0, chi2 per degree of freedom)."""
+    a2 = np.asarray(a, dtype=np.float64) ** 2
+    E = np.asarray(E, dtype=np.float64)
+    w = 1.0 / np.asarray(sig, dtype=np.float64) ** 2
+    X = np.stack([np.ones_like(a2), a2], axis=1)
+    cov = np.linalg.inv(X.T @ (X * w[:, None]))
+    beta = cov @ (X.T @ (w * E))
+    r = E - X @ beta
+    dof = max(1, len(E) - 2)
+    return float(beta[0]), float(np.sqrt(cov[0, 0])), float((w * r * r).sum() / dof)
+
+
 def copy_probe():
     """A plain device copy of 512 MiB: the reference for scaling the HBM byte
     counters (FETCH_SIZE, WRITE_SIZE) of a profiled run."""
@@ -280,6 +384,8 @@ def main():
     ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
     ap.add_argument("--jastrow-grad", action="store_true",
                     help="only time the Jastrow-parameter gradient kernel and exit")
+    ap.add_argument("--neural", choices=["ar", "he"], default=None,
+                    help="only run the learned-Jastrow comparison (VMC, training, LRDMC scan) and exit")
     ap.add_argument("--ascan", action="store_true",
                     help="only run the spacing scan on helium for the three lattice schemes and exit")
     args = ap.parse_args()
@@ -302,6 +408,9 @@ def main():
         return
     if args.ascan:
         print(json.dumps(ascan()), flush=True)
+        return
+    if args.neural:
+        print(json.dumps(neural_bench(args.neural)), flush=True)
         return
     if args.jastrow_grad:
         print(json.dumps(jastrow_grad_bench()), flush=True)

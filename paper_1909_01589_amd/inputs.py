@@ -314,3 +314,84 @@ def jastrow_table(seed: int = 0, n_nodes: int = 33, r_cut: float = 4.0, scale: f
         f = scale * env * P(rng.normal(size=4))(P([0.0, 1.0 / r_cut]))
         tab[t, :, 0], tab[t, :, 1], tab[t, :, 2] = f(r), f.deriv(1)(r), f.deriv(2)(r)
     return tab
+
+
+# Occupied orbitals of the closed s/p shells in filling order: (n, l, axis);
+# axis 0/1/2 = x/y/z for p.
+_SP_ORBITALS = ((1, 0, 0), (2, 0, 0), (2, 1, 0), (2, 1, 1), (2, 1, 2), (3, 0, 0), (3, 1, 0), (3, 1, 1), (3, 1, 2))
+
+
+def _slater_zeff(Z: int, n: int) -> float:
+    """Slater's screening rules for an s/p electron of shell n of the neutral
+    atom with closed s/p shells filled in the order 1s 2s2p 3s3p."""
+    cap = {1: 2, 2: 8, 3: 8}
+    occ, left = {}, Z
+    for m in (1, 2, 3):
+        occ[m] = min(cap[m], left)
+        left -= occ[m]
+    s = (occ[n] - 1) * (0.30 if n == 1 else 0.35)
+    if n >= 2:
+        s += 0.85 * occ[n - 1]
+    if n >= 3:
+        s += 1.0 * sum(occ[m] for m in range(1, n - 1))
+    return Z - s
+
+
+def _hydrogenic_radial(n: int, l: int, zeta: float, r: np.ndarray) -> np.ndarray:
+    """g(r) with orbital = g(r) for s and x_axis g(r) for p: screened
+    hydrogenic shapes of shells 1 to 3 (unnormalized)."""
+    x = zeta * r
+    if (n, l) == (1, 0):
+        return np.exp(-x)
+    if (n, l) == (2, 0):
+        return (2.0 - x) * np.exp(-x / 2.0)
+    if (n, l) == (2, 1):
+        return np.exp(-x / 2.0)
+    if (n, l) == (3, 0):
+        return (27.0 - 18.0 * x + 2.0 * x * x) * np.exp(-x / 3.0)
+    if (n, l) == (3, 1):
+        return (6.0 - x) * np.exp(-x / 3.0)
+    raise ValueError("shells 1s to 3p only")
+
+
+def atom_screened(Z: int, counts, alpha0: float, beta: float, b_ee: float = 1.0, b_en: float = 3.0,
+                  name: str = "") -> System:
+    """Closed-shell atom (Z in 2, 4, 10, 12, 18) whose determinant, times the
+    electron-nucleus Pade factor exp(-Z r / (1 + b_en r)), approximates
+    Slater-screened hydrogenic orbitals: each MO column is the weighted
+    least-squares fit (weight r^(2 + 2l) on a radial grid) of
+    g(r) exp(+Z r / (1 + b_en r)) by the basis functions of its angular type.
+    A trial function with physically placed nodes, in the same even-tempered
+    basis as `atom`."""
+    if Z not in (2, 4, 10, 12, 18):
+        raise ValueError("closed s/p shells only: Z in 2, 4, 10, 12, 18")
+    n_up = n_dn = Z // 2
+    nuc_l, l_l, a_l = _shells_for(0, counts, alpha0, beta)
+    K = int(sum((2 * l + 1) for l in l_l))
+    # first function index of every shell
+    first, at = [], 0
+    for l in l_l:
+        first.append(at)
+        at += 2 * l + 1
+    r = np.geomspace(1e-5, 20.0, 6000)
+    dr = np.gradient(r)
+    jen = np.exp(-Z * r / (1.0 + b_en * r))
+    mo = np.zeros((K, n_up))
+    for j, (n, l, axis) in enumerate(_SP_ORBITALS[:n_up]):
+        g = _hydrogenic_radial(n, l, _slater_zeff(Z, n), r)
+        cols = [q for q, ll in enumerate(l_l) if ll == l]
+        Bm = np.stack([jen * np.exp(-a_l[q] * r * r) for q in cols], axis=1)
+        w = np.sqrt(r ** (2 + 2 * l) * dr)
+        c, *_ = np.linalg.lstsq(Bm * w[:, None], g * w, rcond=1e-13)
+        c /= np.max(np.abs(c))
+        for q, cq in zip(cols, c):
+            mo[first[q] + (axis if l == 1 else 0), j] = cq
+    return System(Z=np.array([float(Z)]), R=np.zeros((1, 3)), n_up=n_up, n_dn=n_dn,
+                  shell_nuc=nuc_l, shell_l=l_l, shell_alpha=a_l, mo=mo,
+                  b_ee=b_ee, b_en=b_en, name=name or f"Z{Z}_screened")
+
+
+def ar_screened() -> System:
+    """Ar (Z=18, 9 up 9 down) in the Ar-like basis (K=64 s/p/d Gaussians
+    0.05*2.5^k) with screened hydrogenic orbitals (1s 2s 2p 3s 3p)."""
+    return atom_screened(18, basis_alloc(64), 0.05, 2.5, name="ar_screened")

@@ -157,11 +157,14 @@ class NeuralJastrow:
         """(J[W], E_L[W]) with the current parameters, differentiable."""
         return TableJastrow.apply(self.table(), engine, pos, self.r_cut)
 
-    def train(self, engine: LRDMC, pos, steps: int = 100, lr: float = 1e-3, power: float = 1.0,
+    def train(self, engine: LRDMC, pos, steps: int = 100, lr: float = 1e-3, power: float = 0.0,
               log: Optional[list] = None):
         """Variance minimisation of E_L over the configurations pos (device
         [W][N][3], sampled with the current trial function) with Adam.
-        Returns the (mean, variance) history as floats."""
+        power = 0: the plain variance over the fixed sample (robust when the
+        trial function moves far from the sampling one); power > 0: the
+        correlated-sampling weights exp(power (J - J0)).  Returns the
+        (mean, variance) history as floats."""
         pos = torch.as_tensor(pos, dtype=torch.float64).to(engine.device).contiguous()
         with torch.no_grad():
             j0, _ = self.energies(engine, pos)
@@ -176,3 +179,35 @@ class NeuralJastrow:
             hist.append((float(mean.detach()), float(var.detach())))
         self.attach(engine)
         return hist
+
+
+def fit_vmc(nj: NeuralJastrow, engine: LRDMC, rounds: int = 8, steps: int = 60, lr: float = 1e-3,
+            vmc_steps: int = 300, step: float = 0.25, power: float = 0.0, log=None):
+    """Rounds of variance minimisation on Metropolis samples of |Psi|^2 from
+    the engine's walkers (lrdmc_vmc), each followed by a fresh sample with the
+    updated trial function; the parameters with the lowest variance of E_L
+    on a fresh sample (held out from their own training) are kept and set on
+    the engine.  The engine's walkers must be equilibrated samples.  Returns
+    one dict per round."""
+    out = engine.get_walkers()
+    best_var = float(out["e_l"].var())
+    best = nj.params.detach().clone()
+    hist = [dict(round=-1, vmc_E=float(out["e_l"].mean()), vmc_var=best_var)]
+    pos = out["pos"]
+    for r in range(rounds):
+        h = nj.train(engine, pos, steps=steps, lr=lr, power=power)
+        engine.vmc(vmc_steps, step)
+        out = engine.get_walkers()
+        e = out["e_l"]
+        row = dict(round=r, train_var_start=h[0][1], train_var_end=h[-1][1], vmc_E=float(e.mean()),
+                   vmc_var=float(e.var()), acceptance=float(out["n_moves"].double().mean()) / vmc_steps)
+        hist.append(row)
+        if log is not None:
+            log(row)
+        if row["vmc_var"] < best_var:
+            best_var, best = row["vmc_var"], nj.params.detach().clone()
+        pos = out["pos"]
+    with torch.no_grad():
+        nj.params.copy_(best)
+    nj.attach(engine)
+    return hist
