@@ -190,7 +190,7 @@ def neural_bench(system="ar", walkers=16384, rounds=8, train_steps=60, lr=1e-3, 
     from paper_1909_01589_amd import inputs, neural, stats
     from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_spacing
     if system == "ar":
-        s, spacings, step, E_ref = inputs.ar_screened(), (0.05, 0.035, 0.025), 0.25, None
+        s, spacings, step, E_ref = inputs.ar_screened(), (0.06, 0.045, 0.035, 0.025, 0.0175), 0.25, None
         moves_per_electron, t_equil = 8.0, 2.0
     elif system == "he":
         s, spacings, step, E_ref = inputs.helium_nodeless(), (0.25, 0.15, 0.1), 0.6, HE_EXACT
@@ -250,8 +250,14 @@ def neural_bench(system="ar", walkers=16384, rounds=8, train_steps=60, lr=1e-3, 
     res = {}
     for label, net in (("pade", False), ("neural", True)):
         rows = [projection(net, a) for a in spacings]
-        E0, s0, chi2 = _fit_e0_linear([r["a"] for r in rows], [r["E"] for r in rows], [r["sigma"] for r in rows])
-        res[label] = dict(rows=rows, E0=E0, sigma_E0=s0, chi2_dof=chi2)
+        a_, E_, s_ = [r["a"] for r in rows], [r["E"] for r in rows], [r["sigma"] for r in rows]
+        if len(rows) >= 4:
+            E0, s0, chi2 = _fit_e0(a_, E_, s_)           # E0 + k1 a^2 + k2 a^4
+            fit = "E0 + k1 a^2 + k2 a^4"
+        else:
+            E0, s0, chi2 = _fit_e0_linear(a_, E_, s_)    # E0 + k1 a^2
+            fit = "E0 + k1 a^2"
+        res[label] = dict(rows=rows, fit=fit, E0=E0, sigma_E0=s0, chi2_dof=chi2)
     ratios = [p["t_1mHa_s"] / q["t_1mHa_s"] for p, q in zip(res["pade"]["rows"], res["neural"]["rows"])]
     dE0 = res["neural"]["E0"] - res["pade"]["E0"]
     return {"neural": {
