@@ -283,6 +283,85 @@ def _fit_e0_linear(a, E, sig):
     return float(beta[0]), float(np.sqrt(cov[0, 0])), float((w * r * r).sum() / dof)
 
 
+def zscan(Zs=(10, 18, 36, 54), walkers=8192, gens=20, warmup=10, moves_per_electron=2.0, seed=0):
+    """Cost of the projection against the atomic number at a = 1/(3.5 Z)
+    (the spacing of the paper's Table I and its CPU-time scaling figure) on
+    the Z-sweep atoms, for the single grid and this paper's double grid
+    (Eq. (3), r_c from Eq. (S-13), a' from Eq. (6)).  Walkers are first
+    brought to the trial function's |Psi|^2 by Metropolis sampling
+    (30 N steps).  Reported per Z and grid: projection time per second
+    W tau n_gen / wall (what the double grid improves), GPU seconds per walker
+    and unit projection time, electron-moves/s, the kernel time per
+    generation; per Z the acceleration (ratio of costs), the single/double
+    move-rate ratio Delta_s / Delta_d beside Eq. (5) with the sampled
+    N_core = <sum_i p(r_i)>; and power-law exponents of the cost in Z.  tau
+    per generation is set for about `moves_per_electron` moves per electron."""
+    import torch
+    from paper_1909_01589_amd import inputs
+    from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_spacing, lrdmc_set_timing, lrdmc_timing
+    rows, per_z = [], []
+    for Z in Zs:
+        s = inputs.zsweep_atom(Z, seed)
+        N = s.n_elec
+        a = 1.0 / (3.5 * Z)
+        g = LRDMC(s, a, a, 1.0, 1.0, walkers, seed=seed, rotate=1, refresh=8, grids=1)
+        g.set_walkers(inputs.initial_walkers(s, walkers, seed), 0)
+        g.vmc(30 * N, 0.2)
+        out = g.get_walkers()
+        pos0 = out["pos"].clone()
+        acc = float(out["n_moves"].double().mean()) / (30 * N)
+        g.close()
+        rc_d, ap_d, nc_model = lrdmc_spacing(float(Z), a)
+        ap_d = max(ap_d, a)
+        nc_sampled = _switch_sum(pos0.cpu().numpy(), s.R[0], rc_d, 0)
+        deltas = {}
+        for mode in ("single_grid", "double_grid"):
+            if mode == "double_grid":
+                rc, ap, kw = rc_d, ap_d, dict(grids=2)
+            else:
+                rc, ap, kw = 1.0, a, dict(grids=1)
+            g = LRDMC(s, a, ap, rc, 1.0, walkers, seed=seed, rotate=1, refresh=8, **kw)
+            delta = float(g.eval_moves(pos0)[2][:, 6].mean())
+            g.close()
+            deltas[mode] = delta
+            tau = moves_per_electron * N / delta
+            g = LRDMC(s, a, ap, rc, tau, walkers, seed=seed, rotate=1, refresh=8, **kw)
+            g.set_walkers(pos0, 0)
+            g.run(warmup)
+            torch.cuda.synchronize()
+            print(f"[zscan] Z={Z} {mode}: tau={tau:.3e}, warm", file=sys.stderr, flush=True)
+            lrdmc_set_timing(g.ctx, 1)
+            t0 = time.perf_counter()
+            out = g.run(gens)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            tm = lrdmc_timing(g.ctx)
+            moves = int(out["n_moves"].sum())
+            g.close()
+            rows.append(dict(Z=Z, mode=mode, electrons=N, basis=s.n_basis, a=a, a_prime=ap, r_c=rc, tau=tau,
+                             delta=delta, moves_per_s=moves / dt,
+                             kernel_ms_per_generation=tm[0] / max(1.0, tm[1]),
+                             projection_time_per_s=walkers * tau * gens / dt,
+                             cost_s_per_walker_per_unit_time=dt / (walkers * gens * tau)))
+            print(f"[zscan] Z={Z} {mode}: a'={ap:.4f} {moves / dt / 1e6:.1f} M moves/s, "
+                  f"{rows[-1]['projection_time_per_s']:.3g} walker-Ha^-1 per s", file=sys.stderr, flush=True)
+        c = {x["mode"]: x["cost_s_per_walker_per_unit_time"] for x in rows if x["Z"] == Z}
+        ratio = ap_d / a
+        per_z.append(dict(Z=Z, vmc_acceptance=acc, n_core_model=nc_model, n_core_sampled=nc_sampled,
+                          a_prime_over_a=ratio, acceleration=c["single_grid"] / c["double_grid"],
+                          move_rate_ratio=deltas["single_grid"] / deltas["double_grid"],
+                          eq5_sampled=1.0 / (nc_sampled / N + (N - nc_sampled) / N * ratio ** -2),
+                          eq5_model=1.0 / (nc_model / N + (N - nc_model) / N * ratio ** -2)))
+    fits = {}
+    for mode in ("single_grid", "double_grid"):
+        r = [x for x in rows if x["mode"] == mode]
+        fits[mode] = float(np.polyfit(np.log([x["Z"] for x in r]),
+                                      np.log([x["cost_s_per_walker_per_unit_time"] for x in r]), 1)[0])
+    return {"zscan": {"walkers": walkers, "generations": gens, "rows": rows, "per_Z": per_z,
+                      "cost_exponent": fits,
+                      "cost": "GPU seconds per walker per unit projection time (1/Ha), at a = 1/(3.5 Z)"}}
+
+
 def copy_probe():
     """A plain device copy of 512 MiB: the reference for scaling the HBM byte
     counters (FETCH_SIZE, WRITE_SIZE) of a profiled run."""
@@ -392,6 +471,8 @@ def main():
                     help="only time the Jastrow-parameter gradient kernel and exit")
     ap.add_argument("--neural", choices=["ar", "he"], default=None,
                     help="only run the learned-Jastrow comparison (VMC, training, LRDMC scan) and exit")
+    ap.add_argument("--zscan", action="store_true",
+                    help="only run the single/double-grid cost scan over Z = 10, 18, 36, 54 and exit")
     ap.add_argument("--ascan", action="store_true",
                     help="only run the spacing scan on helium for the three lattice schemes and exit")
     args = ap.parse_args()
@@ -414,6 +495,9 @@ def main():
         return
     if args.ascan:
         print(json.dumps(ascan()), flush=True)
+        return
+    if args.zscan:
+        print(json.dumps(zscan()), flush=True)
         return
     if args.neural:
         print(json.dumps(neural_bench(args.neural)), flush=True)
