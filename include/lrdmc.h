@@ -302,9 +302,14 @@ int lrdmc_net_tabulate_backward(const double *params, int32_t hidden, int32_t n_
  * any system, kernels built for fixed system sizes (electrons per spin, basis
  * functions, nuclei; see LRDMC_FIXED_SHAPES in the kernel source).
  * lrdmc_create picks such a kernel when the system's sizes and LDS layout
- * match one; both compute the same method and agree to rounding.
- * lrdmc_use_generic(ctx, enable != 0) forces the general kernel for later
- * launches (for comparison and testing); errors: LRDMC_EINVAL (NULL).
+ * match one; both compute the same method and agree to rounding.  For large
+ * systems (a walker state above 40 KB) the general kernels keep the
+ * orbital-projected inverse in the walker's device-memory state instead of
+ * LDS, so that more walkers share a compute unit; results are the same.
+ * lrdmc_use_generic(ctx, mode) for later launches (comparison and testing):
+ * 0 = automatic, 1 = the general kernel, 2 = the general kernel with the
+ * inverse in device memory at any size.  Errors: LRDMC_EINVAL (NULL, mode
+ * outside 0..2).
  * lrdmc_is_specialized returns 1 when the next projection runs a fixed-size
  * kernel, else 0 (also for NULL). */
 int lrdmc_use_generic(lrdmc_ctx *ctx, int32_t enable);

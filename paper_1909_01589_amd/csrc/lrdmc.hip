@@ -73,6 +73,7 @@ struct Layout {
     int fac;    // [2][ns]           elimination factors
     int bvb;    // [EB][5][K]        basis blocks of a batch of electrons
     int EB;     // electrons per batch
+    int yg;     // 1: Y is not in LDS but at the start of the walker's HBM state blob
     int total;
 };
 
@@ -88,13 +89,14 @@ constexpr __host__ __device__ int threads_for(int M)
 // LDS layout of one walker.  The electron batch of the generation start grows until the block reaches
 // `target` bytes (or all electrons fit), never below one electron.
 constexpr __host__ __device__ Layout make_layout(int N, int ns, int K, int Kp, int M, int n_nuc, int NT,
-                                                 size_t target)
+                                                 size_t target, bool yg = false)
 {
     Layout L{};
     int o = 0;
     auto take = [&](int n) { int r = o; o += n; return r; };
     L.pos = take(3 * N);
-    L.Y = take(N * Kp);
+    L.yg = yg ? 1 : 0;
+    L.Y = yg ? 0 : take(N * Kp);
     L.Ainv = take(2 * ns * ns);
     L.dld = 4 * ns + 1;
     L.gD = take(4 * N);
@@ -703,7 +705,17 @@ __device__ __forceinline__ double psi_lap_term(const double *d, const double *j)
 // Gauss-Jordan inversion with partial pivoting, Y = C Ainv, determinant and
 // Jastrow derivatives, local energy.  Returns an error code (uniform);
 // EL, LAP (sum_i lap_i Psi/Psi) and V reach every thread.
-template <bool CORR>
+// The orbital-projected inverse Y[N][Kp]: in LDS, or (large systems) at the
+// start of the walker slot's output state blob in HBM, where it stays for the
+// whole generation (L2-resident) and is read and updated in place.
+template <bool YG>
+__device__ __forceinline__ double *y_base(const KArgs &A, double *lds)
+{
+    if constexpr (YG) return A.state_out + (size_t)blockIdx.x * A.state_len;
+    else return lds + A.L.Y;
+}
+
+template <bool CORR, bool YG>
 __device__ __forceinline__ int walker_setup(const KArgs &A, double *lds, double *dphi, int *sflag, double &EL, double &LAP,
                             double &V)
 {
@@ -792,7 +804,7 @@ __device__ __forceinline__ int walker_setup(const KArgs &A, double *lds, double 
     __syncthreads();
 
     // Y[i][mu] = sum_j C[mu][j] Ainv_s[j][i_s]
-    double *Y = lds + L.Y;
+    double *Y = y_base<YG>(A, lds);
     for (int t = tid; t < N * K; t += NT) {
         const int i = t / K, mu = t - i * K;
         const int s = spin_of(A, i), n = s ? A.n_dn : A.n_up, il = s ? i - A.n_up : i;
@@ -849,12 +861,12 @@ __device__ __forceinline__ void wave_sync()
 // each step evaluates the +/- pair (m, m + 1) along one axis of one grid of
 // one electron.  Returns the sum of the weights; with diag, stores rho and k
 // and accumulates sum k, L^a and V_sf.
-template <bool CORR>
+template <bool CORR, bool YG>
 __device__ __forceinline__ double move_table(const KArgs &A, double *lds, const double *Rm, int c0, int c1,
                                              int *last, double *rho_g, double *k_g, double acc[3], bool diag)
 {
     const Layout &L = A.L;
-    const double *pos = lds + L.pos, *Y = lds + L.Y, *Jo = lds + L.Jo;
+    const double *pos = lds + L.pos, *Y = y_base<YG>(A, lds), *Jo = lds + L.Jo;
     double *T = lds + L.T;
     double part = 0.0;
     for (int m = c0; m < c1; m += 2) {
@@ -955,7 +967,7 @@ __device__ __forceinline__ double seq_dot(const double *x, const double *y, int 
 //     of kp (Jastrow gradient, Laplacian and own sum of k; the potential
 //     change into the block scalars).
 // Item ranges of different cost start on wavefront boundaries.
-template <bool CORR>
+template <bool CORR, bool YG>
 __device__ __forceinline__ void accept_move(const KArgs &A, double *lds, double *dphi, int k, const double rold[3],
                             const double rnew[3])
 {
@@ -964,7 +976,7 @@ __device__ __forceinline__ void accept_move(const KArgs &A, double *lds, double 
     const int s = spin_of(A, k), n = s ? A.n_dn : A.n_up, kl = s ? k - A.n_up : k, i0 = s ? A.n_up : 0;
     const int np = N + A.n_nuc;
     double *pos = lds + L.pos, *bv = lds + L.bv, *vrow = lds + L.vrow, *wrow = lds + L.wrow;
-    double *colk = lds + L.colk, *Yk = lds + L.Yk, *Y = lds + L.Y;
+    double *colk = lds + L.colk, *Yk = lds + L.Yk, *Y = y_base<YG>(A, lds);
     double *gD = lds + L.gD, *gJ = lds + L.gJ, *Jo = lds + L.Jo, *dq = lds + L.dq, *kp = lds + L.kp;
     double *inv = lds + L.Ainv + s * ns * ns;
     auto up64 = [](int x) { return (x + 63) & ~63; };
@@ -1094,7 +1106,7 @@ __device__ __forceinline__ double local_energy(const KArgs &A, const double *lds
 
 // One workgroup per walker slot: a generation of continuous-time projection,
 // or (eval != 0) the move table at frozen positions.
-template <bool CORR>
+template <bool CORR, bool YG>
 __device__ __forceinline__ void project_body(const KArgs &A)
 {
     extern __shared__ double lds[];
@@ -1124,17 +1136,24 @@ __device__ __forceinline__ void project_body(const KArgs &A)
     }
 
     double EL, LAP = 0.0, V;
-    const int blob = A.dphi_at - 2;  // LDS part of the state blob
+    const int blob = A.dphi_at - 2;  // Y and the LDS part of the state blob
+    // LDS part: [Ainv, Jo + N) at blob offset N Kp (with Y in LDS, Y precedes
+    // Ainv and is copied with it)
+    const int lds0 = YG ? L.Ainv : L.Y, blob0 = YG ? N * A.Kp : 0;
     double *dphi = A.state_out + (size_t)slot * A.state_len + A.dphi_at;
     if (A.state_in && !A.eval) {
         const double *sb = A.state_in + (size_t)src * A.state_len;
-        for (int t = tid; t < blob; t += NT) lds[L.Y + t] = sb[t];
+        if (YG) {
+            double *yo = A.state_out + (size_t)slot * A.state_len;
+            for (int t = tid; t < blob0; t += NT) yo[t] = sb[t];
+        }
+        for (int t = tid; t < blob - blob0; t += NT) lds[lds0 + t] = sb[blob0 + t];
         for (int t = tid; t < N * L.dld; t += NT) dphi[t] = sb[A.dphi_at + t];
         EL = uni(sb[blob]);
         V = uni(sb[blob + 1]);
         __syncthreads();
     } else {
-        int rc = walker_setup<CORR>(A, lds, dphi, sflag, EL, LAP, V);
+        int rc = walker_setup<CORR, YG>(A, lds, dphi, sflag, EL, LAP, V);
         if (rc) {
             if (tid == 0) report(A.err, rc, slot);
             return;
@@ -1148,7 +1167,7 @@ __device__ __forceinline__ void project_body(const KArgs &A)
     if (A.eval) {
         double acc[3] = {0.0, 0.0, 0.0};
         int last = -1;
-        const double part = move_table<CORR>(A, lds, rng_slot(rng, 0), c0, c1, &last,
+        const double part = move_table<CORR, YG>(A, lds, rng_slot(rng, 0), c0, c1, &last,
                                        A.rho_out ? A.rho_out + (size_t)slot * M : nullptr,
                                        A.k_out ? A.k_out + (size_t)slot * M : nullptr, acc, true);
         double v[4] = {acc[0], acc[1], acc[2], part};
@@ -1175,7 +1194,7 @@ __device__ __forceinline__ void project_body(const KArgs &A)
         const double *R = rng_slot(rng, it);
         int last = -1;
         double dummy[3];
-        const double part = move_table<CORR>(A, lds, R, c0, c1, &last, nullptr, nullptr, dummy, false);
+        const double part = move_table<CORR, YG>(A, lds, R, c0, c1, &last, nullptr, nullptr, dummy, false);
 
         // inclusive prefix of the per-thread sums within each wavefront; the
         // wavefront totals go to LDS
@@ -1260,7 +1279,7 @@ __device__ __forceinline__ void project_body(const KArgs &A)
             for (int c = 0; c < 3; ++c) rnew[c] = uni(rnew[c]);
             const double rold[3] = {uni(pos[3 * k]), uni(pos[3 * k + 1]), uni(pos[3 * k + 2])};
             __syncthreads();   // every wavefront is done with T and xs
-            accept_move<CORR>(A, lds, dphi, k, rold, rnew);
+            accept_move<CORR, YG>(A, lds, dphi, k, rold, rnew);
             if (((it + 1) & 7) == 0) refill_rng(A, rng, slot, it + 1);
         }
         __syncthreads();
@@ -1275,7 +1294,7 @@ __device__ __forceinline__ void project_body(const KArgs &A)
     for (int t = tid; t < 3 * N; t += NT) A.pos_out[(size_t)slot * 3 * N + t] = pos[t];
     if (A.save_state) {
         double *sb = A.state_out + (size_t)slot * A.state_len;
-        for (int t = tid; t < blob; t += NT) sb[t] = lds[L.Y + t];
+        for (int t = tid; t < blob - blob0; t += NT) sb[blob0 + t] = lds[lds0 + t];
         if (tid == 0) {
             sb[blob] = EL;
             sb[blob + 1] = V;
@@ -1291,10 +1310,10 @@ __device__ __forceinline__ void project_body(const KArgs &A)
 
 // The projection kernel for any system: sizes and LDS offsets come from the
 // arguments.
-template <bool CORR>
+template <bool CORR, bool YG>
 __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) project_kernel(KArgs A)
 {
-    project_body<CORR>(A);
+    project_body<CORR, YG>(A);
 }
 
 // The same kernel built for one system size: electron counts, basis size and
@@ -1316,7 +1335,7 @@ project_kernel_fixed(KArgs A)
     constexpr Layout L = make_layout(S::N, S::ns, KB, S::Kp, S::M, NNUC, S::NT, 0);
     A.N = S::N; A.n_up = NUP; A.n_dn = NDN; A.ns = S::ns; A.K = KB; A.Kp = S::Kp; A.M = S::M;
     A.n_nuc = NNUC; A.nt = S::NT; A.mpe = 12; A.L = L;
-    project_body<CORR>(A);
+    project_body<CORR, false>(A);
 }
 
 // Derivatives with respect to the Pade parameters theta = (b_ee, b_en) of
@@ -1329,7 +1348,7 @@ project_kernel_fixed(KArgs A)
 // out[slot][6] = {E_L, J, dJ/db_ee, dJ/db_en, dE_L/db_ee, dE_L/db_en}.  With
 // CORR, J and E_L include the learned correction (which does not depend on
 // theta).
-template <bool CORR>
+template <bool CORR, bool YG>
 __global__ void __launch_bounds__(kMaxThreads) jastrow_grad_kernel(KArgs A, double *out)
 {
     extern __shared__ double lds[];
@@ -1351,7 +1370,7 @@ __global__ void __launch_bounds__(kMaxThreads) jastrow_grad_kernel(KArgs A, doub
     }
     double EL, LAP = 0.0, V;
     double *dphi = A.state_out + (size_t)slot * A.state_len + A.dphi_at;
-    const int rc = walker_setup<CORR>(A, lds, dphi, sflag, EL, LAP, V);
+    const int rc = walker_setup<CORR, YG>(A, lds, dphi, sflag, EL, LAP, V);
     if (rc) {
         if (tid == 0) report(A.err, rc, slot);
         return;
@@ -1454,6 +1473,7 @@ __device__ __forceinline__ void corr_adjoint(const KArgs &A, int type, double r,
     unsafeAtomicAdd(g + 5, e2 * h * h);
 }
 
+template <bool YG>
 __global__ void __launch_bounds__(kMaxThreads) jastrow_table_grad_kernel(KArgs A, const double *cJ,
                                                                          const double *cE, double *gtab)
 {
@@ -1476,7 +1496,7 @@ __global__ void __launch_bounds__(kMaxThreads) jastrow_table_grad_kernel(KArgs A
     }
     double EL, LAP = 0.0, V;
     double *dphi = A.state_out + (size_t)slot * A.state_len + A.dphi_at;
-    const int rc = walker_setup<true>(A, lds, dphi, sflag, EL, LAP, V);
+    const int rc = walker_setup<true, YG>(A, lds, dphi, sflag, EL, LAP, V);
     if (rc) {
         if (tid == 0) report(A.err, rc, slot);
         return;
@@ -1523,7 +1543,7 @@ __global__ void __launch_bounds__(kMaxThreads) jastrow_table_grad_kernel(KArgs A
 // orbital-projected inverse and the Jastrow sums), leaves |Psi|^2
 // invariant.  An accepted step updates the state as an accepted projection
 // move.  Writes positions, E_L at the end and the accepted count; log w = 0.
-template <bool CORR>
+template <bool CORR, bool YG>
 __global__ void __launch_bounds__(kMaxThreads) vmc_kernel(KArgs A)
 {
     extern __shared__ double lds[];
@@ -1551,12 +1571,12 @@ __global__ void __launch_bounds__(kMaxThreads) vmc_kernel(KArgs A)
     }
     double EL, LAP = 0.0, V;
     double *dphi = A.state_out + (size_t)slot * A.state_len + A.dphi_at;
-    const int rc = walker_setup<CORR>(A, lds, dphi, sflag, EL, LAP, V);
+    const int rc = walker_setup<CORR, YG>(A, lds, dphi, sflag, EL, LAP, V);
     if (rc) {
         if (tid == 0) report(A.err, rc, slot);
         return;
     }
-    const double *Jo = lds + L.Jo, *Y = lds + L.Y;
+    const double *Jo = lds + L.Jo, *Y = y_base<YG>(A, lds);
     int acc = 0;
     for (int it = 0; it < A.vmc_steps; ++it) {
         double u[4];
@@ -1581,7 +1601,7 @@ __global__ void __launch_bounds__(kMaxThreads) vmc_kernel(KArgs A)
             return;
         }
         if (u[3] < rho * rho) {
-            accept_move<CORR>(A, lds, dphi, i, rold, rnew);
+            accept_move<CORR, YG>(A, lds, dphi, i, rold, rnew);
             __syncthreads();
             V = uni(V + lds[L.sc + SC_DV]);
             ++acc;
@@ -1963,7 +1983,12 @@ struct lrdmc_ctx {
     size_t lds_bytes = 0;
     Layout L{};
     const void *fixed_fn[2] = {nullptr, nullptr};  // kernels built for this system's sizes, if any
-    bool force_generic = false;
+    // LDS layouts with Y in LDS and with Y in the HBM state blob (same blob
+    // format); the second is taken automatically when the first would leave
+    // fewer than four walkers per CU
+    Layout L_lds{}, L_yg{};
+    bool yg_auto = false;
+    int kmode = 0;   // 0 automatic, 1 general kernel, 2 general kernel with Y in HBM
     // learned Jastrow correction
     bool corr = false;
     int f_G = 0;
@@ -1996,6 +2021,41 @@ int fail(lrdmc_ctx *ctx, int code, const std::string &msg)
             return fail((ctx), e_ == hipErrorOutOfMemory ? LRDMC_ENOMEM : LRDMC_EDEVICE,            \
                         std::string(#expr) + ": " + hipGetErrorString(e_));                         \
     } while (0)
+
+void apply_kernel_mode(lrdmc_ctx *c)
+{
+    c->L = (c->kmode == 2 || c->yg_auto) ? c->L_yg : c->L_lds;
+    c->lds_bytes = sizeof(double) * (size_t)c->L.total;
+}
+
+bool use_fixed(const lrdmc_ctx *c) { return c->kmode == 0 && !c->L.yg && c->fixed_fn[c->corr]; }
+
+const void *project_fn(const lrdmc_ctx *c)
+{
+    if (use_fixed(c)) return c->fixed_fn[c->corr];
+    const void *f[4] = {(const void *)project_kernel<false, false>, (const void *)project_kernel<false, true>,
+                        (const void *)project_kernel<true, false>, (const void *)project_kernel<true, true>};
+    return f[2 * (int)c->corr + c->L.yg];
+}
+
+const void *jastrow_grad_fn(const lrdmc_ctx *c)
+{
+    const void *f[4] = {(const void *)jastrow_grad_kernel<false, false>, (const void *)jastrow_grad_kernel<false, true>,
+                        (const void *)jastrow_grad_kernel<true, false>, (const void *)jastrow_grad_kernel<true, true>};
+    return f[2 * (int)c->corr + c->L.yg];
+}
+
+const void *vmc_fn(const lrdmc_ctx *c)
+{
+    const void *f[4] = {(const void *)vmc_kernel<false, false>, (const void *)vmc_kernel<false, true>,
+                        (const void *)vmc_kernel<true, false>, (const void *)vmc_kernel<true, true>};
+    return f[2 * (int)c->corr + c->L.yg];
+}
+
+const void *table_grad_fn(const lrdmc_ctx *c)
+{
+    return c->L.yg ? (const void *)jastrow_table_grad_kernel<true> : (const void *)jastrow_table_grad_kernel<false>;
+}
 
 KArgs base_args(const lrdmc_ctx *c)
 {
@@ -2111,9 +2171,7 @@ int launch_project(lrdmc_ctx *c, hipStream_t st, const double *pos_in, const int
     A.k_out = k;
     A.diag_out = diag;
     const int ev = eval ? -1 : timing_begin(c, st, 0);
-    const void *fn = (c->fixed_fn[c->corr] && !c->force_generic)
-                         ? c->fixed_fn[c->corr]
-                         : (c->corr ? (const void *)project_kernel<true> : (const void *)project_kernel<false>);
+    const void *fn = project_fn(c);
     void *args[] = {&A};
     HIP_TRY(c, hipLaunchKernel(fn, dim3(c->W), dim3(c->nt), args, c->lds_bytes, st));
     timing_end(c, st, ev);
@@ -2351,19 +2409,23 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
         }
     c->v_nn = vnn;
     c->nt = threads_for(c->M);
-    c->L = make_layout(N, ns, K, c->Kp, c->M, sys->n_nuc, c->nt, prm->refresh > 1 ? 0 : 38 * 1024);
+    const size_t target = prm->refresh > 1 ? 0 : 38 * 1024;
+    c->L_lds = make_layout(N, ns, K, c->Kp, c->M, sys->n_nuc, c->nt, target, false);
+    c->L_yg = make_layout(N, ns, K, c->Kp, c->M, sys->n_nuc, c->nt, target, true);
+    c->yg_auto = sizeof(double) * (size_t)c->L_lds.total > 40 * 1024;
+    apply_kernel_mode(c);
     // a kernel built for these sizes serves the context if its layout is this one
     for (const FixedKernel &F : kFixedKernels) {
         if (F.n_up != sys->n_up || F.n_dn != sys->n_dn || F.K != K || F.n_nuc != sys->n_nuc || c->M != 12 * N)
             continue;
         const Layout Lf = make_layout(N, ns, K, c->Kp, c->M, sys->n_nuc, c->nt, 0);
-        if (std::memcmp(&Lf, &c->L, sizeof(Layout)) == 0) {
+        if (!c->yg_auto && std::memcmp(&Lf, &c->L_lds, sizeof(Layout)) == 0) {
             c->fixed_fn[0] = F.fn[0];
             c->fixed_fn[1] = F.fn[1];
         }
     }
-    c->lds_bytes = sizeof(double) * (size_t)c->L.total;
-    c->dphi_at = (c->L.Jo + N - c->L.Y) + 2;
+    // state blob: Y [N][Kp], the LDS part [Ainv, Jo + N), E_L, V, derivative rows
+    c->dphi_at = N * c->Kp + (c->L_lds.Jo + N - c->L_lds.Ainv) + 2;
     c->state_len = c->dphi_at + N * c->L.dld;
 
     auto cleanup = [&](int code, const std::string &m) {
@@ -2376,14 +2438,24 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
         return cleanup(LRDMC_EDEVICE, "lrdmc_create: no HIP device");
     if (c->lds_bytes > (size_t)prop.sharedMemPerBlock)
         return cleanup(LRDMC_EINVAL, "lrdmc_create: walker state does not fit in LDS");
-    if (c->lds_bytes > 65536) {
-        for (const void *fn : {(const void *)project_kernel<false>, (const void *)project_kernel<true>, c->fixed_fn[0],
-                               c->fixed_fn[1], (const void *)jastrow_grad_kernel<false>,
-                               (const void *)jastrow_grad_kernel<true>, (const void *)jastrow_table_grad_kernel,
-                               (const void *)vmc_kernel<false>, (const void *)vmc_kernel<true>})
-            if (fn && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_bytes) !=
-                          hipSuccess)
-                return cleanup(LRDMC_EDEVICE, "lrdmc_create: cannot raise the LDS limit");
+    {
+        // the LDS limit of every kernel (the current layout is the larger one
+        // that can run: the HBM-Y layout is never larger)
+        const size_t lim = c->lds_bytes;
+        if (lim > 65536) {
+            for (const void *fn :
+                 {(const void *)project_kernel<false, false>, (const void *)project_kernel<false, true>,
+                  (const void *)project_kernel<true, false>, (const void *)project_kernel<true, true>, c->fixed_fn[0],
+                  c->fixed_fn[1], (const void *)jastrow_grad_kernel<false, false>,
+                  (const void *)jastrow_grad_kernel<false, true>, (const void *)jastrow_grad_kernel<true, false>,
+                  (const void *)jastrow_grad_kernel<true, true>, (const void *)jastrow_table_grad_kernel<false>,
+                  (const void *)jastrow_table_grad_kernel<true>, (const void *)vmc_kernel<false, false>,
+                  (const void *)vmc_kernel<false, true>, (const void *)vmc_kernel<true, false>,
+                  (const void *)vmc_kernel<true, true>})
+                if (fn && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) !=
+                              hipSuccess)
+                    return cleanup(LRDMC_EDEVICE, "lrdmc_create: cannot raise the LDS limit");
+        }
     }
 
     const size_t W = n_walkers, s3 = 3 * (size_t)N;
@@ -2519,11 +2591,10 @@ int lrdmc_jastrow_grad(lrdmc_ctx *c, const double *pos, double *out, void *strea
     A.state_len = c->state_len;
     A.dphi_at = c->dphi_at;
     A.state_out = c->d_state[c->cur ^ 1];   // derivative rows as scratch, as in lrdmc_eval_moves
-    if (c->corr)
-        hipLaunchKernelGGL(jastrow_grad_kernel<true>, dim3(c->W), dim3(c->nt), c->lds_bytes, st, A, out);
-    else
-        hipLaunchKernelGGL(jastrow_grad_kernel<false>, dim3(c->W), dim3(c->nt), c->lds_bytes, st, A, out);
-    HIP_TRY(c, hipGetLastError());
+    {
+        void *args[] = {&A, &out};
+        HIP_TRY(c, hipLaunchKernel(jastrow_grad_fn(c), dim3(c->W), dim3(c->nt), args, c->lds_bytes, st));
+    }
     return check_kernel_error(c, st);
 }
 
@@ -2585,8 +2656,10 @@ int lrdmc_jastrow_table_grad(lrdmc_ctx *c, const double *pos, const double *c_j,
     A.state_out = c->d_state[c->cur ^ 1];
     const size_t n = 2 * (size_t)c->f_G * 3;
     hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, gtab, n, 0.0);
-    hipLaunchKernelGGL(jastrow_table_grad_kernel, dim3(c->W), dim3(c->nt), c->lds_bytes, st, A, c_j, c_e, gtab);
-    HIP_TRY(c, hipGetLastError());
+    {
+        void *args[] = {&A, &c_j, &c_e, &gtab};
+        HIP_TRY(c, hipLaunchKernel(table_grad_fn(c), dim3(c->W), dim3(c->nt), args, c->lds_bytes, st));
+    }
     return check_kernel_error(c, st);
 }
 
@@ -2697,11 +2770,10 @@ int lrdmc_vmc(lrdmc_ctx *c, int32_t n_steps, double step, void *stream)
     A.nmov = c->d_nmov;
     A.vmc_steps = n_steps;
     A.vmc_step = step;
-    if (c->corr)
-        hipLaunchKernelGGL(vmc_kernel<true>, dim3(c->W), dim3(c->nt), c->lds_bytes, st, A);
-    else
-        hipLaunchKernelGGL(vmc_kernel<false>, dim3(c->W), dim3(c->nt), c->lds_bytes, st, A);
-    HIP_TRY(c, hipGetLastError());
+    {
+        void *args[] = {&A};
+        HIP_TRY(c, hipLaunchKernel(vmc_fn(c), dim3(c->W), dim3(c->nt), args, c->lds_bytes, st));
+    }
     c->cur ^= 1;
     c->pending = false;
     c->projected = false;
@@ -2713,13 +2785,15 @@ int lrdmc_vmc(lrdmc_ctx *c, int32_t n_steps, double step, void *stream)
 int lrdmc_use_generic(lrdmc_ctx *c, int32_t enable)
 {
     if (!c) return fail(nullptr, LRDMC_EINVAL, "lrdmc_use_generic: NULL context");
-    c->force_generic = enable != 0;
+    if (enable < 0 || enable > 2) return fail(c, LRDMC_EINVAL, "lrdmc_use_generic: mode must be 0, 1 or 2");
+    c->kmode = enable;
+    apply_kernel_mode(c);   // the state blob format is the same for every mode
     return LRDMC_OK;
 }
 
 int32_t lrdmc_is_specialized(const lrdmc_ctx *c)
 {
-    return (c && c->fixed_fn[c->corr] && !c->force_generic) ? 1 : 0;
+    return (c && use_fixed(c)) ? 1 : 0;
 }
 
 int lrdmc_set_timing(lrdmc_ctx *c, int32_t enable)

@@ -275,8 +275,10 @@ def lrdmc_net_tabulate_backward(params, hidden: int, n_nodes: int, r_cut: float,
                                               _dptr(work, torch.float64), _stream(stream)))
 
 
-def lrdmc_use_generic(ctx, enable: bool = True):
-    _check(load().lrdmc_use_generic(ctx, 1 if enable else 0), ctx)
+def lrdmc_use_generic(ctx, enable=True):
+    """0/False automatic, 1/True the general kernel, 2 the general kernel with
+    the orbital-projected inverse in device memory."""
+    _check(load().lrdmc_use_generic(ctx, int(enable)), ctx)
 
 
 def lrdmc_is_specialized(ctx) -> bool:

@@ -86,14 +86,28 @@ def test_call_order_errors():
     gpu.close()
 
 
-def test_state_too_large_for_lds_is_refused():
-    """64 electrons with 512 basis functions cannot keep a walker in LDS."""
-    from paper_1909_01589_amd.lrdmc import LRDMCError
+def test_largest_system_runs_with_y_in_device_memory():
+    """64 electrons (32 per spin) with 512 basis functions, the largest sizes
+    lrdmc_create accepts: the orbital-projected inverse (256 KB per walker)
+    cannot sit in LDS, so the general kernel keeps it in the walker's
+    device-memory state; the move table and E_L still match the oracle."""
+    import oracle
+    from oracle import spacing
+    from paper_1909_01589_amd.lrdmc import lrdmc_is_specialized
     counts = (112, 100, 20)   # 112 + 300 + 100 = 512 functions
     s = inputs.atom(64, counts, 0.05, 2.0, seed=0)
-    with pytest.raises(LRDMCError) as e:
-        _LRDMC()(s, 0.01, 0.02, 0.05, 1e-4, 2)
-    assert e.value.code == -1
+    rc, ap, _ = spacing.spacing(s.z_max, 0.01)
+    gpu = _LRDMC()(s, 0.01, ap, rc, 1e-4, 2)
+    assert not lrdmc_is_specialized(gpu.ctx)
+    orc = oracle.Oracle(s, 0.01, ap, rc, tau=1e-4, seed=0, rotate=1)
+    pos = inputs.initial_walkers(s, 2, 1)
+    rho, k, diag = (x.cpu().numpy() for x in gpu.eval_moves(pos))
+    for w in range(2):
+        print(f"largest system walker={w}", flush=True)
+        r_o, k_o, d_o = orc.eval_moves(pos[w], orc.move_rotation(w, 0, 0))
+        assert np.all(np.abs(rho[w] - r_o) <= 1e-9 * (np.abs(r_o) + np.max(np.abs(r_o))))
+        assert abs(diag[w, 0] - d_o["e_l"]) <= 1e-9 * (1 + abs(d_o["e_l"]) + abs(d_o["lap_exact"]))
+    gpu.close()
 
 
 def test_runs_are_deterministic():

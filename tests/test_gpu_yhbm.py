@@ -1,0 +1,121 @@
+"""The general kernels with the orbital-projected inverse Y in the walker's
+device-memory state (chosen automatically for large systems, forced here on
+small ones with lrdmc_use_generic(ctx, 2)) against the oracle: move tables,
+whole runs resuming the stored state, a switch between the two placements
+inside a run, the Metropolis sampler, the gradient kernels and the learned
+correction.  Bars as in the main parity tests."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from oracle import spacing  # noqa: E402
+from paper_1909_01589_amd import inputs  # noqa: E402
+
+
+def _system(name):
+    return {"be": (inputs.be_like(0), 0.2, 0.0161), "ar": (inputs.ar_like(0), 0.1, 0.00318),
+            "tiny": (inputs.tiny_mixed(seed=1, n_up=3, n_dn=2), 0.06, 0.02)}[name]
+
+
+def _pair(name, W, seed=3, refresh=1, tab=None):
+    from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_use_generic
+    s, a, tau = _system(name)
+    rc, ap, _ = spacing.spacing(s.z_max, a)
+    gpu = LRDMC(s, a, ap, rc, tau, W, seed=seed, rotate=1, refresh=refresh)
+    lrdmc_use_generic(gpu.ctx, 2)
+    if tab is not None:
+        gpu.set_jastrow_table(tab, 4.0)
+    orc = oracle.Oracle(s, a, ap, rc, tau=tau, seed=seed, rotate=1, ftab=tab, ftab_rcut=4.0)
+    return s, gpu, orc
+
+
+@pytest.mark.parametrize("name,W", [("be", 8), ("tiny", 6), ("ar", 4)])
+def test_eval_moves_y_in_hbm(name, W):
+    s, gpu, orc = _pair(name, W)
+    pos = inputs.initial_walkers(s, W, 7)
+    rho, k, diag = (x.cpu().numpy() for x in gpu.eval_moves(pos))
+    for w in range(W):
+        r_o, k_o, d_o = orc.eval_moves(pos[w], orc.move_rotation(w, 0, 0))
+        assert np.all(np.abs(rho[w] - r_o) <= 1e-9 * (np.abs(r_o) + np.max(np.abs(r_o))))
+        assert abs(diag[w, 0] - d_o["e_l"]) <= 1e-9 * (1 + abs(d_o["e_l"]) + abs(d_o["lap_exact"]))
+    gpu.close()
+
+
+@pytest.mark.parametrize("name,W,n_gen,refresh,table", [("be", 64, 5, 4, False), ("tiny", 32, 4, 3, True),
+                                                        ("ar", 16, 3, 2, False), ("ar", 16, 3, 1, True)])
+def test_run_y_in_hbm(name, W, n_gen, refresh, table):
+    tab = inputs.jastrow_table(seed=2, n_nodes=65, r_cut=4.0, scale=0.3) if table else None
+    s, gpu, orc = _pair(name, W, seed=9, refresh=refresh, tab=tab)
+    pos = inputs.initial_walkers(s, W, 2)
+    gpu.set_walkers(pos, 0)
+    out = gpu.run(n_gen, want_idx=True)
+    ref = orc.run(pos, n_gen, gen0=0)
+    print(f"y-hbm run case={name} refresh={refresh} table={table}", flush=True)
+    assert np.array_equal(out["n_moves"].cpu().numpy(), ref["n_moves"])
+    assert np.array_equal(out["idx"].cpu().numpy(), ref["idx"])
+    assert np.all(np.abs(out["ebar"].cpu().numpy() - ref["ebar"]) <= 1e-9 * (1 + np.abs(ref["ebar"])))
+    assert np.allclose(gpu.get_walkers()["pos"].cpu().numpy(), ref["pos"], rtol=0, atol=1e-10)
+    gpu.close()
+
+
+def test_switching_placement_inside_a_run():
+    """Two generations with Y in LDS (fixed-size kernel), two with Y in
+    device memory resuming the stored state, two back in LDS: the same
+    records as the oracle's uninterrupted run."""
+    from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_is_specialized, lrdmc_use_generic
+    s, a, tau = _system("be")
+    rc, ap, _ = spacing.spacing(s.z_max, a)
+    W = 64
+    gpu = LRDMC(s, a, ap, rc, tau, W, seed=5, rotate=1, refresh=8)
+    orc = oracle.Oracle(s, a, ap, rc, tau=tau, seed=5, rotate=1)
+    pos = inputs.initial_walkers(s, W, 3)
+    gpu.set_walkers(pos, 0)
+    idx, eb = [], []
+    for mode in (0, 2, 0):
+        lrdmc_use_generic(gpu.ctx, mode)
+        assert lrdmc_is_specialized(gpu.ctx) == (mode == 0)
+        out = gpu.run(2, want_idx=True)
+        idx.append(out["idx"].cpu().numpy())
+        eb.append(out["ebar"].cpu().numpy())
+    ref = orc.run(pos, 6, gen0=0)
+    assert np.array_equal(np.concatenate(idx), ref["idx"])
+    assert np.all(np.abs(np.concatenate(eb) - ref["ebar"]) <= 1e-9 * (1 + np.abs(ref["ebar"])))
+    gpu.close()
+
+
+def test_vmc_and_gradients_y_in_hbm():
+    tab = inputs.jastrow_table(seed=3, n_nodes=33, r_cut=4.0, scale=0.3)
+    s, gpu, orc = _pair("tiny", 6, seed=4, tab=tab)
+    pos = inputs.initial_walkers(s, 6, 5)
+    gpu.set_walkers(pos, 0)
+    gpu.vmc(40, 0.3)
+    out = {k: v.cpu().numpy() for k, v in gpu.get_walkers().items()}
+    for w in range(6):
+        p, acc, el = orc.vmc(pos[w], w, 0, 40, 0.3)
+        assert out["n_moves"][w] == acc
+        assert np.allclose(out["pos"][w], p, rtol=0, atol=1e-10)
+    g = gpu.jastrow_grad(pos).cpu().numpy()
+    for w in range(6):
+        e_o = orc.local_energy(pos[w])[0]
+        assert abs(g[w, 0] - e_o) <= 1e-9 * (1 + abs(e_o))
+        assert abs(g[w, 1] - orc.jastrow(pos[w])) <= 1e-11 * (1 + abs(g[w, 1]))
+    gt = gpu.jastrow_table_grad(pos, np.ones(6), np.ones(6)).cpu().numpy()
+    from paper_1909_01589_amd.lrdmc import lrdmc_use_generic
+    lrdmc_use_generic(gpu.ctx, 1)
+    gt_lds = gpu.jastrow_table_grad(pos, np.ones(6), np.ones(6)).cpu().numpy()
+    assert np.allclose(gt, gt_lds, rtol=1e-12, atol=1e-12 * np.abs(gt).max())
+    gpu.close()
+
+
+def test_mode_errors():
+    from paper_1909_01589_amd.lrdmc import LRDMC, LRDMCError, lrdmc_use_generic
+    s, a, tau = _system("be")
+    gpu = LRDMC(s, a, 0.3, 0.4, tau, 4, seed=1)
+    for bad in (-1, 3):
+        with pytest.raises(LRDMCError, match="EINVAL"):
+            lrdmc_use_generic(gpu.ctx, bad)
+    gpu.close()
