@@ -613,8 +613,13 @@ double orc_p_switch(const orc_system *s, const orc_params *p, const double x[3])
  * New position r' = r_i + sign h e_axis; p is taken at the midpoint
  * r_i + sign (h/2) e_axis; coefficient k = p/a^2 or (1-p)/a'^2.
  * Single grid: m = 6 i + dir, spacing a, k = 1/a^2 (p = 1 everywhere). */
-void orc_move(const orc_system *s, const orc_params *p, const double *pos, const double Rm[9],
-              int m, double rp[3], double *k)
+/* Small-grid moves whose switch p at the midpoint is below 2^-52 are dropped
+ * from the heat bath (T = 0; their weight p/a^2 is below the rounding of the
+ * large-grid weights of the same electron); rho and k are still reported. */
+#define ORC_P_DROP 0x1p-52
+
+static void move_geom(const orc_system *s, const orc_params *p, const double *pos, const double Rm[9], int m,
+                      double rp[3], double *k, int *dropped)
 {
     const int mpe = moves_per_electron(p);
     int i = m / mpe, g = mpe == 12 ? (m / 6) % 2 : 0, dir = m % 6, ax = dir / 2;
@@ -626,12 +631,21 @@ void orc_move(const orc_system *s, const orc_params *p, const double *pos, const
         rp[c] = pos[3 * i + c] + sgn * h * e[c];
         mid[c] = pos[3 * i + c] + sgn * (0.5 * h) * e[c];
     }
+    *dropped = 0;
     if (mpe == 6) {
         *k = 1.0 / (p->a * p->a);
         return;
     }
     double pv = orc_p_switch(s, p, mid);
     *k = (g == 0) ? pv / (p->a * p->a) : (1.0 - pv) / (p->a_prime * p->a_prime);
+    *dropped = (g == 0) && pv < ORC_P_DROP;
+}
+
+void orc_move(const orc_system *s, const orc_params *p, const double *pos, const double Rm[9],
+              int m, double rp[3], double *k)
+{
+    int dropped;
+    move_geom(s, p, pos, Rm, m, rp, k, &dropped);
 }
 
 /* Psi(x')/Psi(x) for x' = x with electron i at rp: the moved spin's
@@ -662,9 +676,10 @@ static int ratio_full(const orc_system *s, const double *pos, int i, const doubl
  *   [6] Delta = sum T         [7] V
  *   [8] sum k                 [9] unused
  * V^a = V + (L^a - lap Psi/Psi)/2; V_sf = -1/2 sum_{rho<0} k rho;
- * T = k max(rho,0)/2; e_L = sum k/2 + V^a + V_sf - Delta. */
-int orc_eval_moves(const orc_system *s, const orc_params *p, const double *pos, const double Rm[9],
-                   double *rho, double *kout, double *diag)
+ * T = k max(rho,0)/2 (0 for dropped moves); e_L = sum k/2 + V^a + V_sf -
+ * Delta.  T (optional) receives the heat-bath weights. */
+static int eval_table(const orc_system *s, const orc_params *p, const double *pos, const double Rm[9],
+                      double *rho, double *kout, double *T, double *diag)
 {
     int N = s->n_up + s->n_dn, K = orc_nbasis(s), M = moves_per_electron(p) * N;
     int nmax = s->n_up > s->n_dn ? s->n_up : s->n_dn;
@@ -690,8 +705,8 @@ int orc_eval_moves(const orc_system *s, const orc_params *p, const double *pos, 
     double sumk = 0, La = 0, Vsf = 0, Delta = 0;
     for (int m = 0; m < M; ++m) {
         double rp[3], k;
-        int i = m / moves_per_electron(p), sg = spin_of(s, i);
-        orc_move(s, p, pos, Rm, m, rp, &k);
+        int i = m / moves_per_electron(p), sg = spin_of(s, i), dropped;
+        move_geom(s, p, pos, Rm, m, rp, &k, &dropped);
         double r;
         ratio_full(s, pos, i, rp, A[sg], ld[sg], sgn[sg], J, pos_tmp, Atmp, w, &r);
         rho[m] = r;
@@ -699,7 +714,9 @@ int orc_eval_moves(const orc_system *s, const orc_params *p, const double *pos, 
         sumk += k;
         La += k * (r - 1.0);
         if (r < 0) Vsf += -0.5 * k * r;
-        Delta += 0.5 * k * (r > 0 ? r : 0.0);
+        double t = dropped ? 0.0 : 0.5 * k * (r > 0 ? r : 0.0);
+        if (T) T[m] = t;
+        Delta += t;
     }
     free(w);
     double EL, lap, V;
@@ -718,6 +735,12 @@ int orc_eval_moves(const orc_system *s, const orc_params *p, const double *pos, 
         diag[9] = 0.0;
     }
     return rc;
+}
+
+int orc_eval_moves(const orc_system *s, const orc_params *p, const double *pos, const double Rm[9],
+                   double *rho, double *kout, double *diag)
+{
+    return eval_table(s, p, pos, Rm, rho, kout, NULL, diag);
 }
 
 /* Heat-bath choice: first m with C_m > u2 * Delta, C the sequential
@@ -762,13 +785,10 @@ int orc_generation(const orc_system *s, const orc_params *p, uint64_t slot, uint
             orc_draw(p->seed, slot, gen, it, 1, u);
             orc_rotation(u, Rm);
         }
-        rc = orc_eval_moves(s, p, pos, Rm, rho, k, NULL);
+        rc = eval_table(s, p, pos, Rm, rho, k, T, NULL);
         if (rc) break;
         double D = 0.0;
-        for (int m = 0; m < M; ++m) {
-            T[m] = 0.5 * k[m] * (rho[m] > 0 ? rho[m] : 0.0);
-            D += T[m];
-        }
+        for (int m = 0; m < M; ++m) D += T[m];
         orc_draw(p->seed, slot, gen, it, 0, u);
         if (!(D > 0.0)) { lw -= tl * EL; break; }
         double td = -log(u[0]) / D;

@@ -857,6 +857,116 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Small-grid moves whose switch p at the midpoint is below 2^-52 are dropped
+// from the heat bath (T = 0); their weight p / a^2 is below the rounding of
+// the large-grid weights of the same electron.
+constexpr double kPDrop = 0x1p-52;
+
+// The heat-bath weights of the table with the dropped pairs skipped (large
+// systems with more pairs than threads, where most valence electrons have p
+// far below 2^-52, so that the kept pairs fit one round): the pairs
+// that keep a move are listed in LDS (wavefront ballots, at most two rounds
+// of NT pairs) and shared out over the threads, then every thread sums the
+// weights of its own contiguous chunk [c0, c1) in move order, so the search
+// sees exactly the sums of the full table.  The list lives in the prefix-sum
+// scratch, which is written only after the last barrier here.
+template <bool CORR, bool YG>
+__device__ __forceinline__ double move_table_compact(const KArgs &A, double *lds, const double *Rm, int c0,
+                                                     int c1, int *last)
+{
+    const Layout &L = A.L;
+    const double *pos = lds + L.pos, *Y = y_base<YG>(A, lds), *Jo = lds + L.Jo;
+    double *T = lds + L.T;
+    int *list = reinterpret_cast<int *>(lds + L.xs);
+    int *cnt = reinterpret_cast<int *>(lds + L.red);
+    const int tid = threadIdx.x, NT = A.nt, lane = tid & 63, wv = tid >> 6, nw = NT >> 6;
+    const int npairs = A.M / 2;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int pre[2] = {0, 0};
+    bool act[2] = {false, false};
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int q = tid + r * NT;
+        bool a = false;
+        if (q < npairs) {
+            const int m = 2 * q, i = m / A.mpe, g = A.mpe == 12 ? (m / 6) & 1 : 1;
+            a = true;
+            if (g == 0) {
+                const int ax = (m % 6) >> 1;
+                const double hh = 0.5 * A.a;
+                double ma[3], mb[3];
+                for (int c = 0; c < 3; ++c) {
+                    const double e = Rm[3 * c + ax], x = pos[3 * i + c];
+                    ma[c] = x + hh * e;
+                    mb[c] = x + (-hh) * e;
+                }
+                a = !(p_switch(A, ma) < kPDrop) || !(p_switch(A, mb) < kPDrop);
+            }
+            if (!a) {
+                T[m] = 0.0;
+                T[m + 1] = 0.0;
+            }
+        }
+        const unsigned long long mask = __ballot(a);
+        if (lane == 0) cnt[r * 4 + wv] = __popcll(mask);
+        pre[r] = __popcll(mask & below);
+        act[r] = a;
+    }
+    __syncthreads();
+    int base = 0, total = 0;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        int off = 0, rt = 0;
+        for (int w = 0; w < nw; ++w) {
+            const int n = cnt[r * 4 + w];
+            if (w < wv) off += n;
+            rt += n;
+        }
+        if (act[r]) list[base + off + pre[r]] = tid + r * NT;
+        base += rt;
+        total += rt;
+    }
+    __syncthreads();
+    for (int e = tid; e < total; e += NT) {
+        const int m = 2 * list[e];
+        const int i = m / A.mpe, g = A.mpe == 12 ? (m / 6) & 1 : 0, ax = (m % 6) >> 1;
+        const double h = grid_spacing(A, g);
+        const double ev[3] = {Rm[ax], Rm[3 + ax], Rm[6 + ax]};
+        double ra[3], rb[3], ma[3], mb[3];
+        for (int c = 0; c < 3; ++c) {
+            const double r = pos[3 * i + c];
+            ra[c] = r + h * ev[c];
+            rb[c] = r + (-h) * ev[c];
+            ma[c] = r + (0.5 * h) * ev[c];
+            mb[c] = r + (-0.5 * h) * ev[c];
+        }
+        double ka = A.inv_a2, kb = A.inv_a2;
+        bool da = false, db = false;
+        if (A.mpe == 12) {
+            const double pa = p_switch(A, ma), pb = p_switch(A, mb);
+            ka = g ? (1.0 - pa) * A.inv_ap2 : pa * A.inv_a2;
+            kb = g ? (1.0 - pb) * A.inv_ap2 : pb * A.inv_a2;
+            da = !g && pa < kPDrop;
+            db = !g && pb < kPDrop;
+        }
+        double rda, rdb, ja, jb;
+        basis_dot2(A, ra, rb, Y + i * A.Kp, rda, rdb);
+        jastrow_point2<CORR>(A, pos, i, ra, rb, ja, jb);
+        const double jo = Jo[i];
+        const double rhoa = rda * exp(ja - jo), rhob = rdb * exp(jb - jo);
+        T[m] = da ? 0.0 : 0.5 * ka * (rhoa > 0.0 ? rhoa : 0.0);
+        T[m + 1] = db ? 0.0 : 0.5 * kb * (rhob > 0.0 ? rhob : 0.0);
+    }
+    __syncthreads();
+    double part = 0.0;
+    for (int m = c0; m < c1; ++m) {
+        const double t = T[m];
+        part += t;
+        if (t > 0.0) *last = m;
+    }
+    return part;
+}
+
 // Heat-bath weights of the moves m in [c0, c1) (S1-S6), c0 and c1 even:
 // each step evaluates the +/- pair (m, m + 1) along one axis of one grid of
 // one electron.  Returns the sum of the weights; with diag, stores rho and k
@@ -865,6 +975,10 @@ template <bool CORR, bool YG>
 __device__ __forceinline__ double move_table(const KArgs &A, double *lds, const double *Rm, int c0, int c1,
                                              int *last, double *rho_g, double *k_g, double acc[3], bool diag)
 {
+    if constexpr (YG) {
+        // compaction pays when it saves a second round of pairs per thread
+        if (!diag && A.M / 2 > A.nt) return move_table_compact<CORR, YG>(A, lds, Rm, c0, c1, last);
+    }
     const Layout &L = A.L;
     const double *pos = lds + L.pos, *Y = y_base<YG>(A, lds), *Jo = lds + L.Jo;
     double *T = lds + L.T;
@@ -882,18 +996,21 @@ __device__ __forceinline__ double move_table(const KArgs &A, double *lds, const 
             mb[c] = r + (-0.5 * h) * e[c];
         }
         double ka = A.inv_a2, kb = A.inv_a2;   // single grid: p = 1
+        bool da = false, db = false;
         if (A.mpe == 12) {
             const double pa = p_switch(A, ma), pb = p_switch(A, mb);
             ka = g ? (1.0 - pa) * A.inv_ap2 : pa * A.inv_a2;
             kb = g ? (1.0 - pb) * A.inv_ap2 : pb * A.inv_a2;
+            da = !g && pa < kPDrop;
+            db = !g && pb < kPDrop;
         }
         double rda, rdb, ja, jb;
         basis_dot2(A, ra, rb, Y + i * A.Kp, rda, rdb);
         jastrow_point2<CORR>(A, pos, i, ra, rb, ja, jb);
         const double jo = Jo[i];
         const double rhoa = rda * exp(ja - jo), rhob = rdb * exp(jb - jo);
-        const double ta = 0.5 * ka * (rhoa > 0.0 ? rhoa : 0.0);
-        const double tb = 0.5 * kb * (rhob > 0.0 ? rhob : 0.0);
+        const double ta = da ? 0.0 : 0.5 * ka * (rhoa > 0.0 ? rhoa : 0.0);
+        const double tb = db ? 0.0 : 0.5 * kb * (rhob > 0.0 ? rhob : 0.0);
         T[m] = ta;
         T[m + 1] = tb;
         part += ta;

@@ -119,3 +119,32 @@ def test_mode_errors():
         with pytest.raises(LRDMCError, match="EINVAL"):
             lrdmc_use_generic(gpu.ctx, bad)
     gpu.close()
+
+
+def test_compacted_table_run():
+    """44 electrons (264 move pairs > 256 threads): the table runs compacted,
+    with the small-grid moves of valence electrons dropped (p < 2^-52); three
+    generations against the oracle, indices bit-exact."""
+    from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_use_generic
+    s = inputs.atom(44, (12, 10, 2), 0.08, 2.0, seed=0)   # Slater matrices well conditioned
+    a = 1.0 / (3.5 * 44)
+    rc, ap, _ = spacing.spacing(44.0, a)
+    W, tau = 8, 4e-5
+    gpu = LRDMC(s, a, ap, rc, tau, W, seed=6, rotate=1, refresh=2)
+    lrdmc_use_generic(gpu.ctx, 2)
+    orc = oracle.Oracle(s, a, ap, rc, tau=tau, seed=6, rotate=1)
+    pos = inputs.initial_walkers(s, W, 4)
+    # the rule drops moves here
+    _, k, d = orc.eval_moves(pos[0], orc.move_rotation(0, 0, 0))
+    g = (np.arange(orc.M) // 6) % 2
+    assert np.sum((g == 0) & (k * a * a < 2.0 ** -52)) > 50
+    gpu.set_walkers(pos, 0)
+    out = gpu.run(3, want_idx=True)
+    ref = orc.run(pos, 3, gen0=0)
+    print(f"compacted run moves={ref['n_moves'].sum()}", flush=True)
+    assert ref["n_moves"].sum() > 3 * W
+    assert np.array_equal(out["n_moves"].cpu().numpy(), ref["n_moves"])
+    assert np.array_equal(out["idx"].cpu().numpy(), ref["idx"])
+    assert np.all(np.abs(out["ebar"].cpu().numpy() - ref["ebar"]) <= 1e-9 * (1 + np.abs(ref["ebar"])))
+    assert np.allclose(gpu.get_walkers()["pos"].cpu().numpy(), ref["pos"], rtol=0, atol=1e-10)
+    gpu.close()
