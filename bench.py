@@ -362,6 +362,31 @@ def zscan(Zs=(10, 18, 36, 54), walkers=8192, gens=20, warmup=10, moves_per_elect
                       "cost": "GPU seconds per walker per unit projection time (1/Ha), at a = 1/(3.5 Z)"}}
 
 
+SWEEP = (("be", 300, 30), ("ar_a0.2", 300, 30), ("ar_a0.1", 300, 30), ("zsweep10", 100, 10), ("zsweep18", 100, 10),
+         ("zsweep36", 30, 5), ("zsweep54", 20, 5), ("molecule", 20, 5))
+
+
+def sweep():
+    """Throughput of every configured workload (generations, warm-up) as in
+    the benchmark line: electron-moves/s, ms per generation, the kernel's
+    HIP-event time and its fraction of the FP64 peak by the algorithmic count
+    (which counts every move of the table, also those the large-system kernels
+    skip under the small-grid drop rule)."""
+    out = []
+    for name, steps, warm in SWEEP:
+        cfg, r = run_workload(name, steps, warm, False, 0.0)
+        s = cfg.system
+        row = dict(workload=name, electrons=s.n_elec, basis=s.n_basis, nuclei=int(s.n_nuc), walkers=r["walkers"],
+                   a=r["a"], a_prime=r["a_prime"], generations=steps, value=r["value"],
+                   ms_per_step=r["ms_per_step"], moves_per_walker_gen=r["moves_per_walker_gen"],
+                   kernel_ms=r["roofline"]["avg_launch_ms"], achieved_tflops=r["roofline"]["achieved"],
+                   frac=r["roofline"]["frac"])
+        print(f"[sweep] {name}: {r['value'] / 1e6:.2f} M electron-moves/s, frac {row['frac']:.3f}",
+              file=sys.stderr, flush=True)
+        out.append(row)
+    return {"sweep": out}
+
+
 def copy_probe():
     """A plain device copy of 512 MiB: the reference for scaling the HBM byte
     counters (FETCH_SIZE, WRITE_SIZE) of a profiled run."""
@@ -471,6 +496,8 @@ def main():
                     help="only time the Jastrow-parameter gradient kernel and exit")
     ap.add_argument("--neural", choices=["ar", "he"], default=None,
                     help="only run the learned-Jastrow comparison (VMC, training, LRDMC scan) and exit")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only time every configured workload (Be-like, Ar-like, Z-sweep, molecule) and exit")
     ap.add_argument("--zscan", action="store_true",
                     help="only run the single/double-grid cost scan over Z = 10, 18, 36, 54 and exit")
     ap.add_argument("--ascan", action="store_true",
@@ -495,6 +522,9 @@ def main():
         return
     if args.ascan:
         print(json.dumps(ascan()), flush=True)
+        return
+    if args.sweep:
+        print(json.dumps(sweep()), flush=True)
         return
     if args.zscan:
         print(json.dumps(zscan()), flush=True)
