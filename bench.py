@@ -13,7 +13,8 @@ Jastrow b = 1, small spacing a = 0.1 bohr with r_c(a, Z) and a' from the
 paper's rule, 4096 walkers.  The a = 0.2 bohr spacing of the same workload is
 timed as a second line inside the same JSON object.
 
-Prints one JSON line.  Multi-GPU runs are not part of this build.
+Prints one JSON line.  Runs on one GPU only (the walker population is not
+sharded over several GPUs).
 """
 from __future__ import annotations
 
@@ -508,8 +509,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on exactly one GPU; --gpus must be 1 "
-              "(multi-GPU sharding of the walker population is described in DESIGN.md, not built)",
+        print("bench.py: runs on exactly one GPU; --gpus must be 1 "
+              "(the walker population is not sharded over several GPUs)",
               file=sys.stderr)
         sys.exit(2)
 
