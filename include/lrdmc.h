@@ -262,8 +262,10 @@ int lrdmc_set_jastrow_table(lrdmc_ctx *ctx, const double *tab, int32_t n_nodes, 
  * c_e[w] E_L,w) over the W walker configurations pos (device [W][N][3]);
  * c_j, c_e are device [W] (either may be NULL for zero).  J and E_L are the
  * values lrdmc_jastrow_grad returns; the backward pass of a loss on them.
- * Accumulated with floating-point atomics: the summation order varies from
- * call to call (differences at rounding level).  Synchronizes the stream.
+ * Accumulated with hardware floating-point atomics: the summation order
+ * varies from call to call (differences at rounding level), and gtab must be
+ * ordinary device memory (hipMalloc or a device tensor), not host-mapped or
+ * fine-grained memory.  Synchronizes the stream.
  * Errors: LRDMC_EINVAL (NULL, no table set), LRDMC_ESINGULAR,
  * LRDMC_ENONFINITE, LRDMC_EDEVICE. */
 int lrdmc_jastrow_table_grad(lrdmc_ctx *ctx, const double *pos, const double *c_j, const double *c_e,

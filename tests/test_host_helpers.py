@@ -1,0 +1,46 @@
+"""Host-side helpers (CPU): the E(a) fits and the sampled N_core of the
+benchmark modes, and the packing of the network parameters."""
+import numpy as np
+import pytest
+
+import bench
+
+
+def test_fit_e0_recovers_a_polynomial():
+    a = np.array([0.06, 0.045, 0.035, 0.025, 0.0175])
+    E = -520.4 + 300.0 * a ** 2 - 2.0e4 * a ** 4
+    sig = np.full(a.size, 0.01)
+    E0, s0, chi2 = bench._fit_e0(a, E, sig)
+    assert E0 == pytest.approx(-520.4, abs=1e-9)
+    assert chi2 == pytest.approx(0.0, abs=1e-12)
+    E0l, s0l, _ = bench._fit_e0_linear(a[2:], -1.0 + 5.0 * a[2:] ** 2, sig[2:])
+    assert E0l == pytest.approx(-1.0, abs=1e-12)
+    # the error of E0 grows with the error bars
+    assert bench._fit_e0(a, E, 2 * sig)[1] == pytest.approx(2 * s0, rel=1e-12)
+
+
+def test_switch_sum_counts_core_electrons():
+    R = np.zeros(3)
+    pos = np.zeros((4, 3, 3))
+    pos[:, 1, 0] = 10.0          # far electron: p = 0
+    pos[:, 2, 0] = 0.1           # near electron: p = exp(-0.01 / (2 r_c^2))
+    rc = 0.2
+    got = bench._switch_sum(pos, R, rc, 0)
+    assert got == pytest.approx(1.0 + 0.0 + np.exp(-0.01 / (2 * rc * rc)), rel=1e-14)
+    got_pade = bench._switch_sum(pos, R, rc, 1)
+    assert got_pade == pytest.approx(1.0 + 1.0 / (1 + rc * rc * 100.0) + 1.0 / (1 + rc * rc * 0.01), rel=1e-14)
+
+
+def test_network_packing_round_trip():
+    from paper_1909_01589_amd import inputs, neural
+    w = inputs.neural_weights(seed=2, hidden=16)
+    flat = neural.pack(w)
+    assert flat.shape == (2, 16 * 16 + 4 * 16 + 1)
+    back = neural.unpack(flat, 16)
+    for kind in ("ee", "en"):
+        for k, v in w[kind].items():
+            assert np.array_equal(np.asarray(back[kind][k]), np.asarray(v))
+    with pytest.raises(ValueError):
+        bad = {k: dict(v) for k, v in w.items()}
+        bad["ee"]["W2"] = np.zeros((16, 15))
+        neural.pack(bad)
