@@ -174,12 +174,15 @@ def jastrow_grad_bench(name="ar_a0.1", reps=50):
                              "walker_gradients_per_s": cfg.walkers / dt}}
 
 
-def neural_bench(system="ar", walkers=16384, rounds=8, train_steps=60, lr=1e-3, gens=1200, seed=0):
+def neural_bench(system="ar", walkers=16384, rounds=8, train_steps=60, lr=1e-3, gens=1200, seed=0,
+                 train_walkers=131072):
     """Learned Jastrow correction against the Pade trial function alone.
     Metropolis samples of |Psi_Pade|^2 (lrdmc_vmc), rounds of variance
     minimisation of the 2 x 64 SiLU networks (tabulated on 257 nodes up to
-    r_cut = 6 bohr) each followed by a fresh sample (the parameters with the
-    lowest fresh-sample variance are kept), then LRDMC with both trial
+    r_cut = 6 bohr) on `train_walkers` configurations per round (8 rounds:
+    about 10^6 samples), each round followed by a fresh sample (the
+    parameters with the lowest fresh-sample variance are kept), then LRDMC
+    with `walkers` walkers and both trial
     functions at three spacings: energies with reblocked errors, move rates,
     the time to sigma(E) = 1 mHa extrapolated from each run
     (wall x (sigma / 1 mHa)^2), and E0 of the fit E0 + k a^2 (the lattice
@@ -205,17 +208,29 @@ def neural_bench(system="ar", walkers=16384, rounds=8, train_steps=60, lr=1e-3, 
     def note(msg):
         print(f"[neural {system} {time.perf_counter() - t0:6.1f}s] {msg}", file=sys.stderr, flush=True)
 
-    g = LRDMC(s, spacings[0], spacings[0], 1.0, 0.01, walkers, seed=seed + 3, rotate=1, refresh=8)
-    g.set_walkers(pos0, 0)
+    g = LRDMC(s, spacings[0], spacings[0], 1.0, 0.01, train_walkers, seed=seed + 3, rotate=1, refresh=8)
+    g.set_walkers(inputs.initial_walkers(s, train_walkers, seed + 1), 0)
     g.vmc(3000, step)
+
+    def spread(n_snap=4):
+        """E_L over n_snap Metropolis snapshots 300 steps apart: mean, mean of
+        the snapshot variances, and (1.4826 MAD)^2, a width the heavy tails of
+        E_L do not dominate."""
+        es = []
+        for _ in range(n_snap):
+            g.vmc(300, step)
+            es.append(g.get_walkers()["e_l"].cpu().numpy())
+        e = np.concatenate(es)
+        mad = 1.4826 * np.median(np.abs(e - np.median(e)))
+        return dict(E=float(e.mean()), var=float(np.mean([x.var() for x in es])), robust_var=float(mad * mad))
+
+    vmc_pade = spread()
     nj = neural.NeuralJastrow(64, 257, 6.0, seed=seed)
     t_train = time.perf_counter()
     hist = neural.fit_vmc(nj, g, rounds=rounds, steps=train_steps, lr=lr, vmc_steps=300, step=step,
                           log=lambda r: note(f"round {r['round']}: VMC E={r['vmc_E']:.4f} var={r['vmc_var']:.3f}"))
     t_train = time.perf_counter() - t_train
-    g.vmc(300, step)
-    e_n = g.get_walkers()["e_l"]
-    vmc_neural = dict(E=float(e_n.mean()), var=float(e_n.var()))
+    vmc_neural = spread()
     g.close()
 
     def projection(with_net, a):
@@ -262,9 +277,10 @@ def neural_bench(system="ar", walkers=16384, rounds=8, train_steps=60, lr=1e-3, 
     ratios = [p["t_1mHa_s"] / q["t_1mHa_s"] for p, q in zip(res["pade"]["rows"], res["neural"]["rows"])]
     dE0 = res["neural"]["E0"] - res["pade"]["E0"]
     return {"neural": {
-        "system": s.name, "walkers": walkers, "network": "2 x 64 SiLU per pair type, 257-node table, r_cut 6",
+        "system": s.name, "walkers": walkers, "training_walkers": train_walkers,
+        "network": "2 x 64 SiLU per pair type, 257-node table, r_cut 6",
         "training": dict(rounds=rounds, steps_per_round=train_steps, lr=lr, wall_s=t_train, history=hist),
-        "vmc": dict(pade=dict(E=hist[0]["vmc_E"], var=hist[0]["vmc_var"]), neural=vmc_neural),
+        "vmc": dict(pade=vmc_pade, neural=vmc_neural),
         "lrdmc": res, "time_to_1mHa_ratio_pade_over_neural": ratios,
         "E0_difference": dE0, "E0_difference_sigma": float(np.hypot(res["pade"]["sigma_E0"],
                                                                      res["neural"]["sigma_E0"])),
