@@ -44,3 +44,22 @@ def test_network_packing_round_trip():
         bad = {k: dict(v) for k, v in w.items()}
         bad["ee"]["W2"] = np.zeros((16, 15))
         neural.pack(bad)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N with N > 1 exits with a message, before touching a GPU."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2", "--steps", "1", "--warmup", "0"],
+                       cwd=bench.ROOT, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "exactly one GPU" in r.stderr
+
+
+def test_bench_source_hash_is_stable():
+    import subprocess
+    import sys
+    a = subprocess.run([sys.executable, "bench.py", "--source-hash"], cwd=bench.ROOT, capture_output=True, text=True,
+                       timeout=120)
+    assert a.returncode == 0 and len(a.stdout.strip()) == 64
+    assert a.stdout.strip() == bench.kernel_source_hash()
