@@ -471,7 +471,11 @@ def run_workload(name, steps, warmup, want_cpu, cpu_seconds):
     E, sig = stats.estimate(lwb, eb, p=None)
 
     shp = workcount.shape_of(s)
-    ops = workcount.projection_ops(shp, W, moves) if proj_n else 0.0
+    # generation starts: every walker on refresh generations (multiples of
+    # `refresh`, counted from the first generation after set_walkers)
+    R = max(1, int(cfg.refresh))
+    n_refresh = sum(1 for gen in range(warmup, warmup + steps) if R == 1 or gen % R == 0)
+    ops = workcount.projection_ops(shp, W * steps, moves, W * n_refresh) if proj_n else 0.0
     avg_ms = proj_ms / max(proj_n, 1)
     ops_per_launch = ops / max(proj_n, 1)
     achieved = ops_per_launch / (avg_ms * 1e-3) / 1e12 if proj_n else 0.0

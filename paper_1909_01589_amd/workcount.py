@@ -13,7 +13,9 @@ Units:
   M = 12N moves of one walker (done once per move plus once per walker and
   generation for the final holding time);
 * an accepted move: new orbital row with derivatives, Sherman-Morrison
-  update of Ainv and Y, determinant and Jastrow derivatives, local energy;
+  update of Ainv and Y, determinant derivatives, the Jastrow derivative
+  terms of the moved electron's pairs at its new and old position (the
+  other electrons' sums change only by those), local energy;
 * a generation start: Slater matrices with derivatives, Gauss-Jordan
   inversion, Y, derivatives and local energy of one walker.
 """
@@ -93,7 +95,7 @@ def accept_ops(s: Shape) -> float:
             + 3 * n * n              # Ainv rank-1 update
             + 3 * n * s.K            # Y rank-1 update
             + 4 * n * n * 2          # grad/lap D/D of the moved spin
-            + _PAIR_DERIV * s.N * (s.N - 1 + s.n_nuc)   # Jastrow derivatives
+            + _PAIR_DERIV * 2 * (s.N - 1 + s.n_nuc)     # the moved electron's pair terms, new and old
             + 14 * s.N)              # local energy
 
 
@@ -109,10 +111,12 @@ def setup_ops(s: Shape) -> float:
     return ops + _PAIR_DERIV * s.N * (s.N - 1 + s.n_nuc) + 14 * s.N
 
 
-def projection_ops(s: Shape, walkers: int, moves: int) -> float:
-    """Operations of one projection launch with `moves` accepted moves in
-    total over `walkers` walkers (each walker evaluates moves + 1 tables)."""
-    return walkers * setup_ops(s) + (moves + walkers) * table_ops(s) + moves * accept_ops(s)
+def projection_ops(s: Shape, walker_launches: int, moves: int, setups: int) -> float:
+    """Operations of projection launches with `moves` accepted moves in total,
+    `walker_launches` = walkers x launches (each walker evaluates one table
+    per accepted move plus one for the holding time that ends its
+    generation) and `setups` generation starts (refresh generations)."""
+    return setups * setup_ops(s) + (moves + walker_launches) * table_ops(s) + moves * accept_ops(s)
 
 
 def state_bytes(s: Shape) -> float:

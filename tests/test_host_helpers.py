@@ -63,3 +63,17 @@ def test_bench_source_hash_is_stable():
                        timeout=120)
     assert a.returncode == 0 and len(a.stdout.strip()) == 64
     assert a.stdout.strip() == bench.kernel_source_hash()
+
+
+def test_work_model_counts_by_hand():
+    """One electron, one s function, one nucleus: a table entry is 15 (points)
+    + 8 + 2 (switch) + 2 (k) + 13 (one group: 12 + s polynomial 1) + 14 (one
+    Pade pair) + 3 (Jastrow exp) + 3 (T) = 60 operations, 12 moves and the
+    cumulative sum: 12 * 60 + 24; launches add tables, accepts and starts."""
+    from paper_1909_01589_amd import inputs, workcount
+    s = workcount.shape_of(inputs.hydrogenic(1.0))
+    assert (s.N, s.K, s.n_nuc, s.n_heavy, s.groups) == (1, 1, 1, 1, [(0,)])
+    t = workcount.table_ops(s)
+    assert t == 12 * 60 + 24
+    a, g = workcount.accept_ops(s), workcount.setup_ops(s)
+    assert workcount.projection_ops(s, 10, 7, 3) == 3 * g + 17 * t + 7 * a
