@@ -108,3 +108,32 @@ def test_binding_refuses_host_tensors(lib):
     from paper_1909_01589_amd.lrdmc import _dptr
     with pytest.raises(ValueError):
         _dptr(torch.zeros(3, dtype=torch.float64))
+
+
+def test_network_sizes_and_validation(lib):
+    """lrdmc_net_*: sizes, and every argument check returns EINVAL before any
+    device work (the pointers below are never dereferenced)."""
+    assert lib.lrdmc_net_param_count(64) == 64 * 64 + 4 * 64 + 1
+    assert lib.lrdmc_net_param_count(0) == 0 and lib.lrdmc_net_param_count(257) == 0
+    assert lib.lrdmc_net_workspace_size(64, 257) == 2 * 257 * (9 * 64 + 1)
+    for h, g in ((64, 1), (0, 10), (64, 4097), (300, 10)):
+        assert lib.lrdmc_net_workspace_size(h, g) == 0
+    dummy = C.c_void_p(64)
+    for args in ((None, 8, 9, 1.0, dummy), (dummy, 8, 9, 1.0, None), (dummy, 0, 9, 1.0, dummy),
+                 (dummy, 8, 1, 1.0, dummy), (dummy, 8, 4097, 1.0, dummy), (dummy, 8, 9, 0.0, dummy),
+                 (dummy, 8, 9, float("nan"), dummy), (dummy, 8, 9, float("inf"), dummy)):
+        assert lib.lrdmc_net_tabulate(*args, None) == -1
+        assert lib.lrdmc_net_tabulate_backward(args[0], args[1], args[2], args[3], dummy, args[4], dummy,
+                                               None) == -1
+    assert lib.lrdmc_net_tabulate_backward(dummy, 8, 9, 1.0, dummy, dummy, None, None) == -1
+
+
+def test_context_entry_points_reject_null(lib):
+    dummy = C.c_void_p(64)
+    assert lib.lrdmc_vmc(None, 10, 0.3, None) == -1
+    assert lib.lrdmc_set_jastrow_table(None, dummy, 9, 1.0, 0, None) == -1
+    assert lib.lrdmc_jastrow_table_grad(None, dummy, None, None, dummy, None) == -1
+    assert lib.lrdmc_jastrow_grad(None, dummy, dummy, None) == -1
+    assert lib.lrdmc_set_jastrow(None, 1.0, 1.0) == -1
+    assert lib.lrdmc_use_generic(None, 0) == -1
+    assert lib.lrdmc_is_specialized(None) == 0
