@@ -383,6 +383,95 @@ SWEEP = (("be", 300, 30), ("ar_a0.2", 300, 30), ("ar_a0.1", 300, 30), ("zsweep10
          ("zsweep36", 30, 5), ("zsweep54", 20, 5), ("molecule", 20, 5))
 
 
+# Acceleration column of Table S-I (ratio of accepted off-diagonal moves,
+# single over double grid) at a = 1/(alpha Z), for the rows measured here.
+TABLE_S1_ACCELERATION = {("Be", 3.33): 2.0, ("Be", 2.0): 1.8, ("Be", 1.0): 1.4,
+                         ("Ne", 3.33): 3.5, ("Ne", 2.0): 3.1, ("Ne", 1.0): 2.4}
+
+
+def zscan_phys(walkers=8192, gens=100, warmup=20, moves_per_electron=2.0, seed=0):
+    """Single vs double grid for Be, Ne and Ar with screened hydrogenic
+    orbitals (physical core densities, unlike the random-MO Z-sweep atoms) at
+    a = 1/(alpha Z): the move-rate ratio beside Eq. (5) with the sampled
+    N_core and beside the acceleration column of Table S-I (Be and Ne), and
+    the ratio of GPU cost per unit projection time, both grids on the general
+    kernel (the kernels built for fixed sizes exist for the double grid only;
+    where one serves the system, its ratio is reported beside).  Single and double grid
+    share the trial function and its nodes, so to first order the cost ratio
+    is the ratio of times to a fixed error (the paper's CPU-time
+    accelerations at alpha = 3.5: Be 1.4, Ne 2.3, Ar 3.3)."""
+    import torch
+    from paper_1909_01589_amd import inputs
+    from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_is_specialized, lrdmc_spacing, lrdmc_use_generic
+    systems = (("Be", inputs.atom_screened(4, (8, 0, 0), 0.1, 3.0, name="be_screened"), 0.5, (3.33, 2.0, 1.0)),
+               ("Ne", inputs.atom_screened(10, (11, 6, 0), 0.05, 2.5, name="ne_screened"), 0.3,
+                (3.33, 3.5, 2.0, 1.0)),
+               ("Ar", inputs.ar_screened(), 0.25, (3.33, 3.5)))
+    out = []
+    for label, s, step, alphas in systems:
+        Z, N = s.z_max, s.n_elec
+        g = LRDMC(s, 0.01, 0.01, 1.0, 1.0, walkers, seed=seed, rotate=1, refresh=8, grids=1)
+        g.set_walkers(inputs.initial_walkers(s, walkers, seed), 0)
+        g.vmc(100 * N, step)
+        pos0 = g.get_walkers()["pos"].clone()
+        g.close()
+        for alpha in alphas:
+            a = 1.0 / (alpha * Z)
+            rc_d, ap_d, nc_model = lrdmc_spacing(float(Z), a)
+            ap_d = max(ap_d, a)
+            nc = _switch_sum(pos0.cpu().numpy(), s.R[0], rc_d, 0)
+            cost, delta, taus, ms, jumps = {}, {}, {}, {}, {}
+            specialized = False
+            for mode, (rc, ap, grids, generic) in (("single_grid", (1.0, a, 1, 1)), ("double_grid", (rc_d, ap_d, 2, 1)),
+                                                   ("double_grid_auto", (rc_d, ap_d, 2, 0))):
+                if mode == "double_grid_auto":
+                    delta[mode] = delta["double_grid"]
+                else:
+                    g = LRDMC(s, a, ap, rc, 1.0, walkers, seed=seed, rotate=1, refresh=8, grids=grids)
+                    delta[mode] = float(g.eval_moves(pos0)[2][:, 6].mean())
+                    g.close()
+                tau = moves_per_electron * N / delta[mode]
+                g = LRDMC(s, a, ap, rc, tau, walkers, seed=seed, rotate=1, refresh=8, grids=grids)
+                lrdmc_use_generic(g.ctx, generic)
+                if mode == "double_grid_auto":
+                    specialized = lrdmc_is_specialized(g.ctx)
+                    if not specialized:
+                        g.close()
+                        continue
+                g.set_walkers(pos0, 0)
+                g.run(warmup)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rec = g.run(gens)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                jumps[mode] = float(rec["n_moves"].double().mean()) / walkers
+                cost[mode] = wall / (walkers * gens * tau)
+                taus[mode], ms[mode] = tau, 1e3 * wall / gens
+                g.close()
+            ratio = ap_d / a
+            row = dict(atom=label, Z=Z, alpha=alpha, a=a, a_prime=ap_d, r_c=rc_d, n_core_model=nc_model,
+                       n_core_sampled=nc, move_rate_ratio=delta["single_grid"] / delta["double_grid"],
+                       eq5_sampled=1.0 / (nc / N + (N - nc) / N * ratio ** -2),
+                       eq5_model=1.0 / (nc_model / N + (N - nc_model) / N * ratio ** -2),
+                       tau_single=taus["single_grid"], tau_double=taus["double_grid"],
+                       ms_per_gen_single=ms["single_grid"], ms_per_gen_double=ms["double_grid"],
+                       moves_per_walker_gen_single=jumps["single_grid"],
+                       moves_per_walker_gen_double=jumps["double_grid"],
+                       cost_single=cost["single_grid"], cost_double=cost["double_grid"],
+                       acceleration=cost["single_grid"] / cost["double_grid"],
+                       ms_per_gen_double_specialized=ms["double_grid_auto"] if specialized else None,
+                       acceleration_specialized_double=(cost["single_grid"] / cost["double_grid_auto"]
+                                                        if specialized else None),
+                       paper_acceptance=TABLE_S1_ACCELERATION.get((label, alpha)))
+            print(f"[zscan-phys] {label} alpha={alpha}: N_core {nc:.3f} (model {nc_model:.3f}), move-rate ratio "
+                  f"{row['move_rate_ratio']:.3f} (Eq. 5: {row['eq5_sampled']:.3f}), acceleration {row['acceleration']:.2f}",
+                  file=sys.stderr, flush=True)
+            out.append(row)
+    return {"zscan_phys": {"walkers": walkers, "generations": gens, "rows": out,
+                           "paper_cpu_time_alpha_3.5": {"Be": 1.4, "Ne": 2.3, "Ar": 3.3}}}
+
+
 def sweep():
     """Throughput of every configured workload (generations, warm-up) as in
     the benchmark line: electron-moves/s, ms per generation, the kernel's
@@ -519,6 +608,8 @@ def main():
                     help="only run the learned-Jastrow comparison (VMC, training, LRDMC scan) and exit")
     ap.add_argument("--sweep", action="store_true",
                     help="only time every configured workload (Be-like, Ar-like, Z-sweep, molecule) and exit")
+    ap.add_argument("--zscan-phys", action="store_true",
+                    help="only run the single/double-grid comparison for Ne and Ar with screened orbitals and exit")
     ap.add_argument("--zscan", action="store_true",
                     help="only run the single/double-grid cost scan over Z = 10, 18, 36, 54 and exit")
     ap.add_argument("--ascan", action="store_true",
@@ -546,6 +637,9 @@ def main():
         return
     if args.sweep:
         print(json.dumps(sweep()), flush=True)
+        return
+    if args.zscan_phys:
+        print(json.dumps(zscan_phys()), flush=True)
         return
     if args.zscan:
         print(json.dumps(zscan()), flush=True)
