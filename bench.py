@@ -389,7 +389,45 @@ TABLE_S1_ACCELERATION = {("Be", 3.33): 2.0, ("Be", 2.0): 1.8, ("Be", 1.0): 1.4,
                          ("Ne", 3.33): 3.5, ("Ne", 2.0): 3.1, ("Ne", 1.0): 2.4}
 
 
-def zscan_phys(walkers=8192, gens=100, warmup=20, moves_per_electron=2.0, seed=0):
+def _production(s, a, ap, rc, grids, tau, pos0, walkers, t_equil, t_prod, ms_per_gen, seed, tag):
+    """Equilibrate for projection time t_equil, then run t_prod on the general
+    kernel in chunks of about 20 s (a progress line each): (E, sigma) of the
+    generation energies (reblocked), generations and production wall time."""
+    import torch
+    from paper_1909_01589_amd import stats
+    from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_use_generic
+    g = LRDMC(s, a, ap, rc, tau, walkers, seed=seed, rotate=1, refresh=8, grids=grids)
+    lrdmc_use_generic(g.ctx, 1)
+    g.set_walkers(pos0, 0)
+    chunk = max(100, int(20e3 / ms_per_gen))
+    n_eq, n_prod = int(np.ceil(t_equil / tau)), int(np.ceil(t_prod / tau))
+    while n_eq > 0:
+        g.run(min(chunk, n_eq))
+        n_eq -= chunk
+    torch.cuda.synchronize()
+    lw, eb, done, wall = [], [], 0, 0.0
+    while done < n_prod:
+        n = min(chunk, n_prod - done)
+        t0 = time.perf_counter()
+        out = g.run(n)
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        lw.append(out["log_wbar"].cpu().numpy())
+        eb.append(out["ebar"].cpu().numpy())
+        done += n
+        print(f"[zscan-phys] {tag}: {done}/{n_prod} generations", file=sys.stderr, flush=True)
+    g.close()
+    lw, eb = np.concatenate(lw), np.concatenate(eb)
+    E, sig = stats.estimate(lw, eb, p=None)
+    h = n_prod // 2
+    (E1, s1), (E2, s2) = stats.estimate(lw[:h], eb[:h], p=None), stats.estimate(lw[h:], eb[h:], p=None)
+    return dict(E=E, sigma=sig, t_prod=t_prod, generations=n_prod, wall_s=wall,
+                time_to_1mHa_s=wall * (sig / 1e-3) ** 2, E_first_half=E1, sigma_first_half=s1,
+                E_second_half=E2, sigma_second_half=s2)
+
+
+def zscan_phys(walkers=8192, gens=100, warmup=20, moves_per_electron=2.0, seed=0, t_equil=5.0,
+               t_prod=None, alpha_prod=3.5):
     """Single vs double grid for Be, Ne and Ar with screened hydrogenic
     orbitals (physical core densities, unlike the random-MO Z-sweep atoms) at
     a = 1/(alpha Z): the move-rate ratio beside Eq. (5) with the sampled
@@ -399,11 +437,16 @@ def zscan_phys(walkers=8192, gens=100, warmup=20, moves_per_electron=2.0, seed=0
     where one serves the system, its ratio is reported beside).  Single and double grid
     share the trial function and its nodes, so to first order the cost ratio
     is the ratio of times to a fixed error (the paper's CPU-time
-    accelerations at alpha = 3.5: Be 1.4, Ne 2.3, Ar 3.3)."""
+    accelerations at alpha = 3.5: Be 1.4, Ne 2.3, Ar 3.3).  At alpha_prod
+    both grids also run a production of projection time t_prod[atom] for the
+    time to sigma(E) = 1 mHa, its single/double ratio and the double - single
+    energy difference (the bias column of Table S-I)."""
     import torch
     from paper_1909_01589_amd import inputs
     from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_is_specialized, lrdmc_spacing, lrdmc_use_generic
-    systems = (("Be", inputs.atom_screened(4, (8, 0, 0), 0.1, 3.0, name="be_screened"), 0.5, (3.33, 2.0, 1.0)),
+    t_prod = dict(Be=80.0, Ne=40.0, Ar=8.0) if t_prod is None else t_prod
+    systems = (("Be", inputs.atom_screened(4, (8, 0, 0), 0.1, 3.0, name="be_screened"), 0.5,
+                (3.33, 3.5, 2.0, 1.0)),
                ("Ne", inputs.atom_screened(10, (11, 6, 0), 0.05, 2.5, name="ne_screened"), 0.3,
                 (3.33, 3.5, 2.0, 1.0)),
                ("Ar", inputs.ar_screened(), 0.25, (3.33, 3.5)))
@@ -464,6 +507,16 @@ def zscan_phys(walkers=8192, gens=100, warmup=20, moves_per_electron=2.0, seed=0
                        acceleration_specialized_double=(cost["single_grid"] / cost["double_grid_auto"]
                                                         if specialized else None),
                        paper_acceptance=TABLE_S1_ACCELERATION.get((label, alpha)))
+            if alpha == alpha_prod:
+                prod = {}
+                for mode, (rc, ap, grids) in (("single_grid", (1.0, a, 1)), ("double_grid", (rc_d, ap_d, 2))):
+                    prod[mode] = _production(s, a, ap, rc, grids, taus[mode], pos0, walkers, t_equil,
+                                             t_prod[label], ms[mode], seed, f"{label} {mode}")
+                ps, pd = prod["single_grid"], prod["double_grid"]
+                row["production"] = prod
+                row["time_to_error_acceleration"] = ps["time_to_1mHa_s"] / pd["time_to_1mHa_s"]
+                row["bias_mHa"] = 1e3 * (pd["E"] - ps["E"])
+                row["bias_sigma_mHa"] = 1e3 * float(np.hypot(pd["sigma"], ps["sigma"]))
             print(f"[zscan-phys] {label} alpha={alpha}: N_core {nc:.3f} (model {nc_model:.3f}), move-rate ratio "
                   f"{row['move_rate_ratio']:.3f} (Eq. 5: {row['eq5_sampled']:.3f}), acceleration {row['acceleration']:.2f}",
                   file=sys.stderr, flush=True)
