@@ -474,27 +474,14 @@ __device__ __forceinline__ double rsqrt_nr(double a)
 }
 
 
-// u(r) for the move table: one Newton-Raphson step on each hardware estimate
-// (estimates within 2^-24 on gfx950, so about 5e-15 relative after the
-// step), enough for the ratio exp(dJ).
+// 1/r for the move table's pair terms: one Newton-Raphson step on the
+// hardware estimate (estimates within 2^-24 on gfx950, so about 5e-15
+// relative after the step; the same for the shared reciprocals of pair_u2
+// and pair_u4), enough for the ratio exp(dJ).
 __device__ __forceinline__ double rsqrt_move(double d2)
 {
     const double y = __builtin_amdgcn_rsq(d2);
     return fma(y, fma(-0.5 * d2 * y, y, 0.5), y);
-}
-
-// u = c / (1 / r + b) from y = 1 / r.
-__device__ __forceinline__ double pade_u_y(double c, double b, double y)
-{
-    const double a = y + b;
-    double x = __builtin_amdgcn_rcp(a);
-    x = fma(x, fma(-a, x, 1.0), x);
-    return c * x;
-}
-
-__device__ __forceinline__ double pade_u(double c, double b, double d2)
-{
-    return pade_u_y(c, b, rsqrt_move(d2));
 }
 
 struct PairD {
@@ -540,18 +527,56 @@ __device__ __forceinline__ void corr_eval(const KArgs &A, int type, double r, do
     }
 }
 
-// u of a pair with the correction scaled by s (1 for electron pairs, Z for
-// an electron and a nucleus; 0 drops the pair).
+// u = c / (1/r + b) of one pair at the two points a and b of a move pair
+// (squared distances d2a, d2b), plus s F(r) with the learned correction
+// (s = 1 for electron pairs, Z for an electron and a nucleus, 0 drops the
+// pair).  The two denominators share one reciprocal: the hardware estimate
+// of 1 / (d_a d_b) with one Newton-Raphson step, times the other factor.
 template <bool CORR>
-__device__ __forceinline__ double pair_u(const KArgs &A, double c, double b, double d2, int type, double s)
+__device__ __forceinline__ void pair_u2(const KArgs &A, double c, double b, double d2a, double d2b, int type,
+                                        double s, double &ua, double &ub)
 {
+    const double ya = rsqrt_move(d2a), yb = rsqrt_move(d2b);
+    const double da = ya + b, db = yb + b, p = da * db;
+    double x = __builtin_amdgcn_rcp(p);
+    x = fma(x, fma(-p, x, 1.0), x);
+    const double cx = c * x;
+    ua = cx * db;
+    ub = cx * da;
     if constexpr (CORR) {
-        const double y = rsqrt_move(d2);
         double F[3];
-        corr_eval<0>(A, type, d2 * y, F);
-        return fma(s, F[0], pade_u_y(c, b, y));
-    } else {
-        return pade_u(c, b, d2);
+        corr_eval<0>(A, type, d2a * ya, F);
+        ua = fma(s, F[0], ua);
+        corr_eval<0>(A, type, d2b * yb, F);
+        ub = fma(s, F[0], ub);
+    }
+}
+
+// The same for two electron pairs (coefficients c0, c1, correction scales
+// s0, s1) at both points: ua, ub are the sums over both pairs, and the four
+// denominators share one reciprocal.
+template <bool CORR>
+__device__ __forceinline__ void pair_u4(const KArgs &A, double c0, double c1, double b, double qa0, double qb0,
+                                        double qa1, double qb1, double s0, double s1, double &ua, double &ub)
+{
+    const double ya0 = rsqrt_move(qa0), yb0 = rsqrt_move(qb0), ya1 = rsqrt_move(qa1), yb1 = rsqrt_move(qb1);
+    const double da0 = ya0 + b, db0 = yb0 + b, da1 = ya1 + b, db1 = yb1 + b;
+    const double p0 = da0 * db0, p1 = da1 * db1, p = p0 * p1;
+    double x = __builtin_amdgcn_rcp(p);
+    x = fma(x, fma(-p, x, 1.0), x);
+    const double x0 = c0 * (x * p1), x1 = c1 * (x * p0);
+    ua = fma(x0, db0, x1 * db1);
+    ub = fma(x0, da0, x1 * da1);
+    if constexpr (CORR) {
+        double F[3];
+        corr_eval<0>(A, 0, qa0 * ya0, F);
+        ua = fma(s0, F[0], ua);
+        corr_eval<0>(A, 0, qb0 * yb0, F);
+        ub = fma(s0, F[0], ub);
+        corr_eval<0>(A, 0, qa1 * ya1, F);
+        ua = fma(s1, F[0], ua);
+        corr_eval<0>(A, 0, qb1 * yb1, F);
+        ub = fma(s1, F[0], ub);
     }
 }
 
@@ -586,30 +611,42 @@ __device__ __forceinline__ void jastrow_point2(const KArgs &A, const double *pos
         const double x0 = pos[3 * j], y0 = pos[3 * j + 1], z0 = pos[3 * j + 2];
         const double x1 = pos[3 * j + 3], y1 = pos[3 * j + 4], z1 = pos[3 * j + 5];
         double dx = ra[0] - x0, dy = ra[1] - y0, dz = ra[2] - z0;
-        a0 += pair_u<CORR>(A, c0, A.b_ee, dx * dx + dy * dy + dz * dz, 0, s0);
+        const double qa0 = dx * dx + dy * dy + dz * dz;
         dx = rb[0] - x0; dy = rb[1] - y0; dz = rb[2] - z0;
-        b0 += pair_u<CORR>(A, c0, A.b_ee, dx * dx + dy * dy + dz * dz, 0, s0);
+        const double qb0 = dx * dx + dy * dy + dz * dz;
         dx = ra[0] - x1; dy = ra[1] - y1; dz = ra[2] - z1;
-        a1 += pair_u<CORR>(A, c1, A.b_ee, dx * dx + dy * dy + dz * dz, 0, s1);
+        const double qa1 = dx * dx + dy * dy + dz * dz;
         dx = rb[0] - x1; dy = rb[1] - y1; dz = rb[2] - z1;
-        b1 += pair_u<CORR>(A, c1, A.b_ee, dx * dx + dy * dy + dz * dz, 0, s1);
+        const double qb1 = dx * dx + dy * dy + dz * dz;
+        double ua, ub;
+        pair_u4<CORR>(A, c0, c1, A.b_ee, qa0, qb0, qa1, qb1, s0, s1, ua, ub);
+        a0 += ua;
+        b0 += ub;
     }
     if (j < A.N) {
         const double c0 = j == i ? 0.0 : (((j < A.n_up) == up) ? 0.25 : 0.5);
         const double s0 = j == i ? 0.0 : 1.0;
         const double x0 = pos[3 * j], y0 = pos[3 * j + 1], z0 = pos[3 * j + 2];
         double dx = ra[0] - x0, dy = ra[1] - y0, dz = ra[2] - z0;
-        a0 += pair_u<CORR>(A, c0, A.b_ee, dx * dx + dy * dy + dz * dz, 0, s0);
+        const double qa0 = dx * dx + dy * dy + dz * dz;
         dx = rb[0] - x0; dy = rb[1] - y0; dz = rb[2] - z0;
-        b0 += pair_u<CORR>(A, c0, A.b_ee, dx * dx + dy * dy + dz * dz, 0, s0);
+        const double qb0 = dx * dx + dy * dy + dz * dz;
+        double ua, ub;
+        pair_u2<CORR>(A, c0, A.b_ee, qa0, qb0, 0, s0, ua, ub);
+        a0 += ua;
+        b0 += ub;
     }
     for (int I = 0; I < A.n_nuc; ++I) {
         const auto *R = cst(A.Rnuc) + 3 * I;
         const double c = -cst(A.Znuc)[I];
         double dx = ra[0] - R[0], dy = ra[1] - R[1], dz = ra[2] - R[2];
-        a1 += pair_u<CORR>(A, c, A.b_en, dx * dx + dy * dy + dz * dz, 1, -c);
+        const double qa = dx * dx + dy * dy + dz * dz;
         dx = rb[0] - R[0]; dy = rb[1] - R[1]; dz = rb[2] - R[2];
-        b1 += pair_u<CORR>(A, c, A.b_en, dx * dx + dy * dy + dz * dz, 1, -c);
+        const double qb = dx * dx + dy * dy + dz * dz;
+        double ua, ub;
+        pair_u2<CORR>(A, c, A.b_en, qa, qb, 1, -c, ua, ub);
+        a1 += ua;
+        b1 += ub;
     }
     out_a = a0 + a1;
     out_b = b0 + b1;
