@@ -730,6 +730,8 @@ def main():
         "projection_time_per_s": main_res["projection_time_per_s"],
         "E_Ha": main_res["E_Ha"], "sigma_E_Ha": main_res["sigma_E_Ha"],
         "time_to_sigma_1mHa_s": main_res["time_to_sigma_1mHa_s"],
+        "energy_note": "seeded random MOs: a throughput workload whose nodes are not physical; E_Ha and its "
+                       "sigma only record the run (physical energies: --ascan, --zscan-phys, --neural)",
     }
     if "cpu_baseline" in main_res:
         line["cpu_baseline"] = main_res["cpu_baseline"]
