@@ -559,13 +559,15 @@ def copy_probe():
     print(json.dumps({"copy_bytes": n * 8}), flush=True)
 
 
-def cpu_baseline(system, a, ap, rc, tau, seed, pos, gen0, seconds):
+def cpu_baseline(system, a, ap, rc, tau, seed, pos, gen0, seconds, threads=None):
     """The CPU oracle, as it stands, on a bounded sample of the workload:
     chunks of 64 walkers of the equilibrated population, one generation each,
-    until `seconds` of wall time have passed."""
+    until `seconds` of wall time have passed, on `threads` host threads (all
+    by default: OMP_NUM_THREADS, else the CPU count)."""
     import oracle
     oracle.build(force=False)
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    if threads is None:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
     o = oracle.Oracle(system, a, ap, rc, tau=tau, seed=seed)
     W = pos.shape[0]
     moves, chunks = 0, 0
@@ -639,6 +641,8 @@ def run_workload(name, steps, warmup, want_cpu, cpu_seconds):
     if want_cpu:
         pos = gpu.get_walkers()["pos"].cpu().numpy()
         res["cpu_baseline"] = cpu_baseline(s, cfg.a, ap, rc, cfg.tau, cfg.seed, pos, 10_000_000, cpu_seconds)
+        one = cpu_baseline(s, cfg.a, ap, rc, cfg.tau, cfg.seed, pos, 10_000_000, cpu_seconds / 2, threads=1)
+        res["cpu_baseline"]["single_core"] = {"value": one["value"], "sample": one["sample"]}
     gpu.close()
     return cfg, res
 
