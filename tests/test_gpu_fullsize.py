@@ -57,6 +57,35 @@ def test_full_population_sampled_parity(name):
     gpu.close()
 
 
+def test_steady_state_sampled_parity():
+    """The benchmark configuration deep in the run: after 101 generations
+    (walkers settled, more moves per generation), generations 101 and 102
+    run on state carried by Sherman-Morrison updates since the refresh at
+    generation 96; sampled slots against the oracle from the same positions,
+    which recomputes everything."""
+    from paper_1909_01589_amd.lrdmc import LRDMC
+    cfg = inputs.get_config("ar_a0.1")
+    s = cfg.system
+    rc, ap, _ = spacing.spacing(s.z_max, cfg.a)
+    W = cfg.walkers
+    assert cfg.refresh == 8
+    gpu = LRDMC(s, cfg.a, ap, rc, cfg.tau, W, seed=cfg.seed, rotate=cfg.rotate, refresh=cfg.refresh)
+    orc = oracle.Oracle(s, cfg.a, ap, rc, tau=cfg.tau, seed=cfg.seed, rotate=cfg.rotate)
+    gpu.set_walkers(inputs.initial_walkers(s, W, cfg.seed), 0)
+    gpu.run(101)
+    assert gpu.generation == 101
+    slots = [3, 1500, 3333, W - 2]
+    start = gpu.get_walkers()["pos"].cpu().numpy()
+    out = _check_generation(gpu, orc, start, 101, slots)
+    assert out["n_moves"].mean() > 10.0
+    rec = gpu.branch()
+    idx_o, _, eb_o = orc.reconfigure(out["log_w"], out["e_l"], orc.xi(101))
+    assert np.array_equal(rec["idx"].cpu().numpy(), idx_o)
+    start = gpu.get_walkers()["pos"].cpu().numpy()
+    _check_generation(gpu, orc, start, 102, slots)
+    gpu.close()
+
+
 @pytest.mark.parametrize("name,W", [("zsweep54", 64), ("molecule", 32)])
 def test_large_systems_sampled_parity(name, W):
     from paper_1909_01589_amd.lrdmc import LRDMC
