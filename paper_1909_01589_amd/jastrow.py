@@ -22,6 +22,7 @@ class PadeJastrow(torch.autograd.Function):
     @staticmethod
     def forward(ctx, theta: torch.Tensor, engine: LRDMC, pos: torch.Tensor):
         b = theta.detach().to("cpu", torch.float64)
+        pos = engine.positions(pos)
         lrdmc_set_jastrow(engine.ctx, float(b[0]), float(b[1]))
         out = torch.empty(engine.W, 6, dtype=torch.float64, device=engine.device)
         lrdmc_jastrow_grad(engine.ctx, pos, out)

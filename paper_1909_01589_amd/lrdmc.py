@@ -345,11 +345,16 @@ class LRDMC:
     def _f64(self, *shape):
         return torch.empty(*shape, dtype=torch.float64, device=self.device)
 
-    def set_walkers(self, pos, generation: int = 0):
+    def positions(self, pos) -> torch.Tensor:
+        """pos as the contiguous float64 device tensor [W][N][3] the kernels
+        read for this context (the C entry points take bare pointers)."""
         t = torch.as_tensor(pos, dtype=torch.float64).to(self.device).contiguous()
         if tuple(t.shape) != (self.W, self.N, 3):
             raise ValueError(f"positions must be [{self.W}, {self.N}, 3]")
-        lrdmc_set_walkers(self.ctx, t, generation)
+        return t
+
+    def set_walkers(self, pos, generation: int = 0):
+        lrdmc_set_walkers(self.ctx, self.positions(pos), generation)
 
     @property
     def generation(self) -> int:
@@ -396,9 +401,7 @@ class LRDMC:
 
     def jastrow_table_grad(self, pos, c_j=None, c_e=None):
         """[2][G][3]: d/dtab sum_w (c_j[w] J_w + c_e[w] E_L,w)."""
-        t = torch.as_tensor(pos, dtype=torch.float64).to(self.device).contiguous()
-        if tuple(t.shape) != (self.W, self.N, 3):
-            raise ValueError(f"positions must be [{self.W}, {self.N}, 3]")
+        t = self.positions(pos)
         cj = None if c_j is None else torch.as_tensor(c_j, dtype=torch.float64).to(self.device).contiguous()
         ce = None if c_e is None else torch.as_tensor(c_e, dtype=torch.float64).to(self.device).contiguous()
         for c in (cj, ce):
@@ -412,17 +415,13 @@ class LRDMC:
 
     def jastrow_grad(self, pos):
         """[W][6]: E_L, J, dJ/db_ee, dJ/db_en, dE_L/db_ee, dE_L/db_en."""
-        t = torch.as_tensor(pos, dtype=torch.float64).to(self.device).contiguous()
-        if tuple(t.shape) != (self.W, self.N, 3):
-            raise ValueError(f"positions must be [{self.W}, {self.N}, 3]")
+        t = self.positions(pos)
         out = self._f64(self.W, 6)
         lrdmc_jastrow_grad(self.ctx, t, out)
         return out
 
     def eval_moves(self, pos):
-        t = torch.as_tensor(pos, dtype=torch.float64).to(self.device).contiguous()
-        if tuple(t.shape) != (self.W, self.N, 3):
-            raise ValueError(f"positions must be [{self.W}, {self.N}, 3]")
+        t = self.positions(pos)
         rho, k = self._f64(self.W, self.M), self._f64(self.W, self.M)
         diag = self._f64(self.W, LRDMC_NDIAG)
         lrdmc_eval_moves(self.ctx, t, rho, k, diag)

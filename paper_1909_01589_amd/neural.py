@@ -108,6 +108,7 @@ class TableJastrow(torch.autograd.Function):
     @staticmethod
     def forward(ctx, tab: torch.Tensor, engine: LRDMC, pos: torch.Tensor, r_cut: float):
         t = tab.detach().contiguous()
+        pos = engine.positions(pos)
         lrdmc_set_jastrow_table(engine.ctx, t, r_cut)
         engine.table_nodes = int(t.shape[1])
         out = torch.empty(engine.W, 6, dtype=torch.float64, device=engine.device)
@@ -165,7 +166,7 @@ class NeuralJastrow:
         trial function moves far from the sampling one); power > 0: the
         correlated-sampling weights exp(power (J - J0)).  Returns the
         (mean, variance) history as floats."""
-        pos = torch.as_tensor(pos, dtype=torch.float64).to(engine.device).contiguous()
+        pos = engine.positions(pos)
         with torch.no_grad():
             j0, _ = self.energies(engine, pos)
         opt = torch.optim.Adam([self.params], lr=lr)

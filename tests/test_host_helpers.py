@@ -77,3 +77,17 @@ def test_work_model_counts_by_hand():
     assert t == 12 * 60 + 24
     a, g = workcount.accept_ops(s), workcount.setup_ops(s)
     assert workcount.projection_ops(s, 10, 7, 3) == 3 * g + 17 * t + 7 * a
+
+
+def test_positions_are_checked_before_a_pointer_is_passed():
+    """The C entry points take bare device pointers, so the binding checks the
+    walker positions' shape against the context (W, N) before every call;
+    here on an instance without a device context."""
+    from paper_1909_01589_amd.lrdmc import LRDMC
+    eng = object.__new__(LRDMC)
+    eng.W, eng.N, eng.device = 4, 3, "cpu"
+    t = eng.positions(np.zeros((4, 3, 3)))
+    assert t.dtype.is_floating_point and tuple(t.shape) == (4, 3, 3) and t.is_contiguous()
+    for bad in (np.zeros((3, 3, 3)), np.zeros((4, 2, 3)), np.zeros((4, 3))):
+        with pytest.raises(ValueError):
+            eng.positions(bad)
