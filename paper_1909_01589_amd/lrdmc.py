@@ -211,8 +211,12 @@ def lrdmc_eval_moves(ctx, pos, rho=None, k=None, diag=None, stream=None):
 
 
 def lrdmc_reconfigure(log_w, e_loc, xi: float, idx, stats=None, stream=None):
+    """idx[W] (int32) and stats[2] = (log w_bar, e_bar) from log_w[W], e_loc[W]."""
+    W = int(log_w.numel())
+    if e_loc.numel() != W or idx.numel() != W or (stats is not None and stats.numel() < 2):
+        raise ValueError("log_w, e_loc and idx must hold W elements each, stats at least 2")
     _check(load().lrdmc_reconfigure(_dptr(log_w, torch.float64), _dptr(e_loc, torch.float64),
-                                    int(log_w.shape[0]), float(xi), _dptr(idx, torch.int32),
+                                    W, float(xi), _dptr(idx, torch.int32),
                                     _dptr(stats, torch.float64), _stream(stream)))
 
 
