@@ -91,3 +91,16 @@ def test_positions_are_checked_before_a_pointer_is_passed():
     for bad in (np.zeros((3, 3, 3)), np.zeros((4, 2, 3)), np.zeros((4, 3))):
         with pytest.raises(ValueError):
             eng.positions(bad)
+
+
+def test_table_s1_accelerations_quoted_by_the_bench_match_the_fixture():
+    """The acceleration column the single/double comparison prints beside its
+    measured move-rate ratios is the one transcribed (with its citation) in
+    tests/golden/table_s1.txt."""
+    import os
+    rows = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "table_s1.txt"))
+    names = {4: "Be", 10: "Ne"}
+    for (atom, alpha), acc in bench.TABLE_S1_ACCELERATION.items():
+        hit = [r for r in rows if names.get(int(r[0])) == atom and abs(r[2] - alpha) < 1e-9]
+        assert len(hit) == 1, (atom, alpha)
+        assert hit[0][3] == acc
