@@ -7,7 +7,13 @@ the seeded inputs of ``paper_1909_01589_amd.inputs``.
 
 ``lrdmc_oracle.c`` (plain C, FP64) holds the projection step; ``spacing.py``
 the host-side parameter choice of the paper (r_c and a'/a); ``estimator.py``
-the energy estimator and its error bar.
+the energy estimator and its error bar; ``neural.py`` the learned Jastrow
+correction's network and tabulation.
+
+Every function is pinned by the CPU tests (closed forms, brute force, the
+paper's printed values, statistical limits).  Parity unpinned: the absolute
+energies of the random-MO workloads, which have no reference value and are
+checked only through parity with the GPU path.
 """
 from __future__ import annotations
 

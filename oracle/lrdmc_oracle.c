@@ -15,6 +15,13 @@
  *   - the local energy uses the textbook analytic derivatives;
  *   - cumulative sums are sequential, left to right.
  *
+ * Pins: every function here is checked by the CPU tests against what the
+ * paper and the mathematics fix (closed forms, brute force on small inputs,
+ * the printed values of Table S-I and S-II, statistical limits).  Parity
+ * unpinned: the absolute energies of the random-MO workloads (Be-like,
+ * Ar-like, Z-sweep, molecule) have no reference value; they are checked only
+ * through parity with the GPU path.
+ *
  * Method passages (paper numbering):
  *   main text Eq. (1): Laplacian split into a small-spacing part weighted by
  *     p and a large-spacing part weighted by 1-p;
