@@ -131,7 +131,7 @@ def test_chain_gradient_matches_oracle_objective(power):
     var_o, j_o, e_o = _oracle_objective(s, a, ap, rc_s, pos, flat, H, G, rcut, j0, power)
     assert np.allclose(j.detach().cpu().numpy(), j_o, rtol=1e-11, atol=1e-11)
     assert np.allclose(e.detach().cpu().numpy(), e_o, rtol=1e-9, atol=1e-9)
-    assert float(var) == pytest.approx(var_o, rel=1e-8)
+    assert float(var.detach()) == pytest.approx(var_o, rel=1e-8)
     rng = np.random.default_rng(3)
     idx = list(np.ndindex(*flat.shape))
     idx = [idx[i] for i in rng.choice(len(idx), 24, replace=False)] + [(0, 3 * H + H * H), (1, 4 * H + H * H)]
