@@ -98,3 +98,26 @@ def test_large_systems_sampled_parity(name, W):
     gpu.set_walkers(pos, 0)
     _check_generation(gpu, orc, pos, 0, [0, W // 2, W - 1])
     gpu.close()
+
+
+@pytest.mark.parametrize("name,W", [("zsweep54", 32), ("molecule", 16)])
+def test_large_systems_deep_in_the_run(name, W):
+    """Generations 10 and 11 of the large systems (orbital-projected inverse
+    in device memory; compacted table for Z = 54): state carried by
+    Sherman-Morrison updates since the refresh at generation 8, sampled
+    slots against the oracle from the same positions."""
+    from paper_1909_01589_amd.lrdmc import LRDMC
+    cfg = inputs.get_config(name)
+    s = cfg.system
+    rc, ap, _ = spacing.spacing(s.z_max, cfg.a)
+    assert cfg.refresh == 8
+    gpu = LRDMC(s, cfg.a, ap, rc, cfg.tau, W, seed=cfg.seed, rotate=1, refresh=cfg.refresh)
+    orc = oracle.Oracle(s, cfg.a, ap, rc, tau=cfg.tau, seed=cfg.seed, rotate=1)
+    gpu.set_walkers(inputs.initial_walkers(s, W, 2), 0)
+    gpu.run(10)
+    for gen in (10, 11):
+        start = gpu.get_walkers()["pos"].cpu().numpy()
+        _check_generation(gpu, orc, start, gen, [1, W - 1])
+        gpu.branch()
+    gpu.close()
+
