@@ -525,6 +525,64 @@ def zscan_phys(walkers=8192, gens=100, warmup=20, moves_per_electron=2.0, seed=0
                            "paper_cpu_time_alpha_3.5": {"Be": 1.4, "Ne": 2.3, "Ar": 3.3}}}
 
 
+def mixed_bench(walkers=16384, gens=1200, seed=0):
+    """FP64 against the mixed-precision move table (lrdmc_set_precision 1):
+    throughput on the benchmark workload (same kernel otherwise), and on two
+    physical trial functions (helium with a nodeless orbital, fixed node
+    exact; Ar with screened hydrogenic orbitals) the energy, its reblocked
+    error over `gens` generations after equilibration from the same walkers,
+    and the time to sigma(E) = 1 mHa, both as measured and from the pooled
+    variance per unit projection time of the two runs (the same process up to
+    rounding of the transition probabilities, so the pooled figure isolates
+    the speed)."""
+    import torch
+    from paper_1909_01589_amd import inputs, stats
+    from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_set_precision, lrdmc_spacing
+    out = {"throughput": {}, "systems": []}
+    for p in (0, 1):
+        cfg, r = run_workload("ar_a0.1", 1000, 100, False, 0.0, precision=p)
+        out["throughput"]["fp64" if p == 0 else "mixed"] = dict(value=r["value"], ms_per_step=r["ms_per_step"],
+                                                                 frac=r["roofline"]["frac"])
+        print(f"[mixed] ar_a0.1 precision={p}: {r['value'] / 1e6:.2f} M electron-moves/s", file=sys.stderr, flush=True)
+    for label, s, a, step, mpe, t_equil in (("He nodeless", inputs.helium_nodeless(), 0.1, 0.6, 20.0, 10.0),
+                                             ("Ar screened", inputs.ar_screened(), 0.035, 0.25, 8.0, 2.0)):
+        rc, ap, _ = lrdmc_spacing(s.z_max, a)
+        ap = max(ap, a)
+        g = LRDMC(s, a, ap, rc, 1.0, walkers, seed=seed + 11, rotate=1, refresh=8)
+        g.set_walkers(inputs.initial_walkers(s, walkers, seed), 0)
+        g.vmc(2000, step)
+        pos = g.get_walkers()["pos"].clone()
+        delta = float(g.eval_moves(pos)[2][:, 6].mean())
+        g.close()
+        tau = mpe * s.n_elec / delta
+        rows = {}
+        for p in (0, 1):
+            g = LRDMC(s, a, ap, rc, tau, walkers, seed=seed + 11, rotate=1, refresh=8)
+            lrdmc_set_precision(g.ctx, p)
+            g.set_walkers(pos, 0)
+            g.run(int(t_equil / tau) + 20)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rec = g.run(gens)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            E, sig = stats.estimate(rec["log_wbar"].cpu().numpy(), rec["ebar"].cpu().numpy(), p=None)
+            rows["fp64" if p == 0 else "mixed"] = dict(
+                E=E, sigma=sig, wall_s=wall, moves_per_s=float(rec["n_moves"].sum()) / wall,
+                time_to_1mHa_s=wall * (sig / 1e-3) ** 2)
+            g.close()
+            print(f"[mixed] {label} precision={p}: E={E:.5f} +- {sig:.5f}, {wall:.1f} s", file=sys.stderr, flush=True)
+        f, m = rows["fp64"], rows["mixed"]
+        pooled = 0.5 * (f["sigma"] ** 2 + m["sigma"] ** 2) / 1e-6
+        out["systems"].append(dict(
+            system=label, a=a, a_prime=ap, tau=tau, walkers=walkers, generations=gens, runs=rows,
+            energy_difference=m["E"] - f["E"], energy_difference_sigma=float(np.hypot(f["sigma"], m["sigma"])),
+            speed_ratio=f["wall_s"] / m["wall_s"],
+            time_to_1mHa_ratio_measured=f["time_to_1mHa_s"] / m["time_to_1mHa_s"],
+            time_to_1mHa_pooled_s={"fp64": f["wall_s"] * pooled, "mixed": m["wall_s"] * pooled}))
+    return {"mixed_precision": out}
+
+
 def sweep():
     """Throughput of every configured workload (generations, warm-up) as in
     the benchmark line: electron-moves/s, ms per generation, the kernel's
@@ -585,16 +643,18 @@ def cpu_baseline(system, a, ap, rc, tau, seed, pos, gen0, seconds, threads=None)
                       f"{moves} moves in {dt:.1f} s"}
 
 
-def run_workload(name, steps, warmup, want_cpu, cpu_seconds):
+def run_workload(name, steps, warmup, want_cpu, cpu_seconds, precision=0):
     import torch
     from paper_1909_01589_amd import inputs, stats, workcount
-    from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_set_timing, lrdmc_spacing, lrdmc_timing
+    from paper_1909_01589_amd.lrdmc import (LRDMC, lrdmc_set_precision, lrdmc_set_timing, lrdmc_spacing,
+                                            lrdmc_timing)
 
     cfg = inputs.get_config(name)
     s = cfg.system
     rc, ap, nc = lrdmc_spacing(s.z_max, cfg.a)
     W = cfg.walkers
     gpu = LRDMC(s, cfg.a, ap, rc, cfg.tau, W, seed=cfg.seed, rotate=cfg.rotate, refresh=cfg.refresh)
+    lrdmc_set_precision(gpu.ctx, precision)
     gpu.set_walkers(inputs.initial_walkers(s, W, cfg.seed), 0)
     if warmup:
         gpu.run(warmup)
@@ -665,6 +725,8 @@ def main():
                     help="only run the learned-Jastrow comparison (VMC, training, LRDMC scan) and exit")
     ap.add_argument("--sweep", action="store_true",
                     help="only time every configured workload (Be-like, Ar-like, Z-sweep, molecule) and exit")
+    ap.add_argument("--mixed", action="store_true",
+                    help="FP64 against the mixed-precision move table: throughput, energies, time to 1 mHa")
     ap.add_argument("--zscan-phys", action="store_true",
                     help="only run the single/double-grid comparison for Ne and Ar with screened orbitals and exit")
     ap.add_argument("--zscan", action="store_true",
@@ -694,6 +756,9 @@ def main():
         return
     if args.sweep:
         print(json.dumps(sweep()), flush=True)
+        return
+    if args.mixed:
+        print(json.dumps(mixed_bench()), flush=True)
         return
     if args.zscan_phys:
         print(json.dumps(zscan_phys()), flush=True)

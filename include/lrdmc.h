@@ -317,6 +317,18 @@ int lrdmc_net_tabulate_backward(const double *params, int32_t hidden, int32_t n_
 int lrdmc_use_generic(lrdmc_ctx *ctx, int32_t enable);
 int32_t lrdmc_is_specialized(const lrdmc_ctx *ctx);
 
+/* Arithmetic of the move table for later projections and evaluations.
+ * mode 0 (default): FP64 throughout.  mode 1 (mixed precision): in the
+ * ratios Psi(x')/Psi(x) of the table (S5 of the projection), the Jastrow pair
+ * terms take 1/r and 1/(1/r + b) from the FP32 hardware estimates (relative
+ * error about 2^-22 each) while distances, sums and everything else stay
+ * FP64; the local energy, the weights, the Sherman-Morrison updates and the
+ * reconfiguration are unchanged.  The ratios then differ from FP64 by about
+ * 1e-7 relative (below 1e-5 for any configuration), so move indices agree
+ * with the FP64 path only until such a difference decides one; energies agree
+ * statistically.  Errors: LRDMC_EINVAL (NULL, mode outside 0..1). */
+int lrdmc_set_precision(lrdmc_ctx *ctx, int32_t mode);
+
 /* Generation counter of the next projection. */
 uint64_t lrdmc_generation(const lrdmc_ctx *ctx);
 

@@ -532,17 +532,31 @@ __device__ __forceinline__ void corr_eval(const KArgs &A, int type, double r, do
 // (s = 1 for electron pairs, Z for an electron and a nucleus, 0 drops the
 // pair).  The two denominators share one reciprocal: the hardware estimate
 // of 1 / (d_a d_b) with one Newton-Raphson step, times the other factor.
-template <bool CORR>
+template <bool CORR, bool MX = false>
 __device__ __forceinline__ void pair_u2(const KArgs &A, double c, double b, double d2a, double d2b, int type,
                                         double s, double &ua, double &ub)
 {
-    const double ya = rsqrt_move(d2a), yb = rsqrt_move(d2b);
-    const double da = ya + b, db = yb + b, p = da * db;
-    double x = __builtin_amdgcn_rcp(p);
-    x = fma(x, fma(-p, x, 1.0), x);
-    const double cx = c * x;
-    ua = cx * db;
-    ub = cx * da;
+    double ya, yb;
+    if constexpr (MX) {
+        // mixed precision: 1/r and the shared reciprocal from the FP32
+        // hardware estimates (relative error about 2^-22 each), sums in FP64
+        const float fa = __builtin_amdgcn_rsqf((float)d2a), fb = __builtin_amdgcn_rsqf((float)d2b);
+        const float da = fa + (float)b, db = fb + (float)b;
+        const float x = __builtin_amdgcn_rcpf(da * db);
+        ua = c * (double)(x * db);
+        ub = c * (double)(x * da);
+        ya = fa;
+        yb = fb;
+    } else {
+        ya = rsqrt_move(d2a);
+        yb = rsqrt_move(d2b);
+        const double da = ya + b, db = yb + b, p = da * db;
+        double x = __builtin_amdgcn_rcp(p);
+        x = fma(x, fma(-p, x, 1.0), x);
+        const double cx = c * x;
+        ua = cx * db;
+        ub = cx * da;
+    }
     if constexpr (CORR) {
         double F[3];
         corr_eval<0>(A, type, d2a * ya, F);
@@ -555,18 +569,32 @@ __device__ __forceinline__ void pair_u2(const KArgs &A, double c, double b, doub
 // The same for two electron pairs (coefficients c0, c1, correction scales
 // s0, s1) at both points: ua, ub are the sums over both pairs, and the four
 // denominators share one reciprocal.
-template <bool CORR>
+template <bool CORR, bool MX = false>
 __device__ __forceinline__ void pair_u4(const KArgs &A, double c0, double c1, double b, double qa0, double qb0,
                                         double qa1, double qb1, double s0, double s1, double &ua, double &ub)
 {
-    const double ya0 = rsqrt_move(qa0), yb0 = rsqrt_move(qb0), ya1 = rsqrt_move(qa1), yb1 = rsqrt_move(qb1);
-    const double da0 = ya0 + b, db0 = yb0 + b, da1 = ya1 + b, db1 = yb1 + b;
-    const double p0 = da0 * db0, p1 = da1 * db1, p = p0 * p1;
-    double x = __builtin_amdgcn_rcp(p);
-    x = fma(x, fma(-p, x, 1.0), x);
-    const double x0 = c0 * (x * p1), x1 = c1 * (x * p0);
-    ua = fma(x0, db0, x1 * db1);
-    ub = fma(x0, da0, x1 * da1);
+    double ya0, yb0, ya1, yb1;
+    if constexpr (MX) {
+        const float fb = (float)b;
+        const float fa0 = __builtin_amdgcn_rsqf((float)qa0), fb0 = __builtin_amdgcn_rsqf((float)qb0);
+        const float fa1 = __builtin_amdgcn_rsqf((float)qa1), fb1 = __builtin_amdgcn_rsqf((float)qb1);
+        const float da0 = fa0 + fb, db0 = fb0 + fb, da1 = fa1 + fb, db1 = fb1 + fb;
+        const float p0 = da0 * db0, p1 = da1 * db1;
+        const float x = __builtin_amdgcn_rcpf(p0 * p1);
+        const float x0 = x * p1, x1 = x * p0;
+        ua = c0 * (double)(x0 * db0) + c1 * (double)(x1 * db1);
+        ub = c0 * (double)(x0 * da0) + c1 * (double)(x1 * da1);
+        ya0 = fa0; yb0 = fb0; ya1 = fa1; yb1 = fb1;
+    } else {
+        ya0 = rsqrt_move(qa0); yb0 = rsqrt_move(qb0); ya1 = rsqrt_move(qa1); yb1 = rsqrt_move(qb1);
+        const double da0 = ya0 + b, db0 = yb0 + b, da1 = ya1 + b, db1 = yb1 + b;
+        const double p0 = da0 * db0, p1 = da1 * db1, p = p0 * p1;
+        double x = __builtin_amdgcn_rcp(p);
+        x = fma(x, fma(-p, x, 1.0), x);
+        const double x0 = c0 * (x * p1), x1 = c1 * (x * p0);
+        ua = fma(x0, db0, x1 * db1);
+        ub = fma(x0, da0, x1 * da1);
+    }
     if constexpr (CORR) {
         double F[3];
         corr_eval<0>(A, 0, qa0 * ya0, F);
@@ -597,7 +625,7 @@ __device__ __forceinline__ PairD pair_d(const KArgs &A, double c, double b, doub
 
 // Jastrow terms containing electron i when it sits at ra and at rb (the two
 // points of a +/- move pair; the other electrons fixed).
-template <bool CORR>
+template <bool CORR, bool MX = false>
 __device__ __forceinline__ void jastrow_point2(const KArgs &A, const double *pos, int i, const double ra[3],
                                                const double rb[3], double &out_a, double &out_b)
 {
@@ -619,7 +647,7 @@ __device__ __forceinline__ void jastrow_point2(const KArgs &A, const double *pos
         dx = rb[0] - x1; dy = rb[1] - y1; dz = rb[2] - z1;
         const double qb1 = dx * dx + dy * dy + dz * dz;
         double ua, ub;
-        pair_u4<CORR>(A, c0, c1, A.b_ee, qa0, qb0, qa1, qb1, s0, s1, ua, ub);
+        pair_u4<CORR, MX>(A, c0, c1, A.b_ee, qa0, qb0, qa1, qb1, s0, s1, ua, ub);
         a0 += ua;
         b0 += ub;
     }
@@ -632,7 +660,7 @@ __device__ __forceinline__ void jastrow_point2(const KArgs &A, const double *pos
         dx = rb[0] - x0; dy = rb[1] - y0; dz = rb[2] - z0;
         const double qb0 = dx * dx + dy * dy + dz * dz;
         double ua, ub;
-        pair_u2<CORR>(A, c0, A.b_ee, qa0, qb0, 0, s0, ua, ub);
+        pair_u2<CORR, MX>(A, c0, A.b_ee, qa0, qb0, 0, s0, ua, ub);
         a0 += ua;
         b0 += ub;
     }
@@ -644,7 +672,7 @@ __device__ __forceinline__ void jastrow_point2(const KArgs &A, const double *pos
         dx = rb[0] - R[0]; dy = rb[1] - R[1]; dz = rb[2] - R[2];
         const double qb = dx * dx + dy * dy + dz * dz;
         double ua, ub;
-        pair_u2<CORR>(A, c, A.b_en, qa, qb, 1, -c, ua, ub);
+        pair_u2<CORR, MX>(A, c, A.b_en, qa, qb, 1, -c, ua, ub);
         a1 += ua;
         b1 += ub;
     }
@@ -907,7 +935,7 @@ constexpr double kPDrop = 0x1p-52;
 // weights of its own contiguous chunk [c0, c1) in move order, so the search
 // sees exactly the sums of the full table.  The list lives in the prefix-sum
 // scratch, which is written only after the last barrier here.
-template <bool CORR, bool YG>
+template <bool CORR, bool YG, bool MX = false>
 __device__ __forceinline__ double move_table_compact(const KArgs &A, double *lds, const double *Rm, int c0,
                                                      int c1, int *last)
 {
@@ -988,7 +1016,7 @@ __device__ __forceinline__ double move_table_compact(const KArgs &A, double *lds
         }
         double rda, rdb, ja, jb;
         basis_dot2(A, ra, rb, Y + i * A.Kp, rda, rdb);
-        jastrow_point2<CORR>(A, pos, i, ra, rb, ja, jb);
+        jastrow_point2<CORR, MX>(A, pos, i, ra, rb, ja, jb);
         const double jo = Jo[i];
         const double rhoa = rda * exp(ja - jo), rhob = rdb * exp(jb - jo);
         T[m] = da ? 0.0 : 0.5 * ka * (rhoa > 0.0 ? rhoa : 0.0);
@@ -1008,13 +1036,13 @@ __device__ __forceinline__ double move_table_compact(const KArgs &A, double *lds
 // each step evaluates the +/- pair (m, m + 1) along one axis of one grid of
 // one electron.  Returns the sum of the weights; with diag, stores rho and k
 // and accumulates sum k, L^a and V_sf.
-template <bool CORR, bool YG>
+template <bool CORR, bool YG, bool MX = false>
 __device__ __forceinline__ double move_table(const KArgs &A, double *lds, const double *Rm, int c0, int c1,
                                              int *last, double *rho_g, double *k_g, double acc[3], bool diag)
 {
     if constexpr (YG) {
         // compaction pays when it saves a second round of pairs per thread
-        if (!diag && A.M / 2 > A.nt) return move_table_compact<CORR, YG>(A, lds, Rm, c0, c1, last);
+        if (!diag && A.M / 2 > A.nt) return move_table_compact<CORR, YG, MX>(A, lds, Rm, c0, c1, last);
     }
     const Layout &L = A.L;
     const double *pos = lds + L.pos, *Y = y_base<YG>(A, lds), *Jo = lds + L.Jo;
@@ -1043,7 +1071,7 @@ __device__ __forceinline__ double move_table(const KArgs &A, double *lds, const 
         }
         double rda, rdb, ja, jb;
         basis_dot2(A, ra, rb, Y + i * A.Kp, rda, rdb);
-        jastrow_point2<CORR>(A, pos, i, ra, rb, ja, jb);
+        jastrow_point2<CORR, MX>(A, pos, i, ra, rb, ja, jb);
         const double jo = Jo[i];
         const double rhoa = rda * exp(ja - jo), rhob = rdb * exp(jb - jo);
         const double ta = da ? 0.0 : 0.5 * ka * (rhoa > 0.0 ? rhoa : 0.0);
@@ -1260,7 +1288,7 @@ __device__ __forceinline__ double local_energy(const KArgs &A, const double *lds
 
 // One workgroup per walker slot: a generation of continuous-time projection,
 // or (eval != 0) the move table at frozen positions.
-template <bool CORR, bool YG>
+template <bool CORR, bool YG, bool MX = false>
 __device__ __forceinline__ void project_body(const KArgs &A)
 {
     extern __shared__ double lds[];
@@ -1321,7 +1349,7 @@ __device__ __forceinline__ void project_body(const KArgs &A)
     if (A.eval) {
         double acc[3] = {0.0, 0.0, 0.0};
         int last = -1;
-        const double part = move_table<CORR, YG>(A, lds, rng_slot(rng, 0), c0, c1, &last,
+        const double part = move_table<CORR, YG, MX>(A, lds, rng_slot(rng, 0), c0, c1, &last,
                                        A.rho_out ? A.rho_out + (size_t)slot * M : nullptr,
                                        A.k_out ? A.k_out + (size_t)slot * M : nullptr, acc, true);
         double v[4] = {acc[0], acc[1], acc[2], part};
@@ -1348,7 +1376,7 @@ __device__ __forceinline__ void project_body(const KArgs &A)
         const double *R = rng_slot(rng, it);
         int last = -1;
         double dummy[3];
-        const double part = move_table<CORR, YG>(A, lds, R, c0, c1, &last, nullptr, nullptr, dummy, false);
+        const double part = move_table<CORR, YG, MX>(A, lds, R, c0, c1, &last, nullptr, nullptr, dummy, false);
 
         // inclusive prefix of the per-thread sums within each wavefront; the
         // wavefront totals go to LDS
@@ -1470,6 +1498,13 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
     project_body<CORR, YG>(A);
 }
 
+// The same with the move table's Jastrow pair terms in mixed precision.
+template <bool CORR, bool YG>
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4))) project_kernel_mx(KArgs A)
+{
+    project_body<CORR, YG, true>(A);
+}
+
 // The same kernel built for one system size: electron counts, basis size and
 // nucleus count (hence thread count and every LDS offset) are compile-time
 // constants, so loops over electrons and basis functions have fixed trip
@@ -1490,6 +1525,17 @@ project_kernel_fixed(KArgs A)
     A.N = S::N; A.n_up = NUP; A.n_dn = NDN; A.ns = S::ns; A.K = KB; A.Kp = S::Kp; A.M = S::M;
     A.n_nuc = NNUC; A.nt = S::NT; A.mpe = 12; A.L = L;
     project_body<CORR, false>(A);
+}
+
+template <int NUP, int NDN, int KB, int NNUC, bool CORR>
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4)))
+project_kernel_fixed_mx(KArgs A)
+{
+    using S = FixedShape<NUP, NDN, KB, NNUC>;
+    constexpr Layout L = make_layout(S::N, S::ns, KB, S::Kp, S::M, NNUC, S::NT, 0);
+    A.N = S::N; A.n_up = NUP; A.n_dn = NDN; A.ns = S::ns; A.K = KB; A.Kp = S::Kp; A.M = S::M;
+    A.n_nuc = NNUC; A.nt = S::NT; A.mpe = 12; A.L = L;
+    project_body<CORR, false, true>(A);
 }
 
 // Derivatives with respect to the Pade parameters theta = (b_ee, b_en) of
@@ -2103,13 +2149,15 @@ std::string g_error;  // last failure without a context
 // molecule with 256 functions the fully unrolled kernel spills registers and
 // runs slower than the general one, so it is left out.
 #define LRDMC_SHAPE(u, d, k, z) \
-    {u, d, k, z, {(const void *)project_kernel_fixed<u, d, k, z, false>, (const void *)project_kernel_fixed<u, d, k, z, true>}},
+    {u, d, k, z, {(const void *)project_kernel_fixed<u, d, k, z, false>, (const void *)project_kernel_fixed<u, d, k, z, true>}, \
+     {(const void *)project_kernel_fixed_mx<u, d, k, z, false>, (const void *)project_kernel_fixed_mx<u, d, k, z, true>}},
 #ifndef LRDMC_FIXED_SHAPES
 #define LRDMC_FIXED_SHAPES LRDMC_SHAPE(9, 9, 64, 1) LRDMC_SHAPE(2, 2, 8, 1)
 #endif
 struct FixedKernel {
     int n_up, n_dn, K, n_nuc;
-    const void *fn[2];   // without, with the learned correction
+    const void *fn[2];      // without, with the learned correction
+    const void *fn_mx[2];   // the same in mixed precision
 };
 const FixedKernel kFixedKernels[] = {LRDMC_FIXED_SHAPES};
 
@@ -2137,6 +2185,8 @@ struct lrdmc_ctx {
     size_t lds_bytes = 0;
     Layout L{};
     const void *fixed_fn[2] = {nullptr, nullptr};  // kernels built for this system's sizes, if any
+    const void *fixed_fn_mx[2] = {nullptr, nullptr};
+    int precision = 0;   // 0 FP64; 1 mixed precision in the move table's Jastrow pair terms
     // LDS layouts with Y in LDS and with Y in the HBM state blob (same blob
     // format); the second is taken automatically when the first would leave
     // fewer than four walkers per CU
@@ -2186,6 +2236,12 @@ bool use_fixed(const lrdmc_ctx *c) { return c->kmode == 0 && !c->L.yg && c->fixe
 
 const void *project_fn(const lrdmc_ctx *c)
 {
+    if (c->precision == 1) {
+        if (use_fixed(c) && c->fixed_fn_mx[c->corr]) return c->fixed_fn_mx[c->corr];
+        const void *f[4] = {(const void *)project_kernel_mx<false, false>, (const void *)project_kernel_mx<false, true>,
+                            (const void *)project_kernel_mx<true, false>, (const void *)project_kernel_mx<true, true>};
+        return f[2 * (int)c->corr + c->L.yg];
+    }
     if (use_fixed(c)) return c->fixed_fn[c->corr];
     const void *f[4] = {(const void *)project_kernel<false, false>, (const void *)project_kernel<false, true>,
                         (const void *)project_kernel<true, false>, (const void *)project_kernel<true, true>};
@@ -2576,6 +2632,8 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
         if (!c->yg_auto && std::memcmp(&Lf, &c->L_lds, sizeof(Layout)) == 0) {
             c->fixed_fn[0] = F.fn[0];
             c->fixed_fn[1] = F.fn[1];
+            c->fixed_fn_mx[0] = F.fn_mx[0];
+            c->fixed_fn_mx[1] = F.fn_mx[1];
         }
     }
     // state blob: Y [N][Kp], the LDS part [Ainv, Jo + N), E_L, V, derivative rows
@@ -2600,7 +2658,9 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
             for (const void *fn :
                  {(const void *)project_kernel<false, false>, (const void *)project_kernel<false, true>,
                   (const void *)project_kernel<true, false>, (const void *)project_kernel<true, true>, c->fixed_fn[0],
-                  c->fixed_fn[1], (const void *)jastrow_grad_kernel<false, false>,
+                  c->fixed_fn[1], (const void *)project_kernel_mx<false, false>, (const void *)project_kernel_mx<false, true>,
+                  (const void *)project_kernel_mx<true, false>, (const void *)project_kernel_mx<true, true>,
+                  c->fixed_fn_mx[0], c->fixed_fn_mx[1], (const void *)jastrow_grad_kernel<false, false>,
                   (const void *)jastrow_grad_kernel<false, true>, (const void *)jastrow_grad_kernel<true, false>,
                   (const void *)jastrow_grad_kernel<true, true>, (const void *)jastrow_table_grad_kernel<false>,
                   (const void *)jastrow_table_grad_kernel<true>, (const void *)vmc_kernel<false, false>,
@@ -2942,6 +3002,14 @@ int lrdmc_use_generic(lrdmc_ctx *c, int32_t enable)
     if (enable < 0 || enable > 2) return fail(c, LRDMC_EINVAL, "lrdmc_use_generic: mode must be 0, 1 or 2");
     c->kmode = enable;
     apply_kernel_mode(c);   // the state blob format is the same for every mode
+    return LRDMC_OK;
+}
+
+int lrdmc_set_precision(lrdmc_ctx *c, int32_t mode)
+{
+    if (!c) return fail(nullptr, LRDMC_EINVAL, "lrdmc_set_precision: NULL context");
+    if (mode < 0 || mode > 1) return fail(c, LRDMC_EINVAL, "lrdmc_set_precision: mode must be 0 or 1");
+    c->precision = mode;
     return LRDMC_OK;
 }
 

@@ -57,7 +57,8 @@ EXPORTS = ("lrdmc_spacing", "lrdmc_spacing_pade", "lrdmc_create", "lrdmc_set_wal
            "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure",
            "lrdmc_jastrow_grad", "lrdmc_set_jastrow", "lrdmc_set_jastrow_table", "lrdmc_jastrow_table_grad",
            "lrdmc_vmc", "lrdmc_net_param_count", "lrdmc_net_workspace_size", "lrdmc_net_tabulate", "lrdmc_net_tabulate_backward",
-           "lrdmc_use_generic", "lrdmc_is_specialized", "lrdmc_set_timing", "lrdmc_timing", "lrdmc_generation",
+           "lrdmc_use_generic", "lrdmc_is_specialized", "lrdmc_set_precision", "lrdmc_set_timing", "lrdmc_timing",
+           "lrdmc_generation",
            "lrdmc_last_error", "lrdmc_destroy")
 
 
@@ -92,6 +93,7 @@ def load():
     lib.lrdmc_net_tabulate.argtypes = [P, I32, I32, D, P, P]
     lib.lrdmc_net_tabulate_backward.argtypes = [P, I32, I32, D, P, P, P, P]
     lib.lrdmc_use_generic.argtypes = [P, I32]
+    lib.lrdmc_set_precision.argtypes = [P, I32]
     lib.lrdmc_is_specialized.argtypes = [P]
     lib.lrdmc_is_specialized.restype = I32
     lib.lrdmc_set_timing.argtypes = [P, I32]
@@ -106,7 +108,7 @@ def load():
                  "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure",
                  "lrdmc_jastrow_grad", "lrdmc_set_jastrow", "lrdmc_set_jastrow_table",
                  "lrdmc_jastrow_table_grad", "lrdmc_vmc", "lrdmc_net_tabulate", "lrdmc_net_tabulate_backward",
-                 "lrdmc_use_generic", "lrdmc_set_timing",
+                 "lrdmc_use_generic", "lrdmc_set_precision", "lrdmc_set_timing",
                  "lrdmc_timing"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -283,6 +285,12 @@ def lrdmc_use_generic(ctx, enable=True):
     """0/False automatic, 1/True the general kernel, 2 the general kernel with
     the orbital-projected inverse in device memory."""
     _check(load().lrdmc_use_generic(ctx, int(enable)), ctx)
+
+
+def lrdmc_set_precision(ctx, mode: int):
+    """0 FP64 move table; 1 mixed precision (FP32 estimates of 1/r and of the
+    Pade denominators' reciprocal in the table's Jastrow pair terms)."""
+    _check(load().lrdmc_set_precision(ctx, int(mode)), ctx)
 
 
 def lrdmc_is_specialized(ctx) -> bool:

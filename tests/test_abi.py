@@ -136,4 +136,5 @@ def test_context_entry_points_reject_null(lib):
     assert lib.lrdmc_jastrow_grad(None, dummy, dummy, None) == -1
     assert lib.lrdmc_set_jastrow(None, 1.0, 1.0) == -1
     assert lib.lrdmc_use_generic(None, 0) == -1
+    assert lib.lrdmc_set_precision(None, 1) == -1
     assert lib.lrdmc_is_specialized(None) == 0
