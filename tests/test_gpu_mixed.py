@@ -110,3 +110,27 @@ def test_mixed_projection_energies_agree_with_fp64():
     assert abs(e1 - e0) < 3.5 * np.hypot(s0, s1)
     for e, sg in ((e0, s0), (e1, s1)):
         assert abs(e - HE_EXACT) < 4.0 * sg + 1e-3
+
+
+@pytest.mark.parametrize("name,W", [("zsweep54", 2), ("molecule", 2)])
+def test_mixed_ratios_large_systems(name, W):
+    """The same bound for the kernels with the orbital-projected inverse in
+    device memory: the Z = 54 atom and the molecule (twelve nuclei, each
+    electron-nucleus term in the two-point form of the shared reciprocal)."""
+    from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_set_precision
+    cfg = inputs.get_config(name)
+    s = cfg.system
+    rc, ap, _ = spacing.spacing(s.z_max, cfg.a)
+    gpu = LRDMC(s, cfg.a, ap, rc, cfg.tau, W, seed=4, rotate=1, refresh=8)
+    lrdmc_set_precision(gpu.ctx, 1)
+    pos = inputs.initial_walkers(s, W, 5)
+    rho, k, diag = (x.cpu().numpy() for x in gpu.eval_moves(pos))
+    gpu.close()
+    orc = oracle.Oracle(s, cfg.a, ap, rc, tau=cfg.tau, seed=4, rotate=1)
+    dJ = _jastrow_bound(s)
+    for w in range(W):
+        print(f"mixed precision large case={name} walker={w}", flush=True)
+        r_o, k_o, d_o = orc.eval_moves(pos[w], orc.move_rotation(w, 0, 0))
+        scale = np.max(np.abs(r_o))
+        assert np.all(np.abs(rho[w] - r_o) <= 1e-9 * (np.abs(r_o) + scale) + np.expm1(dJ) * np.abs(r_o))
+        assert abs(diag[w, 0] - d_o["e_l"]) <= 1e-9 * (1 + abs(d_o["e_l"]) + abs(d_o["lap_exact"]))
