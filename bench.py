@@ -716,6 +716,7 @@ def main():
     ap.add_argument("--second", default="ar_a0.2", help="second workload line ('' to skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision line of the benchmark")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device copy (counter calibration) and exit")
     ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
@@ -778,6 +779,9 @@ def main():
     second = None
     if args.second:
         _, second = run_workload(args.second, args.steps, args.warmup, False, 0.0)
+    mixed = None
+    if not args.no_mixed:
+        _, mixed = run_workload(args.workload, args.steps, args.warmup, False, 0.0, precision=1)
 
     s = cfg.system
     line = {
@@ -804,6 +808,11 @@ def main():
     }
     if "cpu_baseline" in main_res:
         line["cpu_baseline"] = main_res["cpu_baseline"]
+    if mixed is not None:
+        line["mixed_precision_table"] = {
+            "value": mixed["value"], "ms_per_step": mixed["ms_per_step"], "dtype": "f64 with f32 Jastrow estimates",
+            "speedup": mixed["value"] / main_res["value"],
+            "note": "lrdmc_set_precision 1: same workload and steps; ratios within a derived 2.3e-5 of FP64"}
     if second is not None:
         line["second_workload"] = {
             "workload": args.second, "value": second["value"], "ms_per_step": second["ms_per_step"],
