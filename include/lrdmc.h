@@ -324,9 +324,11 @@ int32_t lrdmc_is_specialized(const lrdmc_ctx *ctx);
  * error about 2^-22 each) while distances, sums and everything else stay
  * FP64; the local energy, the weights, the Sherman-Morrison updates and the
  * reconfiguration are unchanged.  The ratios then differ from FP64 by about
- * 1e-7 relative (below 1e-5 for any configuration), so move indices agree
- * with the FP64 path only until such a difference decides one; energies agree
- * statistically.  Errors: LRDMC_EINVAL (NULL, mode outside 0..1). */
+ * 1e-7 relative and at most by the factor exp(dJ),
+ * dJ = 2^-20 (sum_j c_ij / b_ee + sum_I Z_I / b_en) (2.3e-5 for the 18-electron
+ * atom of the benchmark), so move indices agree with the FP64 path only until
+ * such a difference decides one; energies agree statistically.  Errors:
+ * LRDMC_EINVAL (NULL, mode outside 0..1). */
 int lrdmc_set_precision(lrdmc_ctx *ctx, int32_t mode);
 
 /* Generation counter of the next projection. */
