@@ -534,7 +534,8 @@ def mixed_bench(walkers=16384, gens=1200, seed=0):
     and the time to sigma(E) = 1 mHa, both as measured and from the pooled
     variance per unit projection time of the two runs (the same process up to
     rounding of the transition probabilities, so the pooled figure isolates
-    the speed)."""
+    the speed); last, the throughput of both tables on the screened Ar atom
+    with and without a learned-correction table."""
     import torch
     from paper_1909_01589_amd import inputs, stats
     from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_set_precision, lrdmc_spacing
@@ -580,6 +581,32 @@ def mixed_bench(walkers=16384, gens=1200, seed=0):
             speed_ratio=f["wall_s"] / m["wall_s"],
             time_to_1mHa_ratio_measured=f["time_to_1mHa_s"] / m["time_to_1mHa_s"],
             time_to_1mHa_pooled_s={"fp64": f["wall_s"] * pooled, "mixed": m["wall_s"] * pooled}))
+    # throughput with and without a learned-correction table on the screened Ar atom
+    s = inputs.ar_screened()
+    a, tau = 0.05, 0.02
+    rc, ap, _ = lrdmc_spacing(s.z_max, a)
+    ap = max(ap, a)
+    pos0 = inputs.initial_walkers(s, walkers, seed)
+    tab = inputs.jastrow_table(seed=1, n_nodes=257, r_cut=6.0, scale=0.05)
+    out["correction"] = []
+    for table in (False, True):
+        row = dict(table=table, a=a, tau=tau, walkers=walkers)
+        for p in (0, 1):
+            g = LRDMC(s, a, ap, rc, tau, walkers, seed=1, rotate=1, refresh=8)
+            if table:
+                g.set_jastrow_table(tab, 6.0)
+            lrdmc_set_precision(g.ctx, p)
+            g.set_walkers(pos0, 0)
+            g.run(40)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rec = g.run(60)
+            torch.cuda.synchronize()
+            row["fp64" if p == 0 else "mixed"] = float(rec["n_moves"].sum()) / (time.perf_counter() - t0)
+            g.close()
+        print(f"[mixed] screened Ar table={table}: {row['fp64'] / 1e6:.1f} -> {row['mixed'] / 1e6:.1f} M electron-moves/s",
+              file=sys.stderr, flush=True)
+        out["correction"].append(row)
     return {"mixed_precision": out}
 
 
