@@ -545,6 +545,11 @@ def mixed_bench(walkers=16384, gens=1200, seed=0):
         out["throughput"]["fp64" if p == 0 else "mixed"] = dict(value=r["value"], ms_per_step=r["ms_per_step"],
                                                                  frac=r["roofline"]["frac"])
         print(f"[mixed] ar_a0.1 precision={p}: {r['value'] / 1e6:.2f} M electron-moves/s", file=sys.stderr, flush=True)
+    out["throughput_z54"] = {}
+    for p in (0, 1):
+        cfg, r = run_workload("zsweep54", 20, 5, False, 0.0, precision=p)
+        out["throughput_z54"]["fp64" if p == 0 else "mixed"] = dict(value=r["value"], ms_per_step=r["ms_per_step"])
+        print(f"[mixed] zsweep54 precision={p}: {r['value'] / 1e6:.2f} M electron-moves/s", file=sys.stderr, flush=True)
     for label, s, a, step, mpe, t_equil in (("He nodeless", inputs.helium_nodeless(), 0.1, 0.6, 20.0, 10.0),
                                              ("Ar screened", inputs.ar_screened(), 0.035, 0.25, 8.0, 2.0)):
         rc, ap, _ = lrdmc_spacing(s.z_max, a)
