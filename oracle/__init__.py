@@ -100,14 +100,18 @@ def load():
         lib.orc_eval_moves.restype = C.c_int
         lib.orc_select.argtypes = [P, C.c_int, C.c_double]
         lib.orc_select.restype = C.c_int
-        lib.orc_generation.argtypes = [P, P, C.c_uint64, C.c_uint64, P, P, P, P]
+        lib.orc_select_margin.argtypes = [P, C.c_int, C.c_double, P]
+        lib.orc_select_margin.restype = C.c_int
+        lib.orc_generation.argtypes = [P, P, C.c_uint64, C.c_uint64, P, P, P, P, P]
+        lib.orc_generations.argtypes = [P, P, C.c_int, P, C.c_uint64, P, P, P, P, C.c_int]
+        lib.orc_generations.restype = C.c_int
         lib.orc_vmc.argtypes = [P, P, C.c_uint64, C.c_uint64, C.c_int, C.c_double, P, P, P]
         lib.orc_generation.restype = C.c_int
-        lib.orc_reconfigure.argtypes = [P, P, C.c_int, C.c_double, P, P, P]
+        lib.orc_reconfigure.argtypes = [P, P, C.c_int, C.c_double, P, P, P, P]
         lib.orc_reconfigure.restype = C.c_int
         lib.orc_xi.argtypes = [C.c_uint64, C.c_uint64]
         lib.orc_xi.restype = C.c_double
-        lib.orc_run.argtypes = [P, P, C.c_int, P, C.c_uint64, C.c_int, P, P, P, P, C.c_int]
+        lib.orc_run.argtypes = [P, P, C.c_int, P, C.c_uint64, C.c_int, P, P, P, P, P, C.c_int]
         lib.orc_run.restype = C.c_int
         _lib = lib
     return _lib
@@ -271,16 +275,41 @@ class Oracle:
         T = _f64(T)
         return int(self.lib.orc_select(_ptr(T), int(T.shape[0]), float(u2)))
 
+    def select_margin(self, T, u2) -> Tuple[int, float]:
+        """Heat-bath choice and its relative margin (distance of u2 * Delta to
+        the nearer end of the chosen cumulative interval, over Delta)."""
+        T = _f64(T)
+        mg = C.c_double()
+        m = self.lib.orc_select_margin(_ptr(T), int(T.shape[0]), float(u2), C.byref(mg))
+        return int(m), mg.value
+
     # -- projection -------------------------------------------------------
-    def generation(self, pos, slot: int, gen: int):
-        """One walker, one generation.  Returns (pos', log_w, e_L, n_moves)."""
+    def generation(self, pos, slot: int, gen: int, with_margin: bool = False):
+        """One walker, one generation.  Returns (pos', log_w, e_L, n_moves),
+        plus the smallest relative margin of its integer decisions when
+        with_margin."""
         p = _f64(pos).copy()
-        lw, el = C.c_double(), C.c_double()
+        lw, el, mg = C.c_double(), C.c_double(), C.c_double()
         nm = C.c_int64()
         rc = self.lib.orc_generation(C.byref(self.sys), C.byref(self.prm), int(slot), int(gen),
-                                     _ptr(p), C.byref(lw), C.byref(el), C.byref(nm))
+                                     _ptr(p), C.byref(lw), C.byref(el), C.byref(nm), C.byref(mg))
         _check(rc, "generation")
+        if with_margin:
+            return p, lw.value, el.value, nm.value, mg.value
         return p, lw.value, el.value, nm.value
+
+    def generations(self, pos, gen: int, nthreads: int = 0):
+        """One generation of every walker slot of pos [W][N][3] (no
+        reconfiguration), slots in parallel.  Returns dict(pos, log_w, e_l,
+        n_moves, margin) per slot."""
+        p = _f64(pos).copy()
+        W = p.shape[0]
+        lw, el, mg = np.zeros(W), np.zeros(W), np.zeros(W)
+        nm = np.zeros(W, dtype=np.int64)
+        rc = self.lib.orc_generations(C.byref(self.sys), C.byref(self.prm), W, _ptr(p), int(gen),
+                                      _ptr(lw), _ptr(el), _ptr(nm), _ptr(mg), int(nthreads))
+        _check(rc, "generations")
+        return dict(pos=p, log_w=lw, e_l=el, n_moves=nm, margin=mg)
 
     def vmc(self, pos, slot: int, gen: int, n_steps: int, step: float):
         """Metropolis chain of n_steps single-electron moves from pos:
@@ -292,27 +321,35 @@ class Oracle:
         _check(rc, "orc_vmc")
         return p, int(acc.value), float(el.value)
 
-    def reconfigure(self, log_w, e_l, xi):
+    def reconfigure(self, log_w, e_l, xi, with_margin: bool = False):
+        """Systematic resampling: (idx, log_wbar, ebar), plus per destination
+        slot the relative margin of its choice when with_margin."""
         lw = _f64(log_w)
         el = _f64(e_l)
         W = lw.shape[0]
         idx = np.zeros(W, dtype=np.int32)
+        mg = np.zeros(W)
         lwb, eb = C.c_double(), C.c_double()
         rc = self.lib.orc_reconfigure(_ptr(lw), _ptr(el), W, float(xi), _ptr(idx),
-                                      C.byref(lwb), C.byref(eb))
+                                      C.byref(lwb), C.byref(eb), _ptr(mg))
         _check(rc, "reconfigure")
+        if with_margin:
+            return idx, lwb.value, eb.value, mg
         return idx, lwb.value, eb.value
 
     def run(self, pos, n_gen: int, gen0: int = 0, nthreads: int = 0, want_idx: bool = True):
-        """Whole projection.  Returns dict(pos, log_wbar, ebar, n_moves, idx)."""
+        """Whole projection.  Returns dict(pos, log_wbar, ebar, n_moves, idx,
+        margin); margin [n_gen][2][W]: per slot the smallest decision margin of
+        its projection, then per destination slot that of its resampling."""
         p = _f64(pos).copy()
         W = p.shape[0]
         lwb = np.zeros(n_gen)
         eb = np.zeros(n_gen)
         nm = np.zeros(n_gen, dtype=np.int64)
         idx = np.zeros((n_gen, W), dtype=np.int32) if want_idx else None
+        mg = np.zeros((n_gen, 2, W)) if want_idx else None
         rc = self.lib.orc_run(C.byref(self.sys), C.byref(self.prm), W, _ptr(p), int(gen0), int(n_gen),
                               _ptr(lwb), _ptr(eb), _ptr(nm), _ptr(idx) if want_idx else None,
-                              int(nthreads))
+                              _ptr(mg) if want_idx else None, int(nthreads))
         _check(rc, "run")
-        return dict(pos=p, log_wbar=lwb, ebar=eb, n_moves=nm, idx=idx)
+        return dict(pos=p, log_wbar=lwb, ebar=eb, n_moves=nm, idx=idx, margin=mg)

