@@ -7,11 +7,15 @@ Sherman-Morrison update) followed by the fixed-population reconfiguration.
 The timed region runs `--steps` generations through lrdmc_run with the
 walkers resident in HBM, bracketed by device synchronizations.
 
-Workload (default): Ar-like atom, Z = 18 (9 up, 9 down), K = 64 even-tempered
-s/p/d Gaussians 0.05 * 2.5^k with a seeded orthonormal MO matrix, Pade
-Jastrow b = 1, small spacing a = 0.1 bohr with r_c(a, Z) and a' from the
-paper's rule, 4096 walkers.  The a = 0.2 bohr spacing of the same workload is
-timed as a second line inside the same JSON object.
+Workload (default): the largest configuration that fits one GPU, the
+synthetic molecule: 4 nuclei Z = 8 and 8 nuclei Z = 1 at seeded positions
+(minimum separation 1.8 bohr), 20 up / 20 down electrons, K = 256
+even-tempered s/p/d Gaussians 0.05 * 2.5^k with a seeded orthonormal MO
+matrix, Pade Jastrow b = 1, a = 1/28 bohr with r_c(a, Z = 8) and a' from the
+paper's rule, R_c over the Z = 8 nuclei, 16384 walkers, FP64.  The same line
+reports the molecule with the mixed-precision move table and the Ar-like atom
+(Z = 18, K = 64, a = 0.1 bohr, 4096 walkers) on its fixed-size and on the
+general kernel.
 
 Prints one JSON line.  Runs on one GPU only (the walker population is not
 sharded over several GPUs).
@@ -629,7 +633,7 @@ def sweep():
                    a=r["a"], a_prime=r["a_prime"], generations=steps, value=r["value"],
                    ms_per_step=r["ms_per_step"], moves_per_walker_gen=r["moves_per_walker_gen"],
                    kernel_ms=r["roofline"]["avg_launch_ms"], achieved_tflops=r["roofline"]["achieved"],
-                   frac=r["roofline"]["frac"])
+                   frac=r["roofline"]["frac"], ess_fraction=r["ess_fraction"])
         print(f"[sweep] {name}: {r['value'] / 1e6:.2f} M electron-moves/s, frac {row['frac']:.3f}",
               file=sys.stderr, flush=True)
         out.append(row)
@@ -675,11 +679,11 @@ def cpu_baseline(system, a, ap, rc, tau, seed, pos, gen0, seconds, threads=None)
                       f"{moves} moves in {dt:.1f} s"}
 
 
-def run_workload(name, steps, warmup, want_cpu, cpu_seconds, precision=0):
+def run_workload(name, steps, warmup, want_cpu, cpu_seconds, precision=0, generic=0):
     import torch
     from paper_1909_01589_amd import inputs, stats, workcount
-    from paper_1909_01589_amd.lrdmc import (LRDMC, lrdmc_set_precision, lrdmc_set_timing, lrdmc_spacing,
-                                            lrdmc_timing)
+    from paper_1909_01589_amd.lrdmc import (LRDMC, lrdmc_is_specialized, lrdmc_set_precision, lrdmc_set_timing,
+                                            lrdmc_spacing, lrdmc_timing, lrdmc_use_generic)
 
     cfg = inputs.get_config(name)
     s = cfg.system
@@ -687,6 +691,8 @@ def run_workload(name, steps, warmup, want_cpu, cpu_seconds, precision=0):
     W = cfg.walkers
     gpu = LRDMC(s, cfg.a, ap, rc, cfg.tau, W, seed=cfg.seed, rotate=cfg.rotate, refresh=cfg.refresh)
     lrdmc_set_precision(gpu.ctx, precision)
+    lrdmc_use_generic(gpu.ctx, generic)
+    kernel = "project_kernel_fixed" if lrdmc_is_specialized(gpu.ctx) else "project_kernel"
     gpu.set_walkers(inputs.initial_walkers(s, W, cfg.seed), 0)
     if warmup:
         gpu.run(warmup)
@@ -704,6 +710,7 @@ def run_workload(name, steps, warmup, want_cpu, cpu_seconds, precision=0):
     moves = int(n_moves.sum())
     lwb = out["log_wbar"].cpu().numpy()
     eb = out["ebar"].cpu().numpy()
+    ess = out["ess"].cpu().numpy() / W
     E, sig = stats.estimate(lwb, eb, p=None)
 
     shp = workcount.shape_of(s)
@@ -721,12 +728,13 @@ def run_workload(name, steps, warmup, want_cpu, cpu_seconds, precision=0):
         "moves_per_walker_gen": moves / (W * steps),
         "projection_time_per_s": W * cfg.tau * steps / wall,
         "E_Ha": E, "sigma_E_Ha": sig,
+        "ess_fraction": {"median": float(np.median(ess)), "min": float(ess.min())},
         "time_to_sigma_1mHa_s": wall * (sig / 1e-3) ** 2 if np.isfinite(sig) else None,
         "a": cfg.a, "a_prime": ap, "r_c": rc, "n_core": nc, "tau": cfg.tau, "walkers": W,
         "refresh": cfg.refresh,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
-                     "kernel": "project_kernel", "avg_launch_ms": avg_ms,
+                     "kernel": kernel, "avg_launch_ms": avg_ms,
                      "ops_per_launch": ops_per_launch,
                      "reconfigure_avg_ms": br_ms / max(br_n, 1)},
     }
@@ -739,13 +747,46 @@ def run_workload(name, steps, warmup, want_cpu, cpu_seconds, precision=0):
     return cfg, res
 
 
+WORKLOAD_TEXT = {
+    "molecule": "synthetic molecule: 4 nuclei Z=8 + 8 nuclei Z=1 at seeded positions (min separation 1.8 bohr), "
+                "20 up / 20 down electrons, K={K} even-tempered s/p/d Gaussians 0.05*2.5^k, seeded orthonormal MOs, "
+                "Pade Jastrow b=1, a={a:.5f} bohr, a'={ap:.5f}, r_c={rc:.5f} (R_c over the Z=8 nuclei), "
+                "{W} walkers, tau={tau} per generation, FP64",
+    "ar_a0.1": "Ar-like atom Z=18 (9 up, 9 down), K={K} even-tempered s/p/d Gaussians 0.05*2.5^k, seeded "
+               "orthonormal MOs, Pade Jastrow b=1, a={a} bohr, a'={ap:.5f}, r_c={rc:.5f}, {W} walkers, "
+               "tau={tau} per generation, FP64",
+}
+
+
+def _describe(cfg, res):
+    t = WORKLOAD_TEXT.get(cfg.name, cfg.name + ": a={a} bohr, a'={ap:.5f}, {W} walkers, tau={tau}")
+    return cfg.name + ": " + t.format(K=cfg.system.n_basis, a=cfg.a, ap=res["a_prime"], rc=res["r_c"],
+                                      W=cfg.walkers, tau=cfg.tau)
+
+
+def _mixed_bound(system) -> float:
+    """The derived bound on the mixed-precision ratios: exp(dJ) - 1 with
+    dJ = 2^-20 (sum_j c_ij / b_ee + sum_I Z_I / b_en) for the electron with the
+    largest sum (cusp coefficients 1/2 and 1/4)."""
+    s = system
+    worst = 0.0
+    for up in (True, False):
+        same, other = (s.n_up, s.n_dn) if up else (s.n_dn, s.n_up)
+        if same == 0:
+            continue
+        ee = (0.25 * (same - 1) + 0.5 * other) / s.b_ee
+        en = float(np.sum(s.Z)) / s.b_en
+        worst = max(worst, ee + en)
+    return float(np.expm1(2.0 ** -20 * worst))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000, help="timed generations")
-    ap.add_argument("--warmup", type=int, default=100, help="untimed generations before timing")
-    ap.add_argument("--workload", default="ar_a0.1")
-    ap.add_argument("--second", default="ar_a0.2", help="second workload line ('' to skip)")
+    ap.add_argument("--steps", type=int, default=300, help="timed generations")
+    ap.add_argument("--warmup", type=int, default=50, help="untimed generations before timing")
+    ap.add_argument("--workload", default="molecule")
+    ap.add_argument("--second", default="ar_a0.1", help="second workload line ('' to skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision line of the benchmark")
@@ -808,12 +849,14 @@ def main():
 
     cfg, main_res = run_workload(args.workload, args.steps, args.warmup, not args.no_cpu_baseline,
                                  args.cpu_seconds)
-    second = None
-    if args.second:
-        _, second = run_workload(args.second, args.steps, args.warmup, False, 0.0)
+    print(f"[bench] {args.workload}: {main_res['value'] / 1e6:.2f} M electron-moves/s", file=sys.stderr, flush=True)
     mixed = None
     if not args.no_mixed:
         _, mixed = run_workload(args.workload, args.steps, args.warmup, False, 0.0, precision=1)
+    second = second_gen = None
+    if args.second:
+        cfg2, second = run_workload(args.second, args.steps, args.warmup, False, 0.0)
+        _, second_gen = run_workload(args.second, args.steps, args.warmup, False, 0.0, generic=1)
 
     s = cfg.system
     line = {
@@ -822,11 +865,8 @@ def main():
         "ms_per_step": main_res["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {
-            "workload": f"{cfg.name}: Ar-like atom Z=18 (9 up, 9 down), K={s.n_basis} even-tempered "
-                        f"s/p/d Gaussians 0.05*2.5^k, seeded orthonormal MOs, Pade Jastrow b=1, "
-                        f"a={cfg.a} bohr, a'={main_res['a_prime']:.5f}, r_c={main_res['r_c']:.5f}, "
-                        f"{cfg.walkers} walkers, tau={cfg.tau} per generation",
-            "walkers": cfg.walkers, "electrons": s.n_elec, "basis": s.n_basis,
+            "workload": _describe(cfg, main_res),
+            "walkers": cfg.walkers, "electrons": s.n_elec, "basis": s.n_basis, "nuclei": int(s.n_nuc),
             "a": cfg.a, "a_prime": main_res["a_prime"], "r_c": main_res["r_c"], "tau": cfg.tau,
             "refresh": cfg.refresh,
         },
@@ -835,8 +875,10 @@ def main():
         "projection_time_per_s": main_res["projection_time_per_s"],
         "E_Ha": main_res["E_Ha"], "sigma_E_Ha": main_res["sigma_E_Ha"],
         "time_to_sigma_1mHa_s": main_res["time_to_sigma_1mHa_s"],
+        "ess_fraction": main_res["ess_fraction"],
         "energy_note": "seeded random MOs: a throughput workload whose nodes are not physical; E_Ha and its "
-                       "sigma only record the run (physical energies: --ascan, --zscan-phys, --neural)",
+                       "sigma only record the run (physical energies and times to 1 mHa: --ascan, --zscan-phys, "
+                       "--neural, --mixed)",
     }
     if "cpu_baseline" in main_res:
         line["cpu_baseline"] = main_res["cpu_baseline"]
@@ -844,14 +886,17 @@ def main():
         line["mixed_precision_table"] = {
             "value": mixed["value"], "ms_per_step": mixed["ms_per_step"], "dtype": "f64 with f32 Jastrow estimates",
             "speedup": mixed["value"] / main_res["value"],
-            "note": "lrdmc_set_precision 1: same workload and steps; ratios within a derived 2.3e-5 of FP64"}
+            "note": f"lrdmc_set_precision 1: same workload and steps; ratios within a derived "
+                    f"{_mixed_bound(s):.2g} of FP64"}
     if second is not None:
         line["second_workload"] = {
-            "workload": args.second, "value": second["value"], "ms_per_step": second["ms_per_step"],
-            "a": second["a"], "a_prime": second["a_prime"], "tau": second["tau"],
+            "workload": _describe(cfg2, second), "value": second["value"], "ms_per_step": second["ms_per_step"],
+            "kernel": second["roofline"]["kernel"], "roofline_frac": second["roofline"]["frac"],
+            "avg_launch_ms": second["roofline"]["avg_launch_ms"],
             "moves_per_walker_gen": second["moves_per_walker_gen"],
-            "roofline_frac": second["roofline"]["frac"],
-            "time_to_sigma_1mHa_s": second["time_to_sigma_1mHa_s"],
+            "general_kernel": {"value": second_gen["value"], "ms_per_step": second_gen["ms_per_step"],
+                               "roofline_frac": second_gen["roofline"]["frac"],
+                               "avg_launch_ms": second_gen["roofline"]["avg_launch_ms"]},
         }
     print(json.dumps(line), flush=True)
 

@@ -60,6 +60,8 @@ extern "C" {
 #define LRDMC_ENONFINITE -3  /* NaN/Inf in an energy, a weight or a position   */
 #define LRDMC_ENOMEM     -4  /* host or device allocation failed               */
 #define LRDMC_EDEVICE    -5  /* HIP runtime error                              */
+#define LRDMC_ECOLLAPSE  -6  /* population collapse (lrdmc_set_collapse_threshold) */
+#define LRDMC_EITERCAP   -7  /* a walker reached the move cap of a generation   */
 
 /* Number of per-walker diagnostics written by lrdmc_eval_moves. */
 #define LRDMC_NDIAG 9
@@ -150,6 +152,8 @@ int lrdmc_set_walkers(lrdmc_ctx *ctx, const double *pos, uint64_t generation, vo
  * rho_m = Psi(x'_m)/Psi(x) (fixed node: moves with rho_m <= 0 are dropped).
  * If a reconfiguration is pending, slot s starts from the copy it selected.
  * Errors: LRDMC_ESINGULAR, LRDMC_ENONFINITE (with the slot index),
+ * LRDMC_EITERCAP (a walker reached the move cap of lrdmc_set_move_cap in
+ * one generation; with the slot index),
  * LRDMC_EDEVICE. */
 int lrdmc_project(lrdmc_ctx *ctx, void *stream);
 
@@ -158,18 +162,24 @@ int lrdmc_project(lrdmc_ctx *ctx, void *stream);
  * w_j = exp(log w_j - max), t_s = (s + xi) sum(w)/W, idx_s = first j with
  * cumulative weight > t_s.  Writes the generation record at the device
  * pointers (each may be NULL): log_wbar = log(mean w) (including the max),
- * ebar = sum w_j e_L,j / sum w_j, n_moves = total moves of the generation;
- * idx (device, [W] int32, may be NULL).  Advances the generation counter.
+ * ebar = sum w_j e_L,j / sum w_j, n_moves = total moves of the generation,
+ * ess = effective sample size (sum w)^2 / sum w^2 of the weights (W for
+ * equal weights, 1 when one walker carries all the weight); idx (device,
+ * [W] int32, may be NULL).  Advances the generation counter.
  * Errors: LRDMC_EINVAL (no projection since the last reconfiguration),
- * LRDMC_ENONFINITE, LRDMC_EDEVICE. */
+ * LRDMC_ENONFINITE, LRDMC_ECOLLAPSE (the weights' effective sample size
+ * (sum w)^2 / sum w^2 fell below the collapse threshold times W; the
+ * reconfiguration and the record are still written), LRDMC_EDEVICE. */
 int lrdmc_branch(lrdmc_ctx *ctx, void *stream, double *log_wbar, double *ebar,
-                 int64_t *n_moves, int32_t *idx);
+                 int64_t *n_moves, int32_t *idx, double *ess);
 
 /* n_gen x (lrdmc_project + lrdmc_branch) without host synchronization in
  * between.  Device outputs (each may be NULL): log_wbar[n_gen], ebar[n_gen],
- * n_moves[n_gen], idx[n_gen][W]. */
+ * n_moves[n_gen], idx[n_gen][W], ess[n_gen].  Errors as for lrdmc_project and
+ * lrdmc_branch; the first error of the run is reported (a population
+ * collapse names its generation) and the remaining generations still run. */
 int lrdmc_run(lrdmc_ctx *ctx, int32_t n_gen, void *stream, double *log_wbar,
-              double *ebar, int64_t *n_moves, int32_t *idx);
+              double *ebar, int64_t *n_moves, int32_t *idx, double *ess);
 
 /* Copy the walker state to device buffers (each may be NULL): pos[W][N][3],
  * log_w[W], e_loc[W] (analytic local energy), n_moves[W] (moves of the last
@@ -330,6 +340,22 @@ int32_t lrdmc_is_specialized(const lrdmc_ctx *ctx);
  * such a difference decides one; energies agree statistically.  Errors:
  * LRDMC_EINVAL (NULL, mode outside 0..1). */
 int lrdmc_set_precision(lrdmc_ctx *ctx, int32_t mode);
+
+/* Population-collapse check of lrdmc_branch and lrdmc_run: a generation
+ * whose weights have an effective sample size (sum w)^2 / sum w^2 below
+ * min_fraction * W returns LRDMC_ECOLLAPSE (a population of W walkers then
+ * carries the statistics of fewer than min_fraction W; the projection time
+ * per generation is too long for the trial function, or the trial function
+ * is poor).  Default 0 (off); 0.01 is the usual criterion.
+ * Errors: LRDMC_EINVAL (NULL, min_fraction outside [0, 1]). */
+int lrdmc_set_collapse_threshold(lrdmc_ctx *ctx, double min_fraction);
+
+/* Move cap of lrdmc_project and lrdmc_run: a walker that makes max_moves
+ * moves in one generation stops there and the call returns LRDMC_EITERCAP
+ * with its slot (so that every wave ends even when Delta(x) tau is
+ * pathologically large).  Default and maximum 2^22.
+ * Errors: LRDMC_EINVAL (NULL, max_moves outside 1..2^22). */
+int lrdmc_set_move_cap(lrdmc_ctx *ctx, int32_t max_moves);
 
 /* Generation counter of the next projection. */
 uint64_t lrdmc_generation(const lrdmc_ctx *ctx);

@@ -67,11 +67,14 @@ _lib = None
 
 
 def load():
+    """Load the oracle library (LRDMC_ORACLE_LIB names another build of the
+    same source, e.g. one with sanitizers)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        path = os.environ.get("LRDMC_ORACLE_LIB") or _LIB
+        if path == _LIB and not os.path.exists(_LIB):
             build()
-        lib = C.CDLL(_LIB)
+        lib = C.CDLL(path)
         P = C.c_void_p
         lib.orc_philox4x64_10.argtypes = [P, P, P]
         lib.orc_u01.argtypes = [C.c_uint64]

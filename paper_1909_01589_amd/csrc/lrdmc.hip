@@ -39,7 +39,7 @@ constexpr int kMaxThreads = 256;
 constexpr int kMaxIter = 1 << 22;  // moves per walker and generation
 
 // Internal kernel error codes (err[0]); err[1] holds the slot.
-enum { kErrSingular = 1, kErrNonFinite = 2, kErrIterCap = 3 };
+enum { kErrSingular = 1, kErrNonFinite = 2, kErrIterCap = 3, kErrCollapse = 4 };
 
 // Offsets (in doubles) of the per-walker LDS arrays.  The region starting at
 // U is used twice: during the generation start it holds the Gauss-Jordan
@@ -187,6 +187,7 @@ struct KArgs {
     int rotate;
     // walkers
     int W;
+    int max_iter;                  // moves per walker and generation before LRDMC_EITERCAP
     uint64_t gen;
     const double *pos_in;
     const int *idx_in;             // gather on load, or nullptr
@@ -1402,7 +1403,7 @@ __device__ __forceinline__ void project_body(const KArgs &A)
             } else {
                 lw -= td * EL;
                 tl -= td;
-                action = it + 1 >= kMaxIter ? 3 : 1;
+                action = it + 1 >= A.max_iter ? 3 : 1;
                 thr = R[10] * Delta;
             }
         }
@@ -2051,11 +2052,15 @@ __global__ void net_table_reduce_kernel(int H, int G, const double *work, double
 
 // Fixed-population reconfiguration of W walkers by systematic resampling
 // (one workgroup).  cw: W-double scratch for the cumulative weights.
+// out_ess (optional): the effective sample size (sum w)^2 / sum w^2.
+// min_ess > 0: report a population collapse (generation gen in err[1]) when
+// the effective sample size falls below it.
 __global__ void __launch_bounds__(1024) reconfigure_kernel(const double *logw, const double *el,
                                                            const int *nmov, int W, double xi_in,
                                                            uint64_t seed, uint64_t gen, double *cw,
                                                            int *idx, double *out_lwb, double *out_eb,
-                                                           long long *out_nm, int *err)
+                                                           long long *out_nm, double *out_ess, int *err,
+                                                           double min_ess)
 {
     __shared__ double red[32];
     __shared__ long long redi[16];
@@ -2071,13 +2076,14 @@ __global__ void __launch_bounds__(1024) reconfigure_kernel(const double *logw, c
 
     const int chunk = (W + NT - 1) / NT;
     const int c0 = min(W, tid * chunk), c1 = min(W, c0 + chunk);
-    double ws = 0.0, ew = 0.0;
+    double ws = 0.0, ew = 0.0, w2 = 0.0;
     long long nm = 0;
     for (int j = c0; j < c1; ++j) {
         const double w = exp(logw[j] - mx);
         cw[j] = w;
         ws += w;
         ew += w * (el ? el[j] : 0.0);
+        w2 += w * w;
         nm += nmov ? nmov[j] : 0;
     }
     double Ws;
@@ -2087,8 +2093,8 @@ __global__ void __launch_bounds__(1024) reconfigure_kernel(const double *logw, c
         run += cw[j];
         cw[j] = run;
     }
-    double v[1] = {ew};
-    block_sum<1>(v, red + 16);
+    double v[2] = {ew, w2};
+    block_sum<2>(v, red + 16);
     for (int off = 32; off > 0; off >>= 1) nm += __shfl_xor(nm, off, 64);
     if (lane == 0) redi[wv] = nm;
     __syncthreads();
@@ -2116,7 +2122,9 @@ __global__ void __launch_bounds__(1024) reconfigure_kernel(const double *logw, c
         if (out_lwb) *out_lwb = log(Ws / (double)W) + mx;
         if (out_eb) *out_eb = v[0] / Ws;
         if (out_nm) *out_nm = nt;
+        if (out_ess) *out_ess = Ws * Ws / v[1];
         if (!(Ws > 0.0) || !isfinite(Ws) || !isfinite(mx)) report(err, kErrNonFinite, -1);
+        else if (min_ess > 0.0 && Ws * Ws < min_ess * v[1]) report(err, kErrCollapse, (int)gen);
     }
 }
 
@@ -2166,6 +2174,8 @@ const FixedKernel kFixedKernels[] = {LRDMC_FIXED_SHAPES};
 struct lrdmc_ctx {
     int W = 0, N = 0, n_up = 0, n_dn = 0, ns = 0, K = 0, Kp = 0, n_nuc = 0, n_heavy = 0, M = 0;
     double b_ee = 0, b_en = 0, v_nn = 0;
+    double min_ess_frac = 0.0;    // population-collapse threshold (0: off)
+    int max_iter = kMaxIter;      // move cap per walker and generation
     lrdmc_params prm{};
     double *d_Z = nullptr, *d_R = nullptr, *d_mo = nullptr, *d_Rheavy = nullptr;
     FnDesc *d_fn = nullptr;
@@ -2282,7 +2292,7 @@ KArgs base_args(const lrdmc_ctx *c)
     A.sw_c = A.sw_pade ? c->prm.r_c * c->prm.r_c : 1.0 / (2.0 * c->prm.r_c * c->prm.r_c);
     A.mpe = c->M / c->N;
     A.tau = c->prm.tau; A.seed = c->prm.seed; A.rotate = c->prm.rotate;
-    A.W = c->W; A.gen = c->gen; A.err = c->d_err; A.L = c->L;
+    A.W = c->W; A.gen = c->gen; A.err = c->d_err; A.L = c->L; A.max_iter = c->max_iter;
     if (c->corr) {
         A.fcoef = c->d_fcoef;
         A.f_nint = c->f_G - 1;
@@ -2308,8 +2318,13 @@ int check_kernel_error(lrdmc_ctx *c, hipStream_t st)
         snprintf(buf, sizeof buf, "singular Slater matrix in walker slot %d", e[1]);
         return fail(c, LRDMC_ESINGULAR, buf);
     case kErrIterCap:
-        snprintf(buf, sizeof buf, "walker slot %d exceeded %d moves in one generation", e[1], kMaxIter);
-        return fail(c, LRDMC_ENONFINITE, buf);
+        snprintf(buf, sizeof buf, "walker slot %d reached the cap of %d moves in one generation", e[1], c->max_iter);
+        return fail(c, LRDMC_EITERCAP, buf);
+    case kErrCollapse:
+        snprintf(buf, sizeof buf,
+                 "population collapse at generation %d: effective sample size (sum w)^2 / sum w^2 below %g of "
+                 "the %d walkers", e[1], c->min_ess_frac, c->W);
+        return fail(c, LRDMC_ECOLLAPSE, buf);
     default:
         if (e[1] < 0) snprintf(buf, sizeof buf, "non-finite total weight in reconfiguration");
         else snprintf(buf, sizeof buf, "non-finite local energy, weight or rate in walker slot %d", e[1]);
@@ -2388,11 +2403,12 @@ int launch_project(lrdmc_ctx *c, hipStream_t st, const double *pos_in, const int
     return LRDMC_OK;
 }
 
-int launch_branch(lrdmc_ctx *c, hipStream_t st, double *lwb, double *eb, int64_t *nm, int *idx_out)
+int launch_branch(lrdmc_ctx *c, hipStream_t st, double *lwb, double *eb, int64_t *nm, int *idx_out, double *ess)
 {
     const int ev = timing_begin(c, st, 1);
     hipLaunchKernelGGL(reconfigure_kernel, dim3(1), dim3(1024), 0, st, c->d_logw, c->d_el, c->d_nmov, c->W,
-                       -1.0, c->prm.seed, c->gen, c->d_cw, c->d_idx, lwb, eb, (long long *)nm, c->d_err);
+                       -1.0, c->prm.seed, c->gen, c->d_cw, c->d_idx, lwb, eb, (long long *)nm, ess, c->d_err,
+                       c->min_ess_frac * (double)c->W);
     HIP_TRY(c, hipGetLastError());
     timing_end(c, st, ev);
     if (idx_out)
@@ -2735,11 +2751,12 @@ int lrdmc_project(lrdmc_ctx *c, void *stream)
     return check_kernel_error(c, st);
 }
 
-int lrdmc_branch(lrdmc_ctx *c, void *stream, double *log_wbar, double *ebar, int64_t *n_moves, int32_t *idx)
+int lrdmc_branch(lrdmc_ctx *c, void *stream, double *log_wbar, double *ebar, int64_t *n_moves, int32_t *idx,
+                 double *ess)
 {
     if (!c || !c->projected) return fail(c, LRDMC_EINVAL, "lrdmc_branch: no projection to reconfigure");
     hipStream_t st = (hipStream_t)stream;
-    int rc = launch_branch(c, st, log_wbar, ebar, n_moves, idx);
+    int rc = launch_branch(c, st, log_wbar, ebar, n_moves, idx, ess);
     if (rc) return rc;
     c->pending = true;
     c->projected = false;
@@ -2748,7 +2765,7 @@ int lrdmc_branch(lrdmc_ctx *c, void *stream, double *log_wbar, double *ebar, int
 }
 
 int lrdmc_run(lrdmc_ctx *c, int32_t n_gen, void *stream, double *log_wbar, double *ebar, int64_t *n_moves,
-              int32_t *idx)
+              int32_t *idx, double *ess)
 {
     if (!c || !c->loaded || n_gen < 0) return fail(c, LRDMC_EINVAL, "lrdmc_run: no walkers loaded or n_gen < 0");
     hipStream_t st = (hipStream_t)stream;
@@ -2759,7 +2776,8 @@ int lrdmc_run(lrdmc_ctx *c, int32_t n_gen, void *stream, double *log_wbar, doubl
         c->cur ^= 1;
         c->state_ok = c->prm.refresh > 1;
         rc = launch_branch(c, st, log_wbar ? log_wbar + g : nullptr, ebar ? ebar + g : nullptr,
-                           n_moves ? n_moves + g : nullptr, idx ? idx + (size_t)g * c->W : nullptr);
+                           n_moves ? n_moves + g : nullptr, idx ? idx + (size_t)g * c->W : nullptr,
+                           ess ? ess + g : nullptr);
         if (rc) return rc;
         c->pending = true;
         c->projected = false;
@@ -2901,7 +2919,8 @@ int lrdmc_reconfigure(const double *log_w, const double *e_loc, int32_t W, doubl
         return fail(nullptr, LRDMC_ENOMEM, "lrdmc_reconfigure: scratch allocation failed");
     (void)hipMemsetAsync(err, 0, 2 * sizeof(int), st);
     hipLaunchKernelGGL(reconfigure_kernel, dim3(1), dim3(1024), 0, st, log_w, e_loc, (const int *)nullptr, W, xi,
-                       0ull, 0ull, cw, idx, stats, stats ? stats + 1 : nullptr, (long long *)nullptr, err);
+                       0ull, 0ull, cw, idx, stats, stats ? stats + 1 : nullptr, (long long *)nullptr, nullptr, err,
+                       0.0);
     hipError_t le = hipGetLastError();
     int e[2] = {0, 0};
     (void)hipMemcpyAsync(e, err, sizeof(e), hipMemcpyDeviceToHost, st);
@@ -3010,6 +3029,24 @@ int lrdmc_set_precision(lrdmc_ctx *c, int32_t mode)
     if (!c) return fail(nullptr, LRDMC_EINVAL, "lrdmc_set_precision: NULL context");
     if (mode < 0 || mode > 1) return fail(c, LRDMC_EINVAL, "lrdmc_set_precision: mode must be 0 or 1");
     c->precision = mode;
+    return LRDMC_OK;
+}
+
+int lrdmc_set_collapse_threshold(lrdmc_ctx *c, double min_fraction)
+{
+    if (!c) return fail(nullptr, LRDMC_EINVAL, "lrdmc_set_collapse_threshold: NULL context");
+    if (!(min_fraction >= 0.0 && min_fraction <= 1.0))
+        return fail(c, LRDMC_EINVAL, "lrdmc_set_collapse_threshold: need 0 <= min_fraction <= 1");
+    c->min_ess_frac = min_fraction;
+    return LRDMC_OK;
+}
+
+int lrdmc_set_move_cap(lrdmc_ctx *c, int32_t max_moves)
+{
+    if (!c) return fail(nullptr, LRDMC_EINVAL, "lrdmc_set_move_cap: NULL context");
+    if (max_moves < 1 || max_moves > kMaxIter)
+        return fail(c, LRDMC_EINVAL, "lrdmc_set_move_cap: need 1 <= max_moves <= 2^22");
+    c->max_iter = max_moves;
     return LRDMC_OK;
 }
 

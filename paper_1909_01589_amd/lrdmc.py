@@ -18,12 +18,14 @@ import numpy as np
 import torch  # imported before the library so that both share one HIP runtime
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblrdmc.so")
+# LRDMC_LIB names another build of the same sources (e.g. with host sanitizers)
+LIB_PATH = os.environ.get("LRDMC_LIB") or os.path.join(_HERE, "liblrdmc.so")
 
 LRDMC_NDIAG = 9
 DIAG_NAMES = ("e_l", "e_lattice", "lap_lattice", "lap_exact", "v_a", "v_sf", "delta", "v", "sum_k")
 
-ERRORS = {-1: "EINVAL", -2: "ESINGULAR", -3: "ENONFINITE", -4: "ENOMEM", -5: "EDEVICE"}
+ERRORS = {-1: "EINVAL", -2: "ESINGULAR", -3: "ENONFINITE", -4: "ENOMEM", -5: "EDEVICE", -6: "ECOLLAPSE",
+          -7: "EITERCAP"}
 
 
 class LRDMCError(RuntimeError):
@@ -58,7 +60,7 @@ EXPORTS = ("lrdmc_spacing", "lrdmc_spacing_pade", "lrdmc_create", "lrdmc_set_wal
            "lrdmc_jastrow_grad", "lrdmc_set_jastrow", "lrdmc_set_jastrow_table", "lrdmc_jastrow_table_grad",
            "lrdmc_vmc", "lrdmc_net_param_count", "lrdmc_net_workspace_size", "lrdmc_net_tabulate", "lrdmc_net_tabulate_backward",
            "lrdmc_use_generic", "lrdmc_is_specialized", "lrdmc_set_precision", "lrdmc_set_timing", "lrdmc_timing",
-           "lrdmc_generation",
+           "lrdmc_set_collapse_threshold", "lrdmc_set_move_cap", "lrdmc_generation",
            "lrdmc_last_error", "lrdmc_destroy")
 
 
@@ -76,8 +78,8 @@ def load():
     lib.lrdmc_create.argtypes = [P, P, I32, P]
     lib.lrdmc_set_walkers.argtypes = [P, P, U64, P]
     lib.lrdmc_project.argtypes = [P, P]
-    lib.lrdmc_branch.argtypes = [P, P, P, P, P, P]
-    lib.lrdmc_run.argtypes = [P, I32, P, P, P, P, P]
+    lib.lrdmc_branch.argtypes = [P, P, P, P, P, P, P]
+    lib.lrdmc_run.argtypes = [P, I32, P, P, P, P, P, P]
     lib.lrdmc_get_walkers.argtypes = [P, P, P, P, P, P]
     lib.lrdmc_eval_moves.argtypes = [P, P, P, P, P, P]
     lib.lrdmc_reconfigure.argtypes = [P, P, I32, D, P, P, P]
@@ -94,6 +96,8 @@ def load():
     lib.lrdmc_net_tabulate_backward.argtypes = [P, I32, I32, D, P, P, P, P]
     lib.lrdmc_use_generic.argtypes = [P, I32]
     lib.lrdmc_set_precision.argtypes = [P, I32]
+    lib.lrdmc_set_collapse_threshold.argtypes = [P, D]
+    lib.lrdmc_set_move_cap.argtypes = [P, I32]
     lib.lrdmc_is_specialized.argtypes = [P]
     lib.lrdmc_is_specialized.restype = I32
     lib.lrdmc_set_timing.argtypes = [P, I32]
@@ -108,7 +112,8 @@ def load():
                  "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure",
                  "lrdmc_jastrow_grad", "lrdmc_set_jastrow", "lrdmc_set_jastrow_table",
                  "lrdmc_jastrow_table_grad", "lrdmc_vmc", "lrdmc_net_tabulate", "lrdmc_net_tabulate_backward",
-                 "lrdmc_use_generic", "lrdmc_set_precision", "lrdmc_set_timing",
+                 "lrdmc_use_generic", "lrdmc_set_precision", "lrdmc_set_collapse_threshold", "lrdmc_set_move_cap",
+                 "lrdmc_set_timing",
                  "lrdmc_timing"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -188,16 +193,16 @@ def lrdmc_project(ctx, stream=None):
     _check(load().lrdmc_project(ctx, _stream(stream)), ctx)
 
 
-def lrdmc_branch(ctx, log_wbar=None, ebar=None, n_moves=None, idx=None, stream=None):
+def lrdmc_branch(ctx, log_wbar=None, ebar=None, n_moves=None, idx=None, ess=None, stream=None):
     _check(load().lrdmc_branch(ctx, _stream(stream), _dptr(log_wbar, torch.float64),
                                _dptr(ebar, torch.float64), _dptr(n_moves, torch.int64),
-                               _dptr(idx, torch.int32)), ctx)
+                               _dptr(idx, torch.int32), _dptr(ess, torch.float64)), ctx)
 
 
-def lrdmc_run(ctx, n_gen: int, log_wbar=None, ebar=None, n_moves=None, idx=None, stream=None):
+def lrdmc_run(ctx, n_gen: int, log_wbar=None, ebar=None, n_moves=None, idx=None, ess=None, stream=None):
     _check(load().lrdmc_run(ctx, int(n_gen), _stream(stream), _dptr(log_wbar, torch.float64),
                             _dptr(ebar, torch.float64), _dptr(n_moves, torch.int64),
-                            _dptr(idx, torch.int32)), ctx)
+                            _dptr(idx, torch.int32), _dptr(ess, torch.float64)), ctx)
 
 
 def lrdmc_get_walkers(ctx, pos=None, log_w=None, e_loc=None, n_moves=None, stream=None):
@@ -293,6 +298,17 @@ def lrdmc_set_precision(ctx, mode: int):
     _check(load().lrdmc_set_precision(ctx, int(mode)), ctx)
 
 
+def lrdmc_set_collapse_threshold(ctx, min_fraction: float):
+    """Population-collapse check: LRDMC_ECOLLAPSE when a generation's
+    effective sample size falls below min_fraction * W (0 turns it off)."""
+    _check(load().lrdmc_set_collapse_threshold(ctx, float(min_fraction)), ctx)
+
+
+def lrdmc_set_move_cap(ctx, max_moves: int):
+    """Moves per walker and generation before LRDMC_EITERCAP (1..2^22)."""
+    _check(load().lrdmc_set_move_cap(ctx, int(max_moves)), ctx)
+
+
 def lrdmc_is_specialized(ctx) -> bool:
     return bool(load().lrdmc_is_specialized(ctx))
 
@@ -379,16 +395,19 @@ class LRDMC:
         lwb, eb = self._f64(1), self._f64(1)
         nm = torch.empty(1, dtype=torch.int64, device=self.device)
         idx = torch.empty(self.W, dtype=torch.int32, device=self.device)
-        lrdmc_branch(self.ctx, lwb, eb, nm, idx)
-        return dict(log_wbar=float(lwb.item()), ebar=float(eb.item()), n_moves=int(nm.item()), idx=idx)
+        ess = self._f64(1)
+        lrdmc_branch(self.ctx, lwb, eb, nm, idx, ess)
+        return dict(log_wbar=float(lwb.item()), ebar=float(eb.item()), n_moves=int(nm.item()), idx=idx,
+                    ess=float(ess.item()))
 
     def run(self, n_gen: int, want_idx: bool = False, out=None):
         if out is None:
             out = dict(log_wbar=self._f64(n_gen), ebar=self._f64(n_gen),
                        n_moves=torch.empty(n_gen, dtype=torch.int64, device=self.device),
                        idx=(torch.empty(n_gen, self.W, dtype=torch.int32, device=self.device)
-                            if want_idx else None))
-        lrdmc_run(self.ctx, n_gen, out["log_wbar"], out["ebar"], out["n_moves"], out["idx"])
+                            if want_idx else None),
+                       ess=self._f64(n_gen))
+        lrdmc_run(self.ctx, n_gen, out["log_wbar"], out["ebar"], out["n_moves"], out["idx"], out.get("ess"))
         return out
 
     def get_walkers(self):

@@ -19,6 +19,27 @@ import numpy as np
 
 TIE = 1e-12
 OBSERVED: dict = {}
+
+# FP64 bars (design notes, tolerances).  Generation records (ebar, log wbar):
+# the 1e-10 Ha target plus about 900 eps |E| for the synthetic atoms whose
+# energies reach thousands of Ha (cancellation in E_L of tight Gaussians).
+# Per-walker E_L (and sum_i lap_i Psi/Psi) relative to 1 + |E_L| (+ |lap|),
+# log w relative to 1 + |log w|: these carry kappa(A) eps from the inverse
+# and the Sherman-Morrison updates carried since the last refresh.  Move
+# ratios: relative to |rho| plus a share of the walker's largest |rho| (a
+# ratio near a node is a difference of large terms).
+
+
+def record_bar(E):
+    return 1e-10 + 2e-13 * np.abs(E)
+
+
+WALKER_E_REL = 2e-10
+WALKER_LOGW_REL = 2e-11
+
+
+def ratio_bar(rho, scale):
+    return 1e-11 * np.abs(rho) + 2e-12 * scale
 TIES = {"count": 0, "where": []}
 
 

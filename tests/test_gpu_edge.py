@@ -10,7 +10,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
-from parity_bars import check, run_agrees  # noqa: E402
+from parity_bars import check, record_bar, run_agrees  # noqa: E402
 from oracle import spacing  # noqa: E402
 from paper_1909_01589_amd import inputs  # noqa: E402
 
@@ -34,7 +34,7 @@ def test_single_walker_matches_oracle():
     ref = oracle.Oracle(s, a, ap, rc, tau=0.0217, seed=4).run(pos, 4, gen0=2)
     n = run_agrees("single walker", out["n_moves"].cpu().numpy(), out["idx"].cpu().numpy(), ref)
     assert np.all(out["idx"].cpu().numpy() == 0)
-    check("single walker ebar", out["ebar"].cpu().numpy()[:n], ref["ebar"][:n], 1e-10 + 1e-12 * np.abs(ref["ebar"][:n]),
+    check("single walker ebar", out["ebar"].cpu().numpy()[:n], ref["ebar"][:n], record_bar(ref["ebar"][:n]),
           scale=np.abs(ref["ebar"][:n]))
     gpu.close()
 
@@ -189,3 +189,46 @@ def test_get_walkers_after_branch_returns_selected_copies():
     assert np.all(after["log_w"] == 0) and np.all(after["n_moves"] == 0)
     assert rec["n_moves"] == before["n_moves"].sum()
     g.close()
+
+
+def test_population_collapse_is_reported():
+    """The effective sample size of every generation lies in [1, W]; the
+    collapse check (off by default) forced from the host: a threshold of the
+    whole population flags any unequal weights and names the generation (the
+    reconfiguration itself is still done), 0 turns the check off again."""
+    from paper_1909_01589_amd.lrdmc import LRDMCError, lrdmc_set_collapse_threshold
+    s, gpu, _ = _be(32, seed=4)
+    pos = inputs.initial_walkers(s, 32, 3)
+    gpu.set_walkers(pos, 0)
+    ess = gpu.run(3)["ess"].cpu().numpy()
+    assert np.all(ess >= 1.0) and np.all(ess <= 32 * (1 + 1e-12))
+    lrdmc_set_collapse_threshold(gpu.ctx, 1.0)
+    with pytest.raises(LRDMCError) as e:
+        gpu.run(2)
+    assert e.value.code == -6 and "generation 3" in str(e.value)
+    assert gpu.generation == 5
+    lrdmc_set_collapse_threshold(gpu.ctx, 0.0)
+    gpu.run(2)
+    with pytest.raises(LRDMCError) as e:
+        lrdmc_set_collapse_threshold(gpu.ctx, 1.5)
+    assert e.value.code == -1
+    gpu.close()
+
+
+def test_move_cap_is_reported_with_its_slot():
+    """The per-generation move cap, forced from the host with a cap of two
+    moves where walkers make about four per generation: the kernels stop the
+    walker at the cap and the call names its slot."""
+    from paper_1909_01589_amd.lrdmc import LRDMCError, lrdmc_set_move_cap
+    s, gpu, _ = _be(8, seed=4)
+    gpu.set_walkers(inputs.initial_walkers(s, 8, 3), 0)
+    lrdmc_set_move_cap(gpu.ctx, 2)
+    with pytest.raises(LRDMCError) as e:
+        gpu.project()
+    assert e.value.code == -7 and "slot" in str(e.value) and "cap of 2 moves" in str(e.value)
+    lrdmc_set_move_cap(gpu.ctx, 1 << 22)
+    gpu.set_walkers(inputs.initial_walkers(s, 8, 3), 0)
+    gpu.project()
+    with pytest.raises(LRDMCError):
+        lrdmc_set_move_cap(gpu.ctx, 0)
+    gpu.close()

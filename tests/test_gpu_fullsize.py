@@ -21,7 +21,7 @@ torch = pytest.importorskip("torch")
 import oracle  # noqa: E402
 from oracle import spacing  # noqa: E402
 from paper_1909_01589_amd import inputs  # noqa: E402
-from parity_bars import check, slot_agrees, tie  # noqa: E402
+from parity_bars import WALKER_E_REL, WALKER_LOGW_REL, check, record_bar, slot_agrees, tie  # noqa: E402
 
 
 def _check_generation(gpu, orc, start, gen, label):
@@ -37,8 +37,8 @@ def _check_generation(gpu, orc, start, gen, label):
                                out["pos"][w], ref["pos"][w], ref["margin"][w]) for w in range(W)])
     el_o, lw_o = ref["e_l"][ok], ref["log_w"][ok]
     check(f"{label} positions", out["pos"][ok], ref["pos"][ok], 1e-11)
-    check(f"{label} E_L", out["e_l"][ok], el_o, 1e-9 * (1 + np.abs(el_o)), scale=1 + np.abs(el_o))
-    check(f"{label} log w", out["log_w"][ok], lw_o, 1e-9 * (1 + np.abs(lw_o)), scale=1 + np.abs(lw_o))
+    check(f"{label} E_L", out["e_l"][ok], el_o, WALKER_E_REL * (1 + np.abs(el_o)), scale=1 + np.abs(el_o))
+    check(f"{label} log w", out["log_w"][ok], lw_o, WALKER_LOGW_REL * (1 + np.abs(lw_o)), scale=1 + np.abs(lw_o))
     print(f"{label}: {ok.sum()} of {W} slots compared, {ref['n_moves'].sum()} moves, "
           f"smallest oracle margin {ref['margin'].min():.2e}", flush=True)
     return out, ok
@@ -50,8 +50,11 @@ def _check_branch(gpu, orc, out, gen, label):
     idx = rec["idx"].cpu().numpy()
     for b in np.nonzero(idx != idx_o)[0]:
         tie(f"{label} reconfiguration slot {b}", float(mg[b]))
-    check(f"{label} ebar", rec["ebar"], eb_o, 1e-10 + 1e-12 * abs(eb_o), scale=abs(eb_o))
-    check(f"{label} log wbar", rec["log_wbar"], lwb_o, 1e-10 + 1e-12 * abs(lwb_o), scale=1 + abs(lwb_o))
+    check(f"{label} ebar", rec["ebar"], eb_o, record_bar(eb_o), scale=abs(eb_o))
+    check(f"{label} log wbar", rec["log_wbar"], lwb_o, record_bar(lwb_o), scale=1 + abs(lwb_o))
+    w = np.exp(out["log_w"] - out["log_w"].max())
+    ess = w.sum() ** 2 / np.dot(w, w)
+    check(f"{label} effective sample size", rec["ess"], ess, 1e-12 * ess, scale=ess)
     assert rec["n_moves"] == out["n_moves"].sum()
     start = gpu.get_walkers()["pos"].cpu().numpy()
     assert np.array_equal(start, out["pos"][idx])

@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
-from parity_bars import check, run_agrees  # noqa: E402
+from parity_bars import check, record_bar, run_agrees  # noqa: E402
 from oracle import spacing  # noqa: E402
 from paper_1909_01589_amd import inputs  # noqa: E402
 
@@ -101,7 +101,7 @@ def test_parameters_reach_the_projection():
     ref = o.run(mid, 4, gen0=2)
     n = run_agrees("run after set_jastrow", out["n_moves"].cpu().numpy(), out["idx"].cpu().numpy(), ref)
     e = out["ebar"].cpu().numpy()
-    check("run ebar (new Pade parameters)", e[:n], ref["ebar"][:n], 1e-10 + 1e-12 * np.abs(ref["ebar"][:n]),
+    check("run ebar (new Pade parameters)", e[:n], ref["ebar"][:n], record_bar(ref["ebar"][:n]),
           scale=np.abs(ref["ebar"][:n]))
     g.close()
 

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
-from parity_bars import check, run_agrees  # noqa: E402
+from parity_bars import check, record_bar, run_agrees  # noqa: E402
 from oracle import spacing  # noqa: E402
 from paper_1909_01589_amd import inputs  # noqa: E402
 
@@ -75,7 +75,7 @@ def test_run_with_table_matches_oracle(name, W, n_gen, refresh):
     n = run_agrees(f"table run {name} refresh {refresh}", out["n_moves"].cpu().numpy(),
                    out["idx"].cpu().numpy(), ref)
     eb, eb_o = out["ebar"].cpu().numpy(), ref["ebar"]
-    check(f"table run ebar ({name})", eb[:n], eb_o[:n], 1e-9 * (1 + np.abs(eb_o[:n])), scale=np.abs(eb_o[:n]))
+    check(f"table run ebar ({name})", eb[:n], eb_o[:n], record_bar(eb_o[:n]), scale=np.abs(eb_o[:n]))
     if n == n_gen:
         p = gpu.get_walkers()["pos"].cpu().numpy()
         check(f"table run final positions ({name})", p, ref["pos"], 1e-10)

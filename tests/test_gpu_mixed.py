@@ -134,3 +134,55 @@ def test_mixed_ratios_large_systems(name, W):
         scale = np.max(np.abs(r_o))
         assert np.all(np.abs(rho[w] - r_o) <= 1e-9 * (np.abs(r_o) + scale) + np.expm1(dJ) * np.abs(r_o))
         assert abs(diag[w, 0] - d_o["e_l"]) <= 1e-9 * (1 + abs(d_o["e_l"]) + abs(d_o["lap_exact"]))
+
+
+@pytest.mark.parametrize("name,W,generic", [("ar_a0.1", 64, 0), ("ar_a0.1", 32, 1), ("zsweep54", 24, 0),
+                                            ("molecule", 16, 0)])
+def test_mixed_projection_against_the_oracle(name, W, generic):
+    """One generation of the mixed-precision projection kernels against the
+    FP64 oracle, slot by slot: the fixed-size kernel of the Ar-like atom
+    (generic 0) and the general one, the Z = 54 atom (compacted table,
+    inverse in device memory) and the molecule.  A move index may differ from
+    the oracle's only where the oracle's decision margin is within the
+    derived ratio bound eta (the relative change of the rates that the FP32
+    estimates can cause: 2 eta for a heat-bath choice; a move-or-stay
+    comparison also carries the perturbations of the generation's earlier
+    holding times, at most eta tau against tau_d, so the bar is 20 eta for
+    about twenty moves per generation); elsewhere the walker follows the
+    oracle exactly:
+    same moves, positions to 1e-11, E_L to the FP64 bar (the local energy
+    does not use the table), log w to the FP64 bar plus the rate bound times
+    |log w| (each holding time tau_d = -ln u / Delta moves by at most that
+    relative amount)."""
+    from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_is_specialized, lrdmc_set_precision, lrdmc_use_generic
+    cfg = inputs.get_config(name)
+    s = cfg.system
+    rc, ap, _ = spacing.spacing(s.z_max, cfg.a)
+    gpu = LRDMC(s, cfg.a, ap, rc, cfg.tau, W, seed=6, rotate=1, refresh=8)
+    lrdmc_use_generic(gpu.ctx, generic)
+    lrdmc_set_precision(gpu.ctx, 1)
+    if name == "ar_a0.1":
+        assert lrdmc_is_specialized(gpu.ctx) == (generic == 0)
+    pos = inputs.initial_walkers(s, W, 8)
+    gpu.set_walkers(pos, 0)
+    gpu.project()
+    out = {k: v.cpu().numpy() for k, v in gpu.get_walkers().items()}
+    gpu.close()
+    orc = oracle.Oracle(s, cfg.a, ap, rc, tau=cfg.tau, seed=6, rotate=1)
+    ref = orc.generations(pos, 0)
+    eta = float(np.expm1(_jastrow_bound(s)))
+    differ = 0
+    for w in range(W):
+        same = (out["n_moves"][w] == ref["n_moves"][w]
+                and np.allclose(out["pos"][w], ref["pos"][w], rtol=0, atol=1e-11))
+        if not same:
+            assert ref["margin"][w] < 20.0 * eta, (w, ref["margin"][w], eta)
+            differ += 1
+            continue
+        el_o, lw_o = ref["e_l"][w], ref["log_w"][w]
+        assert np.isfinite(out["e_l"][w]) and np.isfinite(out["log_w"][w])
+        assert abs(out["e_l"][w] - el_o) <= 1e-9 * (1 + abs(el_o))
+        assert abs(out["log_w"][w] - lw_o) <= 1e-9 * (1 + abs(lw_o)) + 2.0 * eta * abs(lw_o)
+    print(f"mixed projection {name} generic={generic}: {differ} of {W} slots took another move "
+          f"(oracle margin < {20 * eta:.1e}); {ref['n_moves'].sum()} moves", flush=True)
+    assert differ <= W // 8

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
-from parity_bars import check, run_agrees  # noqa: E402
+from parity_bars import check, record_bar, run_agrees  # noqa: E402
 from oracle import spacing  # noqa: E402
 from paper_1909_01589_amd import inputs  # noqa: E402
 
@@ -82,11 +82,11 @@ def test_run_matches_oracle(mode, name, W, n_gen, refresh):
     print(f"modes run mode={mode} case={name}", flush=True)
     n = run_agrees(f"modes run {mode} {name}", out["n_moves"].cpu().numpy(), out["idx"].cpu().numpy(), ref)
     e = out["ebar"].cpu().numpy()
-    check(f"modes run ebar ({mode}, {name})", e[:n], ref["ebar"][:n], 1e-10 + 1e-12 * np.abs(ref["ebar"][:n]),
+    check(f"modes run ebar ({mode}, {name})", e[:n], ref["ebar"][:n], record_bar(ref["ebar"][:n]),
           scale=np.abs(ref["ebar"][:n]))
     lwb = out["log_wbar"].cpu().numpy()
     check(f"modes run log wbar ({mode}, {name})", lwb[:n], ref["log_wbar"][:n],
-          1e-10 + 1e-12 * np.abs(ref["log_wbar"][:n]), scale=np.abs(ref["log_wbar"][:n]))
+          record_bar(ref["log_wbar"][:n]), scale=np.abs(ref["log_wbar"][:n]))
     if n == n_gen:
         fin = gpu.get_walkers()["pos"].cpu().numpy()
         check(f"modes run final positions ({mode}, {name})", fin, ref["pos"], 1e-11)

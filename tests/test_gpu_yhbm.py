@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
-from parity_bars import check, run_agrees  # noqa: E402
+from parity_bars import check, record_bar, run_agrees  # noqa: E402
 from oracle import spacing  # noqa: E402
 from paper_1909_01589_amd import inputs  # noqa: E402
 
@@ -59,7 +59,7 @@ def test_run_y_in_hbm(name, W, n_gen, refresh, table):
     n = run_agrees(f"y-hbm run {name} refresh {refresh} table {table}", out["n_moves"].cpu().numpy(),
                    out["idx"].cpu().numpy(), ref)
     eb = out["ebar"].cpu().numpy()
-    check(f"y-hbm run ebar ({name})", eb[:n], ref["ebar"][:n], 1e-9 * (1 + np.abs(ref["ebar"][:n])),
+    check(f"y-hbm run ebar ({name})", eb[:n], ref["ebar"][:n], record_bar(ref["ebar"][:n]),
           scale=np.abs(ref["ebar"][:n]))
     if n == n_gen:
         check(f"y-hbm run final positions ({name})", gpu.get_walkers()["pos"].cpu().numpy(), ref["pos"], 1e-10)
@@ -89,7 +89,7 @@ def test_switching_placement_inside_a_run():
     ref = orc.run(pos, 6, gen0=0)
     n = run_agrees("y-hbm placement switch", np.concatenate(nm), np.concatenate(idx), ref)
     check("y-hbm placement switch ebar", np.concatenate(eb)[:n], ref["ebar"][:n],
-          1e-9 * (1 + np.abs(ref["ebar"][:n])), scale=np.abs(ref["ebar"][:n]))
+          record_bar(ref["ebar"][:n]), scale=np.abs(ref["ebar"][:n]))
     gpu.close()
 
 
@@ -151,7 +151,7 @@ def test_compacted_table_run():
     assert ref["n_moves"].sum() > 3 * W
     n = run_agrees("compacted run", out["n_moves"].cpu().numpy(), out["idx"].cpu().numpy(), ref)
     eb = out["ebar"].cpu().numpy()
-    check("compacted run ebar", eb[:n], ref["ebar"][:n], 1e-9 * (1 + np.abs(ref["ebar"][:n])),
+    check("compacted run ebar", eb[:n], ref["ebar"][:n], record_bar(ref["ebar"][:n]),
           scale=np.abs(ref["ebar"][:n]))
     if n == 3:
         check("compacted run final positions", gpu.get_walkers()["pos"].cpu().numpy(), ref["pos"], 1e-10)
