@@ -208,6 +208,20 @@ int lrdmc_eval_moves(lrdmc_ctx *ctx, const double *pos, double *rho, double *k,
 int lrdmc_reconfigure(const double *log_w, const double *e_loc, int32_t W, double xi,
                       int32_t *idx, double *stats, void *stream);
 
+/* lrdmc_reconfigure for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments and results, with the cumulative-weight
+ * scratch in a fixed device array of LRDMC_NOALLOC_MAX_WALKERS doubles per
+ * GPU (8 MiB, held until the process ends) instead of a stream allocation.
+ * The call allocates nothing; it synchronizes the stream.  All calls on one
+ * GPU share that array, so calls that overlap on one GPU (other streams or
+ * host threads) race; sequential calls are independent.
+ * Errors: LRDMC_EINVAL (W < 1, W > LRDMC_NOALLOC_MAX_WALKERS, xi outside
+ * (0,1)), LRDMC_ENONFINITE, LRDMC_EDEVICE. */
+#define LRDMC_NOALLOC_MAX_WALKERS (1 << 20)
+int lrdmc_reconfigure_noalloc(const double *log_w, const double *e_loc, int32_t W, double xi,
+                              int32_t *idx, double *stats, void *stream);
+
 /* Kernel timing with HIP events recorded on the launch stream around every
  * projection and reconfiguration kernel of lrdmc_project, lrdmc_branch and
  * lrdmc_run.  enable != 0 clears the totals and starts accumulating, 0 stops.

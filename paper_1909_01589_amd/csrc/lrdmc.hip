@@ -21,6 +21,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2931,6 +2932,73 @@ int lrdmc_reconfigure(const double *log_w, const double *e_loc, int32_t W, doubl
         return fail(nullptr, LRDMC_EDEVICE, std::string("lrdmc_reconfigure: ") +
                                                 hipGetErrorString(le != hipSuccess ? le : se));
     if (e[0]) return fail(nullptr, LRDMC_ENONFINITE, "lrdmc_reconfigure: non-finite weights");
+    return LRDMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Reconfiguration without allocation.  The cumulative weights and the error
+// flag live in a fixed device array (one per GPU, held until the process
+// ends), so the call allocates nothing.  Calls on one GPU share the array:
+// calls that overlap on one GPU (other streams, other host threads) race.
+
+constexpr int kNoAllocMaxWalkers = LRDMC_NOALLOC_MAX_WALKERS;
+constexpr int kMaxDevices = 64;
+// cumulative weights [kNoAllocMaxWalkers], then the two error ints
+static __device__ __align__(256) double scratch[kNoAllocMaxWalkers + 32];
+
+__global__ void clear_flags_kernel(int *flags, int n)
+{
+    if ((int)threadIdx.x < n) flags[threadIdx.x] = 0;
+}
+
+namespace {
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of this GPU's scratch array, looked up once per device
+// (with the device current); nullptr with the message set on failure.
+static double *scratch_address(int dev)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        double *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            g_error = std::string("lrdmc_reconfigure_noalloc: scratch address: ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+int lrdmc_reconfigure_noalloc(const double *log_w, const double *e_loc, int32_t W, double xi, int32_t *idx,
+                              double *stats, void *stream)
+{
+    if (!log_w || !idx || W < 1 || !(xi > 0.0 && xi < 1.0))
+        return fail(nullptr, LRDMC_EINVAL, "lrdmc_reconfigure_noalloc: invalid arguments");
+    if (W > kNoAllocMaxWalkers)
+        return fail(nullptr, LRDMC_EINVAL, "lrdmc_reconfigure_noalloc: W exceeds LRDMC_NOALLOC_MAX_WALKERS");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return fail(nullptr, LRDMC_EDEVICE, "lrdmc_reconfigure_noalloc: no current device");
+    double *cw = scratch_address(dev);
+    if (!cw) return LRDMC_EDEVICE;
+    int *err = (int *)(cw + kNoAllocMaxWalkers);
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(clear_flags_kernel, dim3(1), dim3(32), 0, st, err, 2);
+    hipLaunchKernelGGL(reconfigure_kernel, dim3(1), dim3(1024), 0, st, log_w, e_loc, (const int *)nullptr, W, xi,
+                       0ull, 0ull, cw, idx, stats, stats ? stats + 1 : nullptr, (long long *)nullptr, nullptr, err,
+                       0.0);
+    hipError_t le = hipGetLastError();
+    int e[2] = {0, 0};
+    hipError_t ce = hipMemcpyAsync(e, err, sizeof(e), hipMemcpyDeviceToHost, st);
+    hipError_t se = hipStreamSynchronize(st);
+    if (le != hipSuccess || ce != hipSuccess || se != hipSuccess)
+        return fail(nullptr, LRDMC_EDEVICE, std::string("lrdmc_reconfigure_noalloc: ") +
+                                                hipGetErrorString(le != hipSuccess ? le : ce != hipSuccess ? ce : se));
+    if (e[0]) return fail(nullptr, LRDMC_ENONFINITE, "lrdmc_reconfigure_noalloc: non-finite weights");
     return LRDMC_OK;
 }
 
