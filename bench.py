@@ -619,6 +619,186 @@ def mixed_bench(walkers=16384, gens=1200, seed=0):
     return {"mixed_precision": out}
 
 
+def tsigma_bench(seeds=8, walkers=16384, a=0.035, gens=1000, moves_per_electron=8.0, t_equil=2.0, seed0=0,
+                 rounds=8, train_steps=60, lr=1e-3, train_walkers=131072, step=0.25):
+    """Time to sigma(E) = 1 mHa of four forms of the projection on the same
+    physical system (Ar with screened hydrogenic orbitals in the Ar-like
+    basis, a = 0.035 bohr, `walkers` walkers): Pade FP64, Pade with the
+    mixed-precision move table, the learned Jastrow correction (trained once
+    by variance minimisation on about 10^6 Metropolis samples), and both.
+    Each form runs `seeds` independent projections (own start walkers and
+    random keys), each `gens` generations after t_equil of equilibration.
+    Per run: c = wall time per unit projection time, v = sigma(E)^2 x
+    projection time (the variance per unit projection time, reblocked).
+    Per form: the means of c and v over the seeds with their standard errors;
+    time to 1 mHa = mean(c) mean(v) / 1e-6; the ratio of FP64 to each form
+    with a 95 % interval from the spread over seeds (delta method on log c
+    and log v).  The energies of the forms are compared with their errors."""
+    import torch
+    from paper_1909_01589_amd import inputs, neural, stats
+    from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_set_precision, lrdmc_spacing
+    s = inputs.ar_screened()
+    N = s.n_elec
+    rc, ap, _ = lrdmc_spacing(s.z_max, a)
+    ap = max(ap, a)
+    t0 = time.perf_counter()
+
+    def note(msg):
+        print(f"[tsigma {time.perf_counter() - t0:7.1f}s] {msg}", file=sys.stderr, flush=True)
+
+    # the learned correction, trained once
+    g = LRDMC(s, a, a, 1.0, 0.01, train_walkers, seed=seed0 + 3, rotate=1, refresh=8)
+    g.set_walkers(inputs.initial_walkers(s, train_walkers, seed0 + 1), 0)
+    g.vmc(3000, step)
+    nj = neural.NeuralJastrow(64, 257, 6.0, seed=seed0)
+    t_train = time.perf_counter()
+    neural.fit_vmc(nj, g, rounds=rounds, steps=train_steps, lr=lr, vmc_steps=300, step=step,
+                   log=lambda r: note(f"training round {r['round']}: VMC var={r['vmc_var']:.2f}"))
+    t_train = time.perf_counter() - t_train
+    g.close()
+
+    def start(net, sd):
+        """VMC-equilibrated start walkers of seed sd and tau for the form's
+        trial function (moves_per_electron moves per electron and generation)."""
+        g = LRDMC(s, a, ap, rc, 1.0, walkers, seed=1000 + sd, rotate=1, refresh=8)
+        if net:
+            nj.attach(g)
+        g.set_walkers(inputs.initial_walkers(s, walkers, 100 + sd), 0)
+        g.vmc(2000, step)
+        pos = g.get_walkers()["pos"].clone()
+        delta = float(g.eval_moves(pos)[2][:, 6].mean())
+        g.close()
+        return pos, delta
+
+    forms = (("fp64", False, 0), ("mixed", False, 1), ("neural", True, 0), ("neural+mixed", True, 1))
+    taus = {}
+    for net in (False, True):
+        _, delta = start(net, 0)
+        taus[net] = float(f"{moves_per_electron * N / delta:.3g}")
+    runs = {f: [] for f, _, _ in forms}
+    for sd in range(seeds):
+        starts = {net: start(net, sd)[0] for net in (False, True)}
+        for label, net, prec in forms:
+            tau = taus[net]
+            g = LRDMC(s, a, ap, rc, tau, walkers, seed=seed0 + 17 * sd + 5, rotate=1, refresh=8)
+            if net:
+                nj.attach(g)
+            lrdmc_set_precision(g.ctx, prec)
+            g.set_walkers(starts[net], 0)
+            g.run(int(t_equil / tau) + 20)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rec = g.run(gens)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t1
+            E, sig = stats.estimate(rec["log_wbar"].cpu().numpy(), rec["ebar"].cpu().numpy(), p=None)
+            ess = rec["ess"].cpu().numpy() / walkers
+            T = gens * tau
+            runs[label].append(dict(seed=sd, E=E, sigma=sig, wall_s=wall, c=wall / T, v=sig * sig * T,
+                                    moves_per_s=float(rec["n_moves"].sum()) / wall, ess_min=float(ess.min())))
+            g.close()
+            note(f"{label} seed {sd}: E={E:.4f} +- {sig:.4f}, {wall:.1f} s")
+
+    def summary(rs):
+        c = np.array([r["c"] for r in rs])
+        v = np.array([r["v"] for r in rs])
+        E = np.array([r["E"] for r in rs])
+        sg = np.array([r["sigma"] for r in rs])
+        n = len(rs)
+        w = 1.0 / sg ** 2
+        Em = float(np.sum(w * E) / np.sum(w))
+        return dict(c=float(c.mean()), c_se=float(c.std(ddof=1) / np.sqrt(n)), v=float(v.mean()),
+                    v_se=float(v.std(ddof=1) / np.sqrt(n)), time_to_1mHa_s=float(c.mean() * v.mean() / 1e-6),
+                    E=Em, E_sigma=float(1.0 / np.sqrt(np.sum(w))),
+                    E_scatter_chi2_dof=float(np.sum(w * (E - Em) ** 2) / max(n - 1, 1)),
+                    moves_per_s=float(np.mean([r["moves_per_s"] for r in rs])),
+                    ess_min=float(min(r["ess_min"] for r in rs)))
+
+    summ = {f: summary(runs[f]) for f, _, _ in forms}
+    base = summ["fp64"]
+    comp = {}
+    for f, _, _ in forms[1:]:
+        q = summ[f]
+        ratio = base["time_to_1mHa_s"] / q["time_to_1mHa_s"]
+        var_log = sum((x[k + "_se"] / x[k]) ** 2 for x in (base, q) for k in ("c", "v"))
+        half = 1.96 * np.sqrt(var_log)
+        comp[f] = dict(ratio=ratio, ci95=[ratio * float(np.exp(-half)), ratio * float(np.exp(half))],
+                       speed_ratio=base["c"] / q["c"], variance_ratio=base["v"] / q["v"],
+                       dE=q["E"] - base["E"], dE_sigma=float(np.hypot(q["E_sigma"], base["E_sigma"])))
+        note(f"{f}: time-to-1mHa ratio FP64/{f} = {ratio:.3f} [{comp[f]['ci95'][0]:.3f}, {comp[f]['ci95'][1]:.3f}], "
+             f"dE = {1e3 * comp[f]['dE']:.2f} +- {1e3 * comp[f]['dE_sigma']:.2f} mHa")
+    return {"tsigma": dict(system=s.name, a=a, a_prime=ap, r_c=rc, walkers=walkers, generations=gens,
+                           seeds=seeds, tau=dict(pade=taus[False], neural=taus[True]), train_wall_s=t_train,
+                           forms=summ, against_fp64=comp, runs=runs, wall_s=time.perf_counter() - t0)}
+
+
+def mfma_probe_bench(reps=10, names=("molecule", "zsweep54")):
+    """The table's contraction two ways on the same walkers (the measurement
+    prototype libmfma_probe.so): determinant ratios of every move of the
+    fixed-axis table by the FP64 dot with Y = C Ainv and by the BF16x3
+    matrix-core product Phi' = B' C followed by the FP64 dot with Ainv; both
+    evaluate the basis functions with the same code.  Walkers after 20
+    projection generations of the workload; kernel times by HIP events over
+    `reps` launches; the BF16x3 ratios against the FP64 ones (relative to the
+    walker's largest |rho_D|, and the moves whose sign changes); for context
+    the projection kernel's time per table of the same population."""
+    import torch
+    from paper_1909_01589_amd import inputs
+    from paper_1909_01589_amd import mfma_probe as mp
+    from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_set_timing, lrdmc_spacing, lrdmc_timing
+    rows = []
+    for name in names:
+        cfg = inputs.get_config(name)
+        s = cfg.system
+        rc, ap, _ = lrdmc_spacing(s.z_max, cfg.a)
+        W = cfg.walkers
+        g = LRDMC(s, cfg.a, ap, rc, cfg.tau, W, seed=cfg.seed, rotate=cfg.rotate, refresh=cfg.refresh)
+        g.set_walkers(inputs.initial_walkers(s, W, cfg.seed), 0)
+        g.run(10)
+        lrdmc_set_timing(g.ctx, True)
+        rec = g.run(10)
+        proj_ms, proj_n, _, _ = lrdmc_timing(g.ctx)
+        tables = W * 10 + int(rec["n_moves"].sum())
+        pos = g.get_walkers()["pos"].cpu().numpy()
+        g.close()
+        t0 = time.perf_counter()
+        probe = mp.Probe(s, pos, cfg.a, ap)
+        prep_s = time.perf_counter() - t0
+        ms = {}
+        for v in (0, 1):
+            probe.ratios(v)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                probe.ratios(v)
+            e1.record()
+            torch.cuda.synchronize()
+            ms[v] = e0.elapsed_time(e1) / reps
+        r64 = probe.ratios(0).cpu().numpy().copy()
+        r16 = probe.ratios(1).cpu().numpy().copy()
+        scale = np.max(np.abs(r64), axis=1, keepdims=True)
+        rel = np.abs(r16 - r64) / scale
+        relm = np.abs(r16 - r64) / np.maximum(np.abs(r64), 1e-300)
+        M = 12 * s.n_elec
+        row = dict(workload=name, walkers=W, moves_per_table=M, basis=s.n_basis,
+                   fp64_ydot_ms=ms[0], bf16x3_mfma_ms=ms[1], mfma_over_fp64=ms[1] / ms[0],
+                   table_evaluations_per_s={"fp64_ydot": W / (ms[0] * 1e-3), "bf16x3_mfma": W / (ms[1] * 1e-3)},
+                   projection_kernel_ms_per_table=proj_ms / tables, projection_ms_per_launch=proj_ms / max(proj_n, 1),
+                   error_over_max_rho={"median": float(np.median(rel)), "p99": float(np.quantile(rel, 0.99)),
+                                       "max": float(rel.max())},
+                   relative_error_median=float(np.median(relm)),
+                   sign_changes=int(np.sum(np.sign(r16) != np.sign(r64))), moves=int(r64.size),
+                   host_prep_s=prep_s)
+        print(f"[mfma-probe] {name}: FP64 Y-dot {ms[0]:.2f} ms, BF16x3 MFMA {ms[1]:.2f} ms per launch of {W} "
+              f"tables; error/max|rho| median {row['error_over_max_rho']['median']:.2e}", file=sys.stderr,
+              flush=True)
+        rows.append(row)
+        del probe
+        torch.cuda.empty_cache()
+    return {"mfma_probe": rows}
+
+
 def sweep():
     """Throughput of every configured workload (generations, warm-up) as in
     the benchmark line: electron-moves/s, ms per generation, the kernel's
@@ -807,6 +987,12 @@ def main():
                     help="only run the single/double-grid cost scan over Z = 10, 18, 36, 54 and exit")
     ap.add_argument("--ascan", action="store_true",
                     help="only run the spacing scan on helium for the three lattice schemes and exit")
+    ap.add_argument("--tsigma", action="store_true",
+                    help="only measure the time to sigma(E) = 1 mHa of FP64, mixed, neural and neural+mixed over "
+                         "independent seeds on screened Ar and exit")
+    ap.add_argument("--seeds", type=int, default=8, help="independent runs per form for --tsigma")
+    ap.add_argument("--mfma-probe", action="store_true",
+                    help="only time the table's contraction as FP64 Y-dot and as BF16x3 MFMA (prototype) and exit")
     args = ap.parse_args()
     if args.source_hash:
         print(kernel_source_hash())
@@ -827,6 +1013,12 @@ def main():
         return
     if args.ascan:
         print(json.dumps(ascan()), flush=True)
+        return
+    if args.tsigma:
+        print(json.dumps(tsigma_bench(seeds=args.seeds)), flush=True)
+        return
+    if args.mfma_probe:
+        print(json.dumps(mfma_probe_bench()), flush=True)
         return
     if args.sweep:
         print(json.dumps(sweep()), flush=True)
