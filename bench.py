@@ -620,7 +620,7 @@ def mixed_bench(walkers=16384, gens=1200, seed=0):
 
 
 def tsigma_bench(seeds=8, walkers=16384, a=0.035, gens=1000, moves_per_electron=8.0, t_equil=2.0, seed0=0,
-                 rounds=8, train_steps=60, lr=1e-3, train_walkers=131072, step=0.25):
+                 rounds=8, train_steps=60, lr=1e-3, train_walkers=131072, step=0.25, first_seed=0, runs_out=None):
     """Time to sigma(E) = 1 mHa of four forms of the projection on the same
     physical system (Ar with screened hydrogenic orbitals in the Ar-like
     basis, a = 0.035 bohr, `walkers` walkers): Pade FP64, Pade with the
@@ -633,7 +633,10 @@ def tsigma_bench(seeds=8, walkers=16384, a=0.035, gens=1000, moves_per_electron=
     Per form: the means of c and v over the seeds with their standard errors;
     time to 1 mHa = mean(c) mean(v) / 1e-6; the ratio of FP64 to each form
     with a 95 % interval from the spread over seeds (delta method on log c
-    and log v).  The energies of the forms are compared with their errors."""
+    and log v).  The energies of the forms are compared with their errors.
+    first_seed: index of the first seed (so that the seeds can be split over
+    several calls); runs_out: a file that receives one JSON line per run as
+    it ends (tsigma_summary combines such files)."""
     import torch
     from paper_1909_01589_amd import inputs, neural, stats
     from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_set_precision, lrdmc_spacing
@@ -676,7 +679,7 @@ def tsigma_bench(seeds=8, walkers=16384, a=0.035, gens=1000, moves_per_electron=
         _, delta = start(net, 0)
         taus[net] = float(f"{moves_per_electron * N / delta:.3g}")
     runs = {f: [] for f, _, _ in forms}
-    for sd in range(seeds):
+    for sd in range(first_seed, first_seed + seeds):
         starts = {net: start(net, sd)[0] for net in (False, True)}
         for label, net, prec in forms:
             tau = taus[net]
@@ -694,10 +697,32 @@ def tsigma_bench(seeds=8, walkers=16384, a=0.035, gens=1000, moves_per_electron=
             E, sig = stats.estimate(rec["log_wbar"].cpu().numpy(), rec["ebar"].cpu().numpy(), p=None)
             ess = rec["ess"].cpu().numpy() / walkers
             T = gens * tau
-            runs[label].append(dict(seed=sd, E=E, sigma=sig, wall_s=wall, c=wall / T, v=sig * sig * T,
-                                    moves_per_s=float(rec["n_moves"].sum()) / wall, ess_min=float(ess.min())))
+            row = dict(form=label, seed=sd, tau=tau, generations=gens, E=E, sigma=sig, wall_s=wall, c=wall / T,
+                       v=sig * sig * T, moves_per_s=float(rec["n_moves"].sum()) / wall, ess_min=float(ess.min()))
+            runs[label].append(row)
+            if runs_out:
+                with open(runs_out, "a") as f:
+                    f.write(json.dumps(row) + "\n")
             g.close()
             note(f"{label} seed {sd}: E={E:.4f} +- {sig:.4f}, {wall:.1f} s")
+
+    res = tsigma_summarize(runs)
+    res.update(system=s.name, a=a, a_prime=ap, r_c=rc, walkers=walkers, generations=gens, seeds=seeds,
+               first_seed=first_seed, tau=dict(pade=taus[False], neural=taus[True]), train_wall_s=t_train,
+               wall_s=time.perf_counter() - t0)
+    for f, q in res["against_fp64"].items():
+        note(f"{f}: time-to-1mHa ratio FP64/{f} = {q['ratio']:.3f} [{q['ci95'][0]:.3f}, {q['ci95'][1]:.3f}], "
+             f"dE = {1e3 * q['dE']:.2f} +- {1e3 * q['dE_sigma']:.2f} mHa")
+    return {"tsigma": res}
+
+
+def tsigma_summarize(runs):
+    """Per form (runs: form -> list of per-run dicts with c, v, E, sigma):
+    means and standard errors of c and v, time to 1 mHa = mean(c) mean(v) /
+    1e-6, inverse-variance mean energy; against FP64 the time-to-1 mHa ratio
+    with a 95 % interval (delta method on log c and log v), the speed and
+    variance ratios and the energy difference."""
+    forms = ("fp64", "mixed", "neural", "neural+mixed")
 
     def summary(rs):
         c = np.array([r["c"] for r in rs])
@@ -714,10 +739,12 @@ def tsigma_bench(seeds=8, walkers=16384, a=0.035, gens=1000, moves_per_electron=
                     moves_per_s=float(np.mean([r["moves_per_s"] for r in rs])),
                     ess_min=float(min(r["ess_min"] for r in rs)))
 
-    summ = {f: summary(runs[f]) for f, _, _ in forms}
+    summ = {f: summary(runs[f]) for f in forms if runs.get(f)}
     base = summ["fp64"]
     comp = {}
-    for f, _, _ in forms[1:]:
+    for f in forms[1:]:
+        if f not in summ:
+            continue
         q = summ[f]
         ratio = base["time_to_1mHa_s"] / q["time_to_1mHa_s"]
         var_log = sum((x[k + "_se"] / x[k]) ** 2 for x in (base, q) for k in ("c", "v"))
@@ -725,11 +752,16 @@ def tsigma_bench(seeds=8, walkers=16384, a=0.035, gens=1000, moves_per_electron=
         comp[f] = dict(ratio=ratio, ci95=[ratio * float(np.exp(-half)), ratio * float(np.exp(half))],
                        speed_ratio=base["c"] / q["c"], variance_ratio=base["v"] / q["v"],
                        dE=q["E"] - base["E"], dE_sigma=float(np.hypot(q["E_sigma"], base["E_sigma"])))
-        note(f"{f}: time-to-1mHa ratio FP64/{f} = {ratio:.3f} [{comp[f]['ci95'][0]:.3f}, {comp[f]['ci95'][1]:.3f}], "
-             f"dE = {1e3 * comp[f]['dE']:.2f} +- {1e3 * comp[f]['dE_sigma']:.2f} mHa")
-    return {"tsigma": dict(system=s.name, a=a, a_prime=ap, r_c=rc, walkers=walkers, generations=gens,
-                           seeds=seeds, tau=dict(pade=taus[False], neural=taus[True]), train_wall_s=t_train,
-                           forms=summ, against_fp64=comp, runs=runs, wall_s=time.perf_counter() - t0)}
+        # paired by seed (same start walkers and random keys in both forms):
+        # the mean over seeds of log(c v)_fp64 - log(c v)_form
+        by_seed = {r["seed"]: r for r in runs["fp64"] if "seed" in r}
+        d = [np.log(by_seed[r["seed"]]["c"] * by_seed[r["seed"]]["v"] / (r["c"] * r["v"]))
+             for r in runs[f] if r.get("seed") in by_seed]
+        if len(d) >= 2:
+            m, se = float(np.mean(d)), float(np.std(d, ddof=1) / np.sqrt(len(d)))
+            comp[f]["paired"] = dict(ratio=float(np.exp(m)), ci95=[float(np.exp(m - 1.96 * se)),
+                                                                   float(np.exp(m + 1.96 * se))], seeds=len(d))
+    return dict(forms=summ, against_fp64=comp, runs=runs)
 
 
 def mfma_probe_bench(reps=10, names=("molecule", "zsweep54")):
@@ -977,6 +1009,7 @@ def main():
                     help="only time the Jastrow-parameter gradient kernel and exit")
     ap.add_argument("--neural", choices=["ar", "he"], default=None,
                     help="only run the learned-Jastrow comparison (VMC, training, LRDMC scan) and exit")
+    ap.add_argument("--neural-gens", type=int, default=1200, help="timed generations per spacing for --neural")
     ap.add_argument("--sweep", action="store_true",
                     help="only time every configured workload (Be-like, Ar-like, Z-sweep, molecule) and exit")
     ap.add_argument("--mixed", action="store_true",
@@ -991,11 +1024,25 @@ def main():
                     help="only measure the time to sigma(E) = 1 mHa of FP64, mixed, neural and neural+mixed over "
                          "independent seeds on screened Ar and exit")
     ap.add_argument("--seeds", type=int, default=8, help="independent runs per form for --tsigma")
+    ap.add_argument("--first-seed", type=int, default=0, help="first seed index for --tsigma")
+    ap.add_argument("--tsigma-gens", type=int, default=1000, help="generations per --tsigma run")
+    ap.add_argument("--runs-out", default=None, help="--tsigma: append one JSON line per run to this file")
+    ap.add_argument("--tsigma-summary", nargs="+", default=None, metavar="FILE",
+                    help="combine the per-run lines of --tsigma --runs-out files (no GPU) and exit")
     ap.add_argument("--mfma-probe", action="store_true",
                     help="only time the table's contraction as FP64 Y-dot and as BF16x3 MFMA (prototype) and exit")
     args = ap.parse_args()
     if args.source_hash:
         print(kernel_source_hash())
+        return
+    if args.tsigma_summary:
+        runs = {}
+        for path in args.tsigma_summary:
+            for line in open(path):
+                if line.strip():
+                    r = json.loads(line)
+                    runs.setdefault(r["form"], []).append(r)
+        print(json.dumps({"tsigma": tsigma_summarize(runs)}), flush=True)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -1015,7 +1062,8 @@ def main():
         print(json.dumps(ascan()), flush=True)
         return
     if args.tsigma:
-        print(json.dumps(tsigma_bench(seeds=args.seeds)), flush=True)
+        print(json.dumps(tsigma_bench(seeds=args.seeds, first_seed=args.first_seed, gens=args.tsigma_gens,
+                                      runs_out=args.runs_out)), flush=True)
         return
     if args.mfma_probe:
         print(json.dumps(mfma_probe_bench()), flush=True)
@@ -1033,7 +1081,7 @@ def main():
         print(json.dumps(zscan()), flush=True)
         return
     if args.neural:
-        print(json.dumps(neural_bench(args.neural)), flush=True)
+        print(json.dumps(neural_bench(args.neural, gens=args.neural_gens)), flush=True)
         return
     if args.jastrow_grad:
         print(json.dumps(jastrow_grad_bench()), flush=True)

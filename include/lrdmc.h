@@ -349,9 +349,16 @@ int32_t lrdmc_is_specialized(const lrdmc_ctx *ctx);
  * FP64; the local energy, the weights, the Sherman-Morrison updates and the
  * reconfiguration are unchanged.  The ratios then differ from FP64 by about
  * 1e-7 relative and at most by the factor exp(dJ),
- * dJ = 2^-20 (sum_j c_ij / b_ee + sum_I Z_I / b_en) (2.3e-5 for the 18-electron
- * atom of the benchmark), so move indices agree with the FP64 path only until
- * such a difference decides one; energies agree statistically.  Errors:
+ * dJ = 2^-20 (sum_j c_ij / b_ee + sum_I Z_I / b_en) (eta = 2.3e-5 for the 18-electron
+ * atom), so move indices agree with the FP64 path only until such a
+ * difference decides one.  Energy: the weights keep the FP64 local energy and
+ * only the rates T_m change, by factors 1 + d_m with |d_m| <= eta =
+ * exp(dJ) - 1; the perturbation of the importance-sampled Hamiltonian has
+ * zero column sums, so to first order the fixed-node energy moves by
+ * dE = -< sum_m d_m T_m (f(x'_m)/f(x) - 1) > over phi^2 (phi the lattice
+ * fixed-node ground state, f = phi/Psi): zero for an exact trial function
+ * and at most eta <Delta> max |f'/f - 1|, where the +/- moves cancel the
+ * part of f'/f - 1 that is first order in the spacing.  Errors:
  * LRDMC_EINVAL (NULL, mode outside 0..1). */
 int lrdmc_set_precision(lrdmc_ctx *ctx, int32_t mode);
 

@@ -38,6 +38,7 @@ constexpr int kMaxK = 512;    // basis functions
 constexpr int kMaxNuc = 64;
 constexpr int kMaxThreads = 256;
 constexpr int kMaxIter = 1 << 22;  // moves per walker and generation
+constexpr int kDphLdsBytes = 2048;  // derivative rows up to this size live in LDS (fixed-size kernels)
 
 // Internal kernel error codes (err[0]); err[1] holds the slot.
 enum { kErrSingular = 1, kErrNonFinite = 2, kErrIterCap = 3, kErrCollapse = 4 };
@@ -57,6 +58,7 @@ struct Layout {
     int red;    // [16]              reduction scratch
     int sc;     // [8]               block scalars
     int rng;    // [8][12]           rotations, -ln u1 and u2 of eight iterations
+    int dph;    // [N][dld]          derivative rows in LDS (small systems), or -1: in the HBM state blob
     // move-loop view of U: the weights and their prefix sums (table to search),
     // then the accepted-move temporaries
     int xs;     // [NT]              per-thread inclusive prefix of T within its wavefront
@@ -106,6 +108,10 @@ constexpr __host__ __device__ Layout make_layout(int N, int ns, int K, int Kp, i
     L.red = take(16);
     L.sc = take(8);
     L.rng = take(8 * 12);
+    // small systems keep the derivative rows in LDS during the generation
+    // (the accepted move reads and writes them; from HBM its three phases
+    // wait on their latency)
+    L.dph = (!yg && N * L.dld * (int)sizeof(double) <= kDphLdsBytes) ? take(N * L.dld) : -1;
     const int U = o;
     // move-loop view.  The prefix sums and weights live from the table to
     // the search, which some wavefronts finish while others already write
@@ -1290,7 +1296,7 @@ __device__ __forceinline__ double local_energy(const KArgs &A, const double *lds
 
 // One workgroup per walker slot: a generation of continuous-time projection,
 // or (eval != 0) the move table at frozen positions.
-template <bool CORR, bool YG, bool MX = false>
+template <bool CORR, bool YG, bool MX = false, bool DL = false>
 __device__ __forceinline__ void project_body(const KArgs &A)
 {
     extern __shared__ double lds[];
@@ -1324,7 +1330,10 @@ __device__ __forceinline__ void project_body(const KArgs &A)
     // LDS part: [Ainv, Jo + N) at blob offset N Kp (with Y in LDS, Y precedes
     // Ainv and is copied with it)
     const int lds0 = YG ? L.Ainv : L.Y, blob0 = YG ? N * A.Kp : 0;
-    double *dphi = A.state_out + (size_t)slot * A.state_len + A.dphi_at;
+    // derivative rows: in the state blob, or (DL) in LDS and copied to the
+    // blob at the end of the generation
+    double *dphi_blob = A.state_out + (size_t)slot * A.state_len + A.dphi_at;
+    double *dphi = DL ? lds + L.dph : dphi_blob;
     if (A.state_in && !A.eval) {
         const double *sb = A.state_in + (size_t)src * A.state_len;
         if (YG) {
@@ -1479,6 +1488,8 @@ __device__ __forceinline__ void project_body(const KArgs &A)
     if (A.save_state) {
         double *sb = A.state_out + (size_t)slot * A.state_len;
         for (int t = tid; t < blob - blob0; t += NT) sb[blob0 + t] = lds[lds0 + t];
+        if (DL)
+            for (int t = tid; t < N * L.dld; t += NT) dphi_blob[t] = dphi[t];
         if (tid == 0) {
             sb[blob] = EL;
             sb[blob + 1] = V;
@@ -1526,7 +1537,7 @@ project_kernel_fixed(KArgs A)
     constexpr Layout L = make_layout(S::N, S::ns, KB, S::Kp, S::M, NNUC, S::NT, 0);
     A.N = S::N; A.n_up = NUP; A.n_dn = NDN; A.ns = S::ns; A.K = KB; A.Kp = S::Kp; A.M = S::M;
     A.n_nuc = NNUC; A.nt = S::NT; A.mpe = 12; A.L = L;
-    project_body<CORR, false>(A);
+    project_body<CORR, false, false, (L.dph >= 0)>(A);
 }
 
 template <int NUP, int NDN, int KB, int NNUC, bool CORR>
@@ -1537,7 +1548,7 @@ project_kernel_fixed_mx(KArgs A)
     constexpr Layout L = make_layout(S::N, S::ns, KB, S::Kp, S::M, NNUC, S::NT, 0);
     A.N = S::N; A.n_up = NUP; A.n_dn = NDN; A.ns = S::ns; A.K = KB; A.Kp = S::Kp; A.M = S::M;
     A.n_nuc = NNUC; A.nt = S::NT; A.mpe = 12; A.L = L;
-    project_body<CORR, false, true>(A);
+    project_body<CORR, false, true, (L.dph >= 0)>(A);
 }
 
 // Derivatives with respect to the Pade parameters theta = (b_ee, b_en) of
