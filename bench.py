@@ -179,7 +179,8 @@ def jastrow_grad_bench(name="ar_a0.1", reps=50):
 
 
 def neural_bench(system="ar", walkers=16384, rounds=8, train_steps=60, lr=1e-3, gens=1200, seed=0,
-                 train_walkers=131072):
+                 train_walkers=131072, spacings=None, forms=("pade", "neural"), gens_inverse_a=False,
+                 runs_out=None):
     """Learned Jastrow correction against the Pade trial function alone.
     Metropolis samples of |Psi_Pade|^2 (lrdmc_vmc), rounds of variance
     minimisation of the 2 x 64 SiLU networks (tabulated on 257 nodes up to
@@ -193,18 +194,25 @@ def neural_bench(system="ar", walkers=16384, rounds=8, train_steps=60, lr=1e-3, 
     bias of LRDMC depends on the trial function; the fixed-node limits must
     agree, the determinant and hence the nodes being the same).
     system "ar": Ar with screened hydrogenic orbitals in the Ar-like basis;
-    "he": He with a nodeless s orbital (fixed node exact)."""
+    "he": He with a nodeless s orbital (fixed node exact).
+    spacings: override the spacings; forms: the trial functions to run
+    ("pade", "neural"); gens_inverse_a: `gens` at the largest spacing and
+    gens x a_max / a at the others (the projection time per generation
+    shrinks as a^2); runs_out: a file that receives one JSON line per LRDMC
+    run (neural_summary combines such files)."""
     import torch
     from paper_1909_01589_amd import inputs, neural, stats
     from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_spacing
     if system == "ar":
-        s, spacings, step, E_ref = inputs.ar_screened(), (0.06, 0.045, 0.035, 0.025, 0.0175), 0.25, None
+        s, sp0, step, E_ref = inputs.ar_screened(), (0.06, 0.045, 0.035, 0.025, 0.0175), 0.25, None
         moves_per_electron, t_equil = 8.0, 2.0
     elif system == "he":
-        s, spacings, step, E_ref = inputs.helium_nodeless(), (0.25, 0.15, 0.1), 0.6, HE_EXACT
+        s, sp0, step, E_ref = inputs.helium_nodeless(), (0.25, 0.15, 0.1), 0.6, HE_EXACT
         moves_per_electron, t_equil = 20.0, 10.0
     else:
         raise ValueError(system)
+    spacings = tuple(spacings) if spacings else sp0
+    a_max = max(spacings)
     Z, N = s.z_max, s.n_elec
     pos0 = inputs.initial_walkers(s, walkers, seed)
     t0 = time.perf_counter()
@@ -230,11 +238,14 @@ def neural_bench(system="ar", walkers=16384, rounds=8, train_steps=60, lr=1e-3, 
 
     vmc_pade = spread()
     nj = neural.NeuralJastrow(64, 257, 6.0, seed=seed)
-    t_train = time.perf_counter()
-    hist = neural.fit_vmc(nj, g, rounds=rounds, steps=train_steps, lr=lr, vmc_steps=300, step=step,
-                          log=lambda r: note(f"round {r['round']}: VMC E={r['vmc_E']:.4f} var={r['vmc_var']:.3f}"))
-    t_train = time.perf_counter() - t_train
-    vmc_neural = spread()
+    hist, t_train, vmc_neural = [], 0.0, None
+    if "neural" in forms:
+        t_train = time.perf_counter()
+        hist = neural.fit_vmc(nj, g, rounds=rounds, steps=train_steps, lr=lr, vmc_steps=300, step=step,
+                              log=lambda r: note(f"round {r['round']}: VMC E={r['vmc_E']:.4f} "
+                                                 f"var={r['vmc_var']:.3f}"))
+        t_train = time.perf_counter() - t_train
+        vmc_neural = spread()
     g.close()
 
     def projection(with_net, a):
@@ -254,41 +265,62 @@ def neural_bench(system="ar", walkers=16384, rounds=8, train_steps=60, lr=1e-3, 
             nj.attach(g)
         g.set_walkers(p, 0)
         g.run(int(t_equil / tau) + 20)
+        n_gen = int(round(gens * a_max / a)) if gens_inverse_a else gens
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        out = g.run(gens)
+        out = g.run(n_gen)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
         E, sig = stats.estimate(out["log_wbar"].cpu().numpy(), out["ebar"].cpu().numpy(), p=None)
         moves = int(out["n_moves"].sum())
         g.close()
-        row = dict(a=a, a_prime=ap, r_c=rc, tau=tau, generations=gens, E=E, sigma=sig, wall_s=dt,
-                   moves_per_s=moves / dt, t_1mHa_s=dt * (sig / 1e-3) ** 2)
-        note(f"{'neural' if with_net else 'pade'} a={a}: E={E:.5f} +- {sig:.5f} t(1mHa)={row['t_1mHa_s']:.1f}s")
+        row = dict(form="neural" if with_net else "pade", a=a, a_prime=ap, r_c=rc, tau=tau, generations=n_gen, E=E,
+                   sigma=sig, wall_s=dt, moves_per_s=moves / dt, t_1mHa_s=dt * (sig / 1e-3) ** 2)
+        if runs_out:
+            with open(runs_out, "a") as f:
+                f.write(json.dumps(row) + "\n")
+        note(f"{row['form']} a={a}: E={E:.5f} +- {sig:.5f} t(1mHa)={row['t_1mHa_s']:.1f}s")
         return row
 
-    res = {}
+    rows = []
     for label, net in (("pade", False), ("neural", True)):
-        rows = [projection(net, a) for a in spacings]
-        a_, E_, s_ = [r["a"] for r in rows], [r["E"] for r in rows], [r["sigma"] for r in rows]
-        if len(rows) >= 4:
+        if label in forms:
+            rows += [projection(net, a) for a in spacings]
+    out = neural_summarize(rows)
+    out.update({
+        "system": s.name, "walkers": walkers, "training_walkers": train_walkers,
+        "network": "2 x 64 SiLU per pair type, 257-node table, r_cut 6",
+        "training": dict(rounds=rounds, steps_per_round=train_steps, lr=lr, wall_s=t_train, history=hist),
+        "vmc": dict(pade=vmc_pade, neural=vmc_neural), "reference_E": E_ref, "wall_s": time.perf_counter() - t0})
+    return {"neural": out}
+
+
+def neural_summarize(rows):
+    """Per trial function (rows: per-run dicts with form, a, E, sigma,
+    t_1mHa_s) the fit of E(a) (E0 + k1 a^2 + k2 a^4 from four spacings on,
+    else E0 + k1 a^2) and, with both forms, the difference of the limits
+    and the time-to-1 mHa ratios at the common spacings."""
+    res = {}
+    for label in ("pade", "neural"):
+        rs = sorted((r for r in rows if r["form"] == label), key=lambda r: -r["a"])
+        if not rs:
+            continue
+        a_, E_, s_ = [r["a"] for r in rs], [r["E"] for r in rs], [r["sigma"] for r in rs]
+        if len(rs) >= 4:
             E0, s0, chi2 = _fit_e0(a_, E_, s_)           # E0 + k1 a^2 + k2 a^4
             fit = "E0 + k1 a^2 + k2 a^4"
         else:
             E0, s0, chi2 = _fit_e0_linear(a_, E_, s_)    # E0 + k1 a^2
             fit = "E0 + k1 a^2"
-        res[label] = dict(rows=rows, fit=fit, E0=E0, sigma_E0=s0, chi2_dof=chi2)
-    ratios = [p["t_1mHa_s"] / q["t_1mHa_s"] for p, q in zip(res["pade"]["rows"], res["neural"]["rows"])]
-    dE0 = res["neural"]["E0"] - res["pade"]["E0"]
-    return {"neural": {
-        "system": s.name, "walkers": walkers, "training_walkers": train_walkers,
-        "network": "2 x 64 SiLU per pair type, 257-node table, r_cut 6",
-        "training": dict(rounds=rounds, steps_per_round=train_steps, lr=lr, wall_s=t_train, history=hist),
-        "vmc": dict(pade=vmc_pade, neural=vmc_neural),
-        "lrdmc": res, "time_to_1mHa_ratio_pade_over_neural": ratios,
-        "E0_difference": dE0, "E0_difference_sigma": float(np.hypot(res["pade"]["sigma_E0"],
-                                                                     res["neural"]["sigma_E0"])),
-        "reference_E": E_ref, "wall_s": time.perf_counter() - t0}}
+        res[label] = dict(rows=rs, fit=fit, E0=E0, sigma_E0=s0, chi2_dof=chi2)
+    out = {"lrdmc": res}
+    if "pade" in res and "neural" in res:
+        by_a = {r["a"]: r for r in res["neural"]["rows"]}
+        out["time_to_1mHa_ratio_pade_over_neural"] = {str(r["a"]): r["t_1mHa_s"] / by_a[r["a"]]["t_1mHa_s"]
+                                                     for r in res["pade"]["rows"] if r["a"] in by_a}
+        out["E0_difference"] = res["neural"]["E0"] - res["pade"]["E0"]
+        out["E0_difference_sigma"] = float(np.hypot(res["pade"]["sigma_E0"], res["neural"]["sigma_E0"]))
+    return out
 
 
 def _fit_e0_linear(a, E, sig):
@@ -1010,6 +1042,13 @@ def main():
     ap.add_argument("--neural", choices=["ar", "he"], default=None,
                     help="only run the learned-Jastrow comparison (VMC, training, LRDMC scan) and exit")
     ap.add_argument("--neural-gens", type=int, default=1200, help="timed generations per spacing for --neural")
+    ap.add_argument("--neural-spacings", type=float, nargs="+", default=None, help="spacings for --neural")
+    ap.add_argument("--neural-forms", nargs="+", default=["pade", "neural"], choices=["pade", "neural"],
+                    help="trial functions for --neural")
+    ap.add_argument("--neural-gens-inverse-a", action="store_true",
+                    help="--neural: --neural-gens at the largest spacing, scaled as 1/a at the others")
+    ap.add_argument("--neural-summary", nargs="+", default=None, metavar="FILE",
+                    help="fit the per-run lines of --neural --runs-out files (no GPU) and exit")
     ap.add_argument("--sweep", action="store_true",
                     help="only time every configured workload (Be-like, Ar-like, Z-sweep, molecule) and exit")
     ap.add_argument("--mixed", action="store_true",
@@ -1034,6 +1073,10 @@ def main():
     args = ap.parse_args()
     if args.source_hash:
         print(kernel_source_hash())
+        return
+    if args.neural_summary:
+        rows = [json.loads(line) for path in args.neural_summary for line in open(path) if line.strip()]
+        print(json.dumps({"neural": neural_summarize(rows)}), flush=True)
         return
     if args.tsigma_summary:
         runs = {}
@@ -1081,7 +1124,9 @@ def main():
         print(json.dumps(zscan()), flush=True)
         return
     if args.neural:
-        print(json.dumps(neural_bench(args.neural, gens=args.neural_gens)), flush=True)
+        print(json.dumps(neural_bench(args.neural, gens=args.neural_gens, spacings=args.neural_spacings,
+                                      forms=tuple(args.neural_forms), gens_inverse_a=args.neural_gens_inverse_a,
+                                      runs_out=args.runs_out)), flush=True)
         return
     if args.jastrow_grad:
         print(json.dumps(jastrow_grad_bench()), flush=True)

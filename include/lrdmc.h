@@ -188,6 +188,16 @@ int lrdmc_run(lrdmc_ctx *ctx, int32_t n_gen, void *stream, double *log_wbar,
 int lrdmc_get_walkers(lrdmc_ctx *ctx, double *pos, double *log_w, double *e_loc,
                       int32_t *n_moves, void *stream);
 
+/* Check of the Sherman-Morrison-carried state (a diagnostic): for every
+ * walker slot, res[s] (device [W]) = max |(A Ainv - I)_ik| over both spins,
+ * with A recomputed from the walker's current positions and Ainv the inverse
+ * stored in its state, carried by rank-one updates since the last refresh
+ * (the survey's check of ||A Ainv - I|| after the updates).  After a
+ * reconfiguration slot s reports the walker it selected.  Synchronizes the
+ * stream.  Errors: LRDMC_EINVAL (NULL; refresh <= 1 or no projection since the
+ * walkers were set, so no state is stored), LRDMC_EDEVICE. */
+int lrdmc_inverse_residual(lrdmc_ctx *ctx, double *res, void *stream);
+
 /* Evaluate the move table at frozen positions pos[W][N][3] without moving:
  * rho[W][M] = Psi(x'_m)/Psi(x), k[W][M] = hopping coefficient of move m,
  * M = 12 N, and diag[W][LRDMC_NDIAG] =

@@ -2140,6 +2140,60 @@ __global__ void __launch_bounds__(1024) reconfigure_kernel(const double *logw, c
     }
 }
 
+// Residual of the inverse Slater matrices carried in the walker state: for
+// walker slot s (its source src[s] after a reconfiguration), A is recomputed
+// from the positions (A[i][j] = phi_j(r_i), phi_j = sum_mu C[mu][j] g_mu)
+// and res[s] = max |(A Ainv - I)_ik| over both spins, with Ainv the one the
+// Sherman-Morrison updates have carried since the last refresh.  One
+// workgroup of 64 threads per slot; LDS: g[K] and phi[N][ns].
+__global__ void __launch_bounds__(64) inverse_residual_kernel(const double *pos, const double *state,
+                                                              const int *src, int W, int N, int n_up,
+                                                              int ns, int K, int state_len, int ainv_at,
+                                                              const FnDesc *fns, const double *moT,
+                                                              double *res)
+{
+    extern __shared__ double sm[];
+    double *g = sm, *phi = sm + K;
+    const int s = blockIdx.x, tid = threadIdx.x;
+    if (s >= W) return;
+    const int j0 = src ? src[s] : s;
+    const double *p = pos + (size_t)j0 * 3 * N;
+    for (int i = 0; i < N; ++i) {
+        const double r0 = p[3 * i], r1 = p[3 * i + 1], r2 = p[3 * i + 2];
+        for (int mu = tid; mu < K; mu += 64) {
+            const FnDesc F = fns[mu];
+            const double dx = r0 - F.R[0], dy = r1 - F.R[1], dz = r2 - F.R[2];
+            double P = 1.0;
+            if (F.l == 1) P = F.comp == 0 ? dx : (F.comp == 1 ? dy : dz);
+            else if (F.l == 2)
+                P = F.comp == 0 ? dx * dy : F.comp == 1 ? dy * dz : F.comp == 2 ? dz * dx
+                  : F.comp == 3 ? dx * dx - dy * dy : 2.0 * dz * dz - dx * dx - dy * dy;
+            g[mu] = P * exp(-F.alpha * (dx * dx + dy * dy + dz * dz));
+        }
+        __syncthreads();
+        for (int j = tid; j < ns; j += 64) {
+            double acc = 0.0;
+            for (int mu = 0; mu < K; ++mu) acc += moT[j * K + mu] * g[mu];
+            phi[i * ns + j] = acc;
+        }
+        __syncthreads();
+    }
+    const double *ainv = state + (size_t)j0 * state_len + ainv_at;
+    double worst = 0.0;
+    for (int t = tid; t < 2 * ns * ns; t += 64) {
+        const int sg = t / (ns * ns), i = (t / ns) % ns, k = t % ns;
+        const int n = sg ? N - n_up : n_up;
+        if (i >= n || k >= n) continue;
+        const double *ai = ainv + sg * ns * ns;
+        const int e = (sg ? n_up : 0) + i;
+        double acc = 0.0;
+        for (int j = 0; j < n; ++j) acc += phi[e * ns + j] * ai[j * ns + k];
+        worst = fmax(worst, fabs(acc - (i == k ? 1.0 : 0.0)));
+    }
+    for (int off = 32; off > 0; off >>= 1) worst = fmax(worst, __shfl_xor(worst, off, 64));
+    if (tid == 0) res[s] = worst;
+}
+
 // Copies selected by a reconfiguration into caller buffers.
 __global__ void gather_kernel(const double *pos, const double *el, const int *idx, int W, int stride,
                               double *pos_out, double *el_out, double *lw_out, int *nm_out)
@@ -2813,6 +2867,24 @@ int lrdmc_get_walkers(lrdmc_ctx *c, double *pos, double *log_w, double *e_loc, i
         if (e_loc) HIP_TRY(c, hipMemcpyAsync(e_loc, c->d_el, sizeof(double) * W, hipMemcpyDeviceToDevice, st));
         if (n_moves) HIP_TRY(c, hipMemcpyAsync(n_moves, c->d_nmov, sizeof(int) * W, hipMemcpyDeviceToDevice, st));
     }
+    HIP_TRY(c, hipStreamSynchronize(st));
+    return LRDMC_OK;
+}
+
+int lrdmc_inverse_residual(lrdmc_ctx *c, double *res, void *stream)
+{
+    if (!c || !res) return fail(c, LRDMC_EINVAL, "lrdmc_inverse_residual: NULL argument");
+    if (!c->loaded || !c->state_ok || c->prm.refresh <= 1)
+        return fail(c, LRDMC_EINVAL, "lrdmc_inverse_residual: no stored walker state (needs refresh > 1 and a "
+                                     "projection since the walkers were set)");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t lds = sizeof(double) * ((size_t)c->K + (size_t)c->N * c->ns);
+    // Ainv sits after Y in the state blob (the blob format of every layout)
+    const int ainv_at = c->N * c->Kp;
+    hipLaunchKernelGGL(inverse_residual_kernel, dim3(c->W), dim3(64), lds, st, c->d_pos[c->cur], c->d_state[c->cur],
+                       c->pending ? c->d_idx : nullptr, c->W, c->N, c->n_up, c->ns, c->K, c->state_len, ainv_at,
+                       c->d_fn, c->d_mo, res);
+    HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipStreamSynchronize(st));
     return LRDMC_OK;
 }

@@ -57,7 +57,7 @@ class lrdmc_params(C.Structure):
 _lib = None
 EXPORTS = ("lrdmc_spacing", "lrdmc_spacing_pade", "lrdmc_create", "lrdmc_set_walkers", "lrdmc_project", "lrdmc_branch",
            "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure",
-           "lrdmc_reconfigure_noalloc", "lrdmc_jastrow_grad", "lrdmc_set_jastrow", "lrdmc_set_jastrow_table", "lrdmc_jastrow_table_grad",
+           "lrdmc_reconfigure_noalloc", "lrdmc_inverse_residual", "lrdmc_jastrow_grad", "lrdmc_set_jastrow", "lrdmc_set_jastrow_table", "lrdmc_jastrow_table_grad",
            "lrdmc_vmc", "lrdmc_net_param_count", "lrdmc_net_workspace_size", "lrdmc_net_tabulate", "lrdmc_net_tabulate_backward",
            "lrdmc_use_generic", "lrdmc_is_specialized", "lrdmc_set_precision", "lrdmc_set_timing", "lrdmc_timing",
            "lrdmc_set_collapse_threshold", "lrdmc_set_move_cap", "lrdmc_generation",
@@ -84,6 +84,7 @@ def load():
     lib.lrdmc_eval_moves.argtypes = [P, P, P, P, P, P]
     lib.lrdmc_reconfigure.argtypes = [P, P, I32, D, P, P, P]
     lib.lrdmc_reconfigure_noalloc.argtypes = [P, P, I32, D, P, P, P]
+    lib.lrdmc_inverse_residual.argtypes = [P, P, P]
     lib.lrdmc_jastrow_grad.argtypes = [P, P, P, P]
     lib.lrdmc_set_jastrow.argtypes = [P, D, D]
     lib.lrdmc_set_jastrow_table.argtypes = [P, P, I32, D, I32, P]
@@ -111,7 +112,7 @@ def load():
     lib.lrdmc_destroy.restype = None
     for name in ("lrdmc_spacing", "lrdmc_spacing_pade", "lrdmc_create", "lrdmc_set_walkers", "lrdmc_project", "lrdmc_branch",
                  "lrdmc_run", "lrdmc_get_walkers", "lrdmc_eval_moves", "lrdmc_reconfigure",
-                 "lrdmc_reconfigure_noalloc", "lrdmc_jastrow_grad", "lrdmc_set_jastrow", "lrdmc_set_jastrow_table",
+                 "lrdmc_reconfigure_noalloc", "lrdmc_inverse_residual", "lrdmc_jastrow_grad", "lrdmc_set_jastrow", "lrdmc_set_jastrow_table",
                  "lrdmc_jastrow_table_grad", "lrdmc_vmc", "lrdmc_net_tabulate", "lrdmc_net_tabulate_backward",
                  "lrdmc_use_generic", "lrdmc_set_precision", "lrdmc_set_collapse_threshold", "lrdmc_set_move_cap",
                  "lrdmc_set_timing",
@@ -240,6 +241,11 @@ def lrdmc_reconfigure_noalloc(log_w, e_loc, xi: float, idx, stats=None, stream=N
     _check(load().lrdmc_reconfigure_noalloc(_dptr(log_w, torch.float64), _dptr(e_loc, torch.float64),
                                             W, float(xi), _dptr(idx, torch.int32),
                                             _dptr(stats, torch.float64), _stream(stream)))
+
+
+def lrdmc_inverse_residual(ctx, res, stream=None):
+    """res[W] (device float64) = max |A Ainv - I| of each walker's carried inverse."""
+    _check(load().lrdmc_inverse_residual(ctx, _dptr(res, torch.float64), _stream(stream)), ctx)
 
 
 def lrdmc_jastrow_grad(ctx, pos, out, stream=None):

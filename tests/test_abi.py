@@ -140,3 +140,4 @@ def test_context_entry_points_reject_null(lib):
     assert lib.lrdmc_is_specialized(None) == 0
     assert lib.lrdmc_set_collapse_threshold(None, 0.01) == -1
     assert lib.lrdmc_set_move_cap(None, 10) == -1
+    assert lib.lrdmc_inverse_residual(None, dummy, None) == -1
