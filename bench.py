@@ -180,7 +180,7 @@ def jastrow_grad_bench(name="ar_a0.1", reps=50):
 
 def neural_bench(system="ar", walkers=16384, rounds=8, train_steps=60, lr=1e-3, gens=1200, seed=0,
                  train_walkers=131072, spacings=None, forms=("pade", "neural"), gens_inverse_a=False,
-                 runs_out=None):
+                 runs_out=None, t_equil=None, t_prod=None):
     """Learned Jastrow correction against the Pade trial function alone.
     Metropolis samples of |Psi_Pade|^2 (lrdmc_vmc), rounds of variance
     minimisation of the 2 x 64 SiLU networks (tabulated on 257 nodes up to
@@ -198,19 +198,24 @@ def neural_bench(system="ar", walkers=16384, rounds=8, train_steps=60, lr=1e-3, 
     spacings: override the spacings; forms: the trial functions to run
     ("pade", "neural"); gens_inverse_a: `gens` at the largest spacing and
     gens x a_max / a at the others (the projection time per generation
-    shrinks as a^2); runs_out: a file that receives one JSON line per LRDMC
-    run (neural_summary combines such files)."""
+    shrinks as a^2); t_prod: instead, the same projection time (Ha^-1) at
+    every spacing; t_equil: projection time discarded before the timed
+    production (default 2 Ha^-1 for Ar, 10 for He); runs_out: a file that
+    receives one JSON line per LRDMC run (neural_summarize combines such
+    files).  Each run also records the energies of the two halves of its
+    production (a check that the discarded part was long enough)."""
     import torch
     from paper_1909_01589_amd import inputs, neural, stats
     from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_spacing
     if system == "ar":
         s, sp0, step, E_ref = inputs.ar_screened(), (0.06, 0.045, 0.035, 0.025, 0.0175), 0.25, None
-        moves_per_electron, t_equil = 8.0, 2.0
+        moves_per_electron, t_equil0 = 8.0, 2.0
     elif system == "he":
         s, sp0, step, E_ref = inputs.helium_nodeless(), (0.25, 0.15, 0.1), 0.6, HE_EXACT
-        moves_per_electron, t_equil = 20.0, 10.0
+        moves_per_electron, t_equil0 = 20.0, 10.0
     else:
         raise ValueError(system)
+    t_equil = t_equil0 if t_equil is None else float(t_equil)
     spacings = tuple(spacings) if spacings else sp0
     a_max = max(spacings)
     Z, N = s.z_max, s.n_elec
@@ -264,22 +269,41 @@ def neural_bench(system="ar", walkers=16384, rounds=8, train_steps=60, lr=1e-3, 
         if with_net:
             nj.attach(g)
         g.set_walkers(p, 0)
-        g.run(int(t_equil / tau) + 20)
+        form = "neural" if with_net else "pade"
+        chunk = max(1, int(round(2.0 / tau)))          # 2 Ha^-1 of projection per call
+        n_eq = int(t_equil / tau) + 20
+        for c0 in range(0, n_eq, chunk):
+            g.run(min(chunk, n_eq - c0))
         n_gen = int(round(gens * a_max / a)) if gens_inverse_a else gens
+        if t_prod is not None:
+            n_gen = int(round(t_prod / tau))
+        note(f"{form} a={a}: {n_eq} generations discarded, {n_gen} timed")
+        parts = []
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        out = g.run(n_gen)
-        torch.cuda.synchronize()
+        t_note = t1
+        for c0 in range(0, n_gen, 4 * chunk):
+            parts.append(g.run(min(4 * chunk, n_gen - c0)))
+            torch.cuda.synchronize()
+            if time.perf_counter() - t_note > 30.0:
+                t_note = time.perf_counter()
+                note(f"  {min(n_gen, c0 + 4 * chunk)} of {n_gen} generations")
         dt = time.perf_counter() - t1
-        E, sig = stats.estimate(out["log_wbar"].cpu().numpy(), out["ebar"].cpu().numpy(), p=None)
-        moves = int(out["n_moves"].sum())
+        lw = torch.cat([q["log_wbar"] for q in parts]).cpu().numpy()
+        eb = torch.cat([q["ebar"] for q in parts]).cpu().numpy()
+        E, sig = stats.estimate(lw, eb, p=None)
+        h = n_gen // 2
+        halves = [stats.estimate(lw[:h], eb[:h], p=None), stats.estimate(lw[h:], eb[h:], p=None)]
+        moves = int(sum(int(q["n_moves"].sum()) for q in parts))
         g.close()
-        row = dict(form="neural" if with_net else "pade", a=a, a_prime=ap, r_c=rc, tau=tau, generations=n_gen, E=E,
-                   sigma=sig, wall_s=dt, moves_per_s=moves / dt, t_1mHa_s=dt * (sig / 1e-3) ** 2)
+        row = dict(form=form, a=a, a_prime=ap, r_c=rc, tau=tau, generations=n_gen, E=E,
+                   sigma=sig, wall_s=dt, moves_per_s=moves / dt, t_1mHa_s=dt * (sig / 1e-3) ** 2,
+                   t_equil=t_equil, t_prod=n_gen * tau, E_halves=[list(x) for x in halves])
         if runs_out:
             with open(runs_out, "a") as f:
                 f.write(json.dumps(row) + "\n")
-        note(f"{row['form']} a={a}: E={E:.5f} +- {sig:.5f} t(1mHa)={row['t_1mHa_s']:.1f}s")
+        note(f"{form} a={a}: E={E:.5f} +- {sig:.5f} t(1mHa)={row['t_1mHa_s']:.1f}s, halves "
+             f"{halves[0][0]:.5f} +- {halves[0][1]:.5f} and {halves[1][0]:.5f} +- {halves[1][1]:.5f}")
         return row
 
     rows = []
@@ -1047,6 +1071,10 @@ def main():
                     help="trial functions for --neural")
     ap.add_argument("--neural-gens-inverse-a", action="store_true",
                     help="--neural: --neural-gens at the largest spacing, scaled as 1/a at the others")
+    ap.add_argument("--neural-equil", type=float, default=None,
+                    help="--neural: projection time (Ha^-1) discarded before each timed run")
+    ap.add_argument("--neural-time", type=float, default=None,
+                    help="--neural: projection time (Ha^-1) of every timed run (instead of generations)")
     ap.add_argument("--neural-summary", nargs="+", default=None, metavar="FILE",
                     help="fit the per-run lines of --neural --runs-out files (no GPU) and exit")
     ap.add_argument("--sweep", action="store_true",
@@ -1126,7 +1154,8 @@ def main():
     if args.neural:
         print(json.dumps(neural_bench(args.neural, gens=args.neural_gens, spacings=args.neural_spacings,
                                       forms=tuple(args.neural_forms), gens_inverse_a=args.neural_gens_inverse_a,
-                                      runs_out=args.runs_out)), flush=True)
+                                      runs_out=args.runs_out, t_equil=args.neural_equil,
+                                      t_prod=args.neural_time)), flush=True)
         return
     if args.jastrow_grad:
         print(json.dumps(jastrow_grad_bench()), flush=True)

@@ -343,11 +343,117 @@ __device__ __forceinline__ void chain_dot2(unsigned long long fl, int len, const
     }
 }
 
+// One group of chain_dot2_pf with its shell flags F (s, p, d) fixed at
+// compile time: all of its loads of y issue together, then the same
+// arithmetic in the same order as chain_dot2.  Returns the group's size.
+template <int F>
+__device__ __forceinline__ int group_dot2(const double *yq, double ax, double ay, double az, double bx,
+                                          double by, double bz, double &pa, double &pb)
+{
+    constexpr int os = 0, op = (F & 1), od = op + ((F & 2) ? 3 : 0);
+    double v[9];
+    if (F & 1) v[0] = yq[os];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+        if (F & 2) v[1 + j] = yq[op + j];
+#pragma unroll
+    for (int j = 0; j < 5; ++j)
+        if (F & 4) v[4 + j] = yq[od + j];
+    pa = 0.0;
+    pb = 0.0;
+    if (F & 1) {
+        pa += v[0];
+        pb += v[0];
+    }
+    if (F & 2) {
+        pa += ax * v[1] + ay * v[2] + az * v[3];
+        pb += bx * v[1] + by * v[2] + bz * v[3];
+    }
+    if (F & 4) {
+        pa += ax * ay * v[4] + ay * az * v[5] + az * ax * v[6] + (ax * ax - ay * ay) * v[7] +
+              (2.0 * az * az - ax * ax - ay * ay) * v[8];
+        pb += bx * by * v[4] + by * bz * v[5] + bz * bx * v[6] + (bx * bx - by * by) * v[7] +
+              (2.0 * bz * bz - bx * bx - by * by) * v[8];
+    }
+    return od + ((F & 4) ? 5 : 0);
+}
+
+// Exponential of the next group of a chain from the current one.
+template <int CODE>
+__device__ __forceinline__ void chain_step(double &ea, double &eb)
+{
+    if (CODE == 3) {
+        ea = ea * ea * ea;
+        eb = eb * eb * eb;
+    } else if (CODE == 2) {
+        const double sa = sqrt_chain(ea), sb = sqrt_chain(eb);
+        ea = (ea * ea) * sa;
+        eb = (eb * eb) * sb;
+    } else if (CODE == 1) {
+        ea = ea * ea;
+        eb = eb * eb;
+    }
+}
+
+// chain_dot2 with y in device memory: each group's loads issue together at
+// its start, in a block of their own for each combination of shells, and
+// (TAIL) a trailing run of at least two s-only groups loads four values at
+// a time (one wait per block instead of one per shell).  Same arithmetic,
+// in the same order, as chain_dot2.
+template <int CODE, bool TAIL>
+__device__ __forceinline__ void chain_dot2_pf(unsigned long long fl, int len, const double *yq, double ax,
+                                              double ay, double az, double bx, double by, double bz, double ea,
+                                              double eb, double &acc_a, double &acc_b)
+{
+    // first group of the trailing s-only run
+    int q1 = len;
+    if (TAIL) {
+        while (q1 > 0 && ((int)(fl >> (3 * (q1 - 1))) & 7) == 1) --q1;
+        if (len - q1 < 2) q1 = len;
+    }
+    for (int q = 0; q < q1; ++q) {
+        const int f = (int)(fl >> (3 * q)) & 7;
+        double pa = 0.0, pb = 0.0;
+        switch (f) {
+        case 2: yq += group_dot2<2>(yq, ax, ay, az, bx, by, bz, pa, pb); break;
+        case 3: yq += group_dot2<3>(yq, ax, ay, az, bx, by, bz, pa, pb); break;
+        case 4: yq += group_dot2<4>(yq, ax, ay, az, bx, by, bz, pa, pb); break;
+        case 5: yq += group_dot2<5>(yq, ax, ay, az, bx, by, bz, pa, pb); break;
+        case 6: yq += group_dot2<6>(yq, ax, ay, az, bx, by, bz, pa, pb); break;
+        case 7: yq += group_dot2<7>(yq, ax, ay, az, bx, by, bz, pa, pb); break;
+        default: yq += group_dot2<1>(yq, ax, ay, az, bx, by, bz, pa, pb); break;
+        }
+        acc_a += ea * pa;
+        acc_b += eb * pb;
+        if (q + 1 == len) return;
+        chain_step<CODE>(ea, eb);
+    }
+    for (int q = q1; q < len; q += 4) {
+        const int nb = min(4, len - q);
+        double v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = yq[min(j, nb - 1)];
+        yq += nb;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (j < nb) {
+                acc_a += ea * (0.0 + v[j]);
+                acc_b += eb * (0.0 + v[j]);
+                if (q + j + 1 < len) chain_step<CODE>(ea, eb);
+            }
+        }
+    }
+}
+
 // sum_mu g_mu(r) y[mu] at the two points ra, rb of a +/- move pair of one
 // electron (y: its orbital-projected inverse row): the determinant ratios of
 // the two moves.  Along a chain the exponential of the next group is a power
 // of the current one (e^2, e^2 sqrt(e), e^3 for beta = 2, 2.5, 3), so a chain
-// costs one exp per point; both points share the loads of y.
+// costs one exp per point; both points share the loads of y.  PF: y is in
+// device memory, and each group's loads issue together (TAIL: with the
+// batched s-only tail; the compacted table, where it measured slower, goes
+// without).
+template <bool PF = false, bool TAIL = true>
 __device__ __forceinline__ void basis_dot2(const KArgs &A, const double ra[3], const double rb[3],
                                            const double *y, double &out_a, double &out_b)
 {
@@ -363,14 +469,25 @@ __device__ __forceinline__ void basis_dot2(const KArgs &A, const double ra[3], c
         const unsigned long long fl = D->flags;
         const int len = D->len, code = D->code;
         const double *yq = y + D->mu0;
-        if (code == 2)
-            chain_dot2<2>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
-        else if (code == 1)
-            chain_dot2<1>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
-        else if (code == 3)
-            chain_dot2<3>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
-        else
-            chain_dot2<0>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+        if constexpr (PF) {
+            if (code == 2)
+                chain_dot2_pf<2, TAIL>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+            else if (code == 1)
+                chain_dot2_pf<1, TAIL>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+            else if (code == 3)
+                chain_dot2_pf<3, TAIL>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+            else
+                chain_dot2_pf<0, TAIL>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+        } else {
+            if (code == 2)
+                chain_dot2<2>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+            else if (code == 1)
+                chain_dot2<1>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+            else if (code == 3)
+                chain_dot2<3>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+            else
+                chain_dot2<0>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+        }
     }
     out_a = acc_a;
     out_b = acc_b;
@@ -428,23 +545,26 @@ __device__ __forceinline__ void contract(const KArgs &A, const double *b, int ne
         const double *bb = b + e * 5 * Kp, *ct = A.moT + (size_t)j * K, *yr = yrow + j * Kp;
         double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         if (live) {
-            for (int q0 = 0; q0 < Q; q0 += 4) {
-                double cv[4], bq[5][4], yv[4];
+            for (int q0 = 0; q0 < Q; q0 += 8) {
+                double cv[8], yv[8];
+                int mcs[8];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < 8; ++u) {
                     const int mu = part + ((q0 + u) << lgP);
                     const bool ok = mu < K;
                     const int mc = ok ? mu : K - 1;
+                    mcs[u] = mc;
                     cv[u] = ok ? ct[mc] : 0.0;
-#pragma unroll
-                    for (int c = 0; c < 5; ++c) bq[c][u] = bb[c * Kp + mc];
                     if (W) yv[u] = ok ? yr[mc] : 0.0;
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < 8; ++u) {
+                    double bq[5];
 #pragma unroll
-                    for (int c = 0; c < 5; ++c) acc[c] = fma(bq[c][u], cv[u], acc[c]);
-                    if (W) acc[5] = fma(bq[0][u], yv[u], acc[5]);
+                    for (int c = 0; c < 5; ++c) bq[c] = bb[c * Kp + mcs[u]];
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) acc[c] = fma(bq[c], cv[u], acc[c]);
+                    if (W) acc[5] = fma(bq[0], yv[u], acc[5]);
                 }
             }
         }
@@ -1023,7 +1143,7 @@ __device__ __forceinline__ double move_table_compact(const KArgs &A, double *lds
             db = !g && pb < kPDrop;
         }
         double rda, rdb, ja, jb;
-        basis_dot2(A, ra, rb, Y + i * A.Kp, rda, rdb);
+        basis_dot2<YG, false>(A, ra, rb, Y + i * A.Kp, rda, rdb);
         jastrow_point2<CORR, MX>(A, pos, i, ra, rb, ja, jb);
         const double jo = Jo[i];
         const double rhoa = rda * exp(ja - jo), rhob = rdb * exp(jb - jo);
@@ -1078,7 +1198,7 @@ __device__ __forceinline__ double move_table(const KArgs &A, double *lds, const 
             db = !g && pb < kPDrop;
         }
         double rda, rdb, ja, jb;
-        basis_dot2(A, ra, rb, Y + i * A.Kp, rda, rdb);
+        basis_dot2<YG>(A, ra, rb, Y + i * A.Kp, rda, rdb);
         jastrow_point2<CORR, MX>(A, pos, i, ra, rb, ja, jb);
         const double jo = Jo[i];
         const double rhoa = rda * exp(ja - jo), rhob = rdb * exp(jb - jo);
@@ -1263,13 +1383,13 @@ __device__ __forceinline__ void accept_move(const KArgs &A, double *lds, double 
                 inv[j * ns + i] -= colk[j] * f;
             }
         }
-        // the spin's rows of Y, four elements per thread in flight
+        // the spin's rows of Y, eight elements per thread in flight
         const int nY = n * K;
-        for (int u0 = tid; u0 < nY; u0 += 4 * NT) {
-            double y[4], yk[4], f[4];
-            int at[4];
+        for (int u0 = tid; u0 < nY; u0 += 8 * NT) {
+            double y[8], yk[8], f[8];
+            int at[8];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
+            for (int v = 0; v < 8; ++v) {
                 const int u = min(u0 + v * NT, nY - 1), i = row_of(u, inv_K), mu = u - i * K;
                 at[v] = (i0 + i) * Kp + mu;
                 y[v] = Y[at[v]];
@@ -1277,7 +1397,7 @@ __device__ __forceinline__ void accept_move(const KArgs &A, double *lds, double 
                 f[v] = (wrow[i] - (i == kl ? 1.0 : 0.0)) * irho;
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
+            for (int v = 0; v < 8; ++v)
                 if (u0 + v * NT < nY) Y[at[v]] = y[v] - yk[v] * f[v];
         }
     }

@@ -156,3 +156,59 @@ def test_compacted_table_run():
     if n == 3:
         check("compacted run final positions", gpu.get_walkers()["pos"].cpu().numpy(), ref["pos"], 1e-10)
     gpu.close()
+
+
+def _shell_mix():
+    """Three nuclei whose groups (shells of one nucleus and exponent) take
+    every combination of s, p and d: a beta = 2.5 chain with flags s, p, sp,
+    d, sd, pd, spd and five trailing s-only groups; a beta = 2 chain sp, sp,
+    s; a beta = 3 chain spd and four s-only groups; a stand-alone p group."""
+    rng = np.random.default_rng(11)
+    shells = []   # (nucleus, l, alpha)
+    flags0 = [(0,), (1,), (0, 1), (2,), (0, 2), (1, 2), (0, 1, 2)] + [(0,)] * 5
+    for k, ls in enumerate(flags0):
+        shells += [(0, l, 0.2 * 2.5 ** k) for l in ls]
+    for k, ls in enumerate([(0, 1), (0, 1), (0,)]):
+        shells += [(1, l, 0.3 * 2.0 ** k) for l in ls]
+    for k, ls in enumerate([(0, 1, 2)] + [(0,)] * 4):
+        shells += [(2, l, 0.5 * 3.0 ** k) for l in ls]
+    shells.append((2, 1, 200.0))
+    nuc, l, al = (list(x) for x in zip(*shells))
+    K = sum(2 * q + 1 for q in l)
+    mo = np.linalg.qr(rng.standard_normal((K, K)))[0][:, :3]
+    R = np.array([[0.0, 0.0, 0.0], [0.3, -0.4, 1.4], [-1.0, 0.5, -0.6]])
+    return inputs.System(Z=np.array([3.0, 1.0, 2.0]), R=R, n_up=3, n_dn=3, shell_nuc=nuc, shell_l=l,
+                         shell_alpha=al, mo=mo, name="shell_mix")
+
+
+def test_every_shell_combination_y_in_hbm():
+    """The device-memory table loads each group's coefficients by its shell
+    combination (and the trailing s-only groups four at a time): move
+    tables against the oracle and against the same kernels with Y in LDS,
+    then a run against the oracle."""
+    from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_use_generic
+    s = _shell_mix()
+    a, tau, W = 0.05, 0.01, 8
+    rc, ap, _ = spacing.spacing(s.z_max, a)
+    gpu = LRDMC(s, a, ap, rc, tau, W, seed=2, rotate=1, refresh=2)
+    orc = oracle.Oracle(s, a, ap, rc, tau=tau, seed=2, rotate=1)
+    pos = inputs.initial_walkers(s, W, 6)
+    lrdmc_use_generic(gpu.ctx, 2)
+    rho = gpu.eval_moves(pos)[0].cpu().numpy().copy()
+    lrdmc_use_generic(gpu.ctx, 1)
+    rho_lds = gpu.eval_moves(pos)[0].cpu().numpy().copy()
+    for w in range(W):
+        r_o = orc.eval_moves(pos[w], orc.move_rotation(w, 0, 0))[0]
+        check("shell mix y-hbm rho", rho[w], r_o, 1e-11 * np.abs(r_o) + 2e-12 * np.max(np.abs(r_o)),
+              scale=np.abs(r_o))
+    check("shell mix y-hbm against y-lds rho", rho, rho_lds, 1e-13 * np.abs(rho_lds).max(),
+          scale=np.abs(rho_lds))
+    lrdmc_use_generic(gpu.ctx, 2)
+    gpu.set_walkers(pos, 0)
+    out = gpu.run(3, want_idx=True)
+    ref = orc.run(pos, 3, gen0=0)
+    n = run_agrees("shell mix y-hbm run", out["n_moves"].cpu().numpy(), out["idx"].cpu().numpy(), ref)
+    eb = out["ebar"].cpu().numpy()
+    check("shell mix y-hbm run ebar", eb[:n], ref["ebar"][:n], record_bar(ref["ebar"][:n]),
+          scale=np.abs(ref["ebar"][:n]))
+    gpu.close()
