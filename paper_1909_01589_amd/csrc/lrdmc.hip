@@ -296,6 +296,38 @@ __device__ __forceinline__ double sqrt_chain(double e)
     return fma(h, fma(-s, s, e), s);
 }
 
+// Angular factors of a point at (x, y, z) from a nucleus, in the basis
+// order of a group: p (x, y, z), then d (xy, yz, zx, x^2 - y^2,
+// 2 z^2 - x^2 - y^2).
+struct Ang {
+    double x, y, z, xy, yz, zx, d3, d4;
+};
+__device__ __forceinline__ Ang ang_of(double x, double y, double z)
+{
+    return Ang{x, y, z, x * y, y * z, z * x, x * x - y * y, 2.0 * z * z - x * x - y * y};
+}
+
+// sum over one group's functions of angular factor times y (v: slot 0 the s
+// function, 1-3 the p, 4-8 the d), accumulated by fused multiply-adds in
+// basis order.
+__device__ __forceinline__ double shell_dot(const Ang &g, bool s, bool p, bool d, const double v[9])
+{
+    double t = s ? v[0] : 0.0;
+    if (p) {
+        t = fma(g.x, v[1], t);
+        t = fma(g.y, v[2], t);
+        t = fma(g.z, v[3], t);
+    }
+    if (d) {
+        t = fma(g.xy, v[4], t);
+        t = fma(g.yz, v[5], t);
+        t = fma(g.zx, v[6], t);
+        t = fma(g.d3, v[7], t);
+        t = fma(g.d4, v[8], t);
+    }
+    return t;
+}
+
 // One chain of basis_dot2 with its step code fixed at compile time
 // (e^2.5 = e^2 sqrt(e)); the chain has no branches on the data.
 template <int CODE>
@@ -305,25 +337,36 @@ __device__ __forceinline__ void chain_dot2(unsigned long long fl, int len, const
 {
     for (int q = 0; q < len; ++q) {
         const int f = (int)(fl >> (3 * q)) & 7;
+        // shell_dot's sums, shell by shell as the loads arrive
         double pa = 0.0, pb = 0.0;
         if (f & 1) {
-            const double ys = yq[0];
-            pa += ys;
-            pb += ys;
+            pa = yq[0];
+            pb = pa;
             yq += 1;
         }
         if (f & 2) {
             const double y0 = yq[0], y1 = yq[1], y2 = yq[2];
-            pa += ax * y0 + ay * y1 + az * y2;
-            pb += bx * y0 + by * y1 + bz * y2;
+            pa = fma(ax, y0, pa);
+            pa = fma(ay, y1, pa);
+            pa = fma(az, y2, pa);
+            pb = fma(bx, y0, pb);
+            pb = fma(by, y1, pb);
+            pb = fma(bz, y2, pb);
             yq += 3;
         }
         if (f & 4) {
             const double y0 = yq[0], y1 = yq[1], y2 = yq[2], y3 = yq[3], y4 = yq[4];
-            pa += ax * ay * y0 + ay * az * y1 + az * ax * y2 + (ax * ax - ay * ay) * y3 +
-                  (2.0 * az * az - ax * ax - ay * ay) * y4;
-            pb += bx * by * y0 + by * bz * y1 + bz * bx * y2 + (bx * bx - by * by) * y3 +
-                  (2.0 * bz * bz - bx * bx - by * by) * y4;
+            const Ang ga = ang_of(ax, ay, az), gb = ang_of(bx, by, bz);
+            pa = fma(ga.xy, y0, pa);
+            pa = fma(ga.yz, y1, pa);
+            pa = fma(ga.zx, y2, pa);
+            pa = fma(ga.d3, y3, pa);
+            pa = fma(ga.d4, y4, pa);
+            pb = fma(gb.xy, y0, pb);
+            pb = fma(gb.yz, y1, pb);
+            pb = fma(gb.zx, y2, pb);
+            pb = fma(gb.d3, y3, pb);
+            pb = fma(gb.d4, y4, pb);
             yq += 5;
         }
         acc_a += ea * pa;
@@ -347,8 +390,7 @@ __device__ __forceinline__ void chain_dot2(unsigned long long fl, int len, const
 // compile time: all of its loads of y issue together, then the same
 // arithmetic in the same order as chain_dot2.  Returns the group's size.
 template <int F>
-__device__ __forceinline__ int group_dot2(const double *yq, double ax, double ay, double az, double bx,
-                                          double by, double bz, double &pa, double &pb)
+__device__ __forceinline__ int group_dot2(const double *yq, const Ang &ga, const Ang &gb, double &pa, double &pb)
 {
     constexpr int os = 0, op = (F & 1), od = op + ((F & 2) ? 3 : 0);
     double v[9];
@@ -359,22 +401,8 @@ __device__ __forceinline__ int group_dot2(const double *yq, double ax, double ay
 #pragma unroll
     for (int j = 0; j < 5; ++j)
         if (F & 4) v[4 + j] = yq[od + j];
-    pa = 0.0;
-    pb = 0.0;
-    if (F & 1) {
-        pa += v[0];
-        pb += v[0];
-    }
-    if (F & 2) {
-        pa += ax * v[1] + ay * v[2] + az * v[3];
-        pb += bx * v[1] + by * v[2] + bz * v[3];
-    }
-    if (F & 4) {
-        pa += ax * ay * v[4] + ay * az * v[5] + az * ax * v[6] + (ax * ax - ay * ay) * v[7] +
-              (2.0 * az * az - ax * ax - ay * ay) * v[8];
-        pb += bx * by * v[4] + by * bz * v[5] + bz * bx * v[6] + (bx * bx - by * by) * v[7] +
-              (2.0 * bz * bz - bx * bx - by * by) * v[8];
-    }
+    pa = shell_dot(ga, F & 1, F & 2, F & 4, v);
+    pb = shell_dot(gb, F & 1, F & 2, F & 4, v);
     return od + ((F & 4) ? 5 : 0);
 }
 
@@ -405,6 +433,7 @@ __device__ __forceinline__ void chain_dot2_pf(unsigned long long fl, int len, co
                                               double ay, double az, double bx, double by, double bz, double ea,
                                               double eb, double &acc_a, double &acc_b)
 {
+    const Ang ga = ang_of(ax, ay, az), gb = ang_of(bx, by, bz);
     // first group of the trailing s-only run
     int q1 = len;
     if (TAIL) {
@@ -415,13 +444,14 @@ __device__ __forceinline__ void chain_dot2_pf(unsigned long long fl, int len, co
         const int f = (int)(fl >> (3 * q)) & 7;
         double pa = 0.0, pb = 0.0;
         switch (f) {
-        case 2: yq += group_dot2<2>(yq, ax, ay, az, bx, by, bz, pa, pb); break;
-        case 3: yq += group_dot2<3>(yq, ax, ay, az, bx, by, bz, pa, pb); break;
-        case 4: yq += group_dot2<4>(yq, ax, ay, az, bx, by, bz, pa, pb); break;
-        case 5: yq += group_dot2<5>(yq, ax, ay, az, bx, by, bz, pa, pb); break;
-        case 6: yq += group_dot2<6>(yq, ax, ay, az, bx, by, bz, pa, pb); break;
-        case 7: yq += group_dot2<7>(yq, ax, ay, az, bx, by, bz, pa, pb); break;
-        default: yq += group_dot2<1>(yq, ax, ay, az, bx, by, bz, pa, pb); break;
+        case 1: yq += group_dot2<1>(yq, ga, gb, pa, pb); break;
+        case 2: yq += group_dot2<2>(yq, ga, gb, pa, pb); break;
+        case 3: yq += group_dot2<3>(yq, ga, gb, pa, pb); break;
+        case 4: yq += group_dot2<4>(yq, ga, gb, pa, pb); break;
+        case 5: yq += group_dot2<5>(yq, ga, gb, pa, pb); break;
+        case 6: yq += group_dot2<6>(yq, ga, gb, pa, pb); break;
+        case 7: yq += group_dot2<7>(yq, ga, gb, pa, pb); break;
+        default: break;
         }
         acc_a += ea * pa;
         acc_b += eb * pb;
@@ -437,8 +467,8 @@ __device__ __forceinline__ void chain_dot2_pf(unsigned long long fl, int len, co
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             if (j < nb) {
-                acc_a += ea * (0.0 + v[j]);
-                acc_b += eb * (0.0 + v[j]);
+                acc_a += ea * v[j];
+                acc_b += eb * v[j];
                 if (q + j + 1 < len) chain_step<CODE>(ea, eb);
             }
         }
