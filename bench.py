@@ -319,11 +319,33 @@ def neural_bench(system="ar", walkers=16384, rounds=8, train_steps=60, lr=1e-3, 
     return {"neural": out}
 
 
+NEURAL_FITS = (("E0 + k1 a^2 + k2 a^4", (2, 4)), ("E0 + k1 a^2 + k2 a^4 + k3 a^6", (2, 4, 6)),
+               ("E0 + k1 a + k2 a^2", (1, 2)), ("E0 + k1 a + k2 a^2 + k3 a^3", (1, 2, 3)))
+
+
+def _fit_poly(a, E, sig, powers):
+    """Weighted fit E = E0 + sum_p k_p a^p: (E0, sigma_E0, chi2 per degree of
+    freedom, degrees of freedom)."""
+    a = np.asarray(a, dtype=np.float64)
+    E = np.asarray(E, dtype=np.float64)
+    w = 1.0 / np.asarray(sig, dtype=np.float64) ** 2
+    X = np.stack([np.ones_like(a)] + [a ** q for q in powers], axis=1)
+    cov = np.linalg.inv(X.T @ (X * w[:, None]))
+    beta = cov @ (X.T @ (w * E))
+    r = E - X @ beta
+    dof = len(E) - X.shape[1]
+    return float(beta[0]), float(np.sqrt(cov[0, 0])), float((w * r * r).sum() / max(dof, 1)), dof
+
+
 def neural_summarize(rows):
     """Per trial function (rows: per-run dicts with form, a, E, sigma,
     t_1mHa_s) the fit of E(a) (E0 + k1 a^2 + k2 a^4 from four spacings on,
     else E0 + k1 a^2) and, with both forms, the difference of the limits
-    and the time-to-1 mHa ratios at the common spacings."""
+    and the time-to-1 mHa ratios at the common spacings.  With five
+    spacings or more, every model of NEURAL_FITS that leaves a degree of
+    freedom is fitted as well ("fits"), with the difference of the limits
+    per model: whether E(a) is in its a^2 regime decides which limit means
+    anything."""
     res = {}
     for label in ("pade", "neural"):
         rs = sorted((r for r in rows if r["form"] == label), key=lambda r: -r["a"])
@@ -337,6 +359,12 @@ def neural_summarize(rows):
             E0, s0, chi2 = _fit_e0_linear(a_, E_, s_)    # E0 + k1 a^2
             fit = "E0 + k1 a^2"
         res[label] = dict(rows=rs, fit=fit, E0=E0, sigma_E0=s0, chi2_dof=chi2)
+        if len(rs) >= 5:
+            res[label]["fits"] = {}
+            for name, powers in NEURAL_FITS:
+                if len(rs) > len(powers) + 1:
+                    e0, se0, c2, dof = _fit_poly(a_, E_, s_, powers)
+                    res[label]["fits"][name] = dict(E0=e0, sigma_E0=se0, chi2_dof=c2, dof=dof)
     out = {"lrdmc": res}
     if "pade" in res and "neural" in res:
         by_a = {r["a"]: r for r in res["neural"]["rows"]}
@@ -344,6 +372,10 @@ def neural_summarize(rows):
                                                      for r in res["pade"]["rows"] if r["a"] in by_a}
         out["E0_difference"] = res["neural"]["E0"] - res["pade"]["E0"]
         out["E0_difference_sigma"] = float(np.hypot(res["pade"]["sigma_E0"], res["neural"]["sigma_E0"]))
+        fp, fn = res["pade"].get("fits", {}), res["neural"].get("fits", {})
+        out["E0_difference_per_fit"] = {k: dict(diff=fn[k]["E0"] - fp[k]["E0"],
+                                                sigma=float(np.hypot(fn[k]["sigma_E0"], fp[k]["sigma_E0"])))
+                                        for k in fp if k in fn}
     return out
 
 
