@@ -329,8 +329,9 @@ __device__ __forceinline__ double shell_dot(const Ang &g, bool s, bool p, bool d
 }
 
 // One chain of basis_dot2 with its step code fixed at compile time
-// (e^2.5 = e^2 sqrt(e)); the chain has no branches on the data.
-template <int CODE>
+// (e^2.5 = e^2 sqrt(e)); the chain has no branches on the data.  TWO false:
+// the first point only (the b results are not formed).
+template <int CODE, bool TWO = true>
 __device__ __forceinline__ void chain_dot2(unsigned long long fl, int len, const double *yq, double ax,
                                            double ay, double az, double bx, double by, double bz, double ea,
                                            double eb, double &acc_a, double &acc_b)
@@ -341,7 +342,7 @@ __device__ __forceinline__ void chain_dot2(unsigned long long fl, int len, const
         double pa = 0.0, pb = 0.0;
         if (f & 1) {
             pa = yq[0];
-            pb = pa;
+            if (TWO) pb = pa;
             yq += 1;
         }
         if (f & 2) {
@@ -349,39 +350,47 @@ __device__ __forceinline__ void chain_dot2(unsigned long long fl, int len, const
             pa = fma(ax, y0, pa);
             pa = fma(ay, y1, pa);
             pa = fma(az, y2, pa);
-            pb = fma(bx, y0, pb);
-            pb = fma(by, y1, pb);
-            pb = fma(bz, y2, pb);
+            if (TWO) {
+                pb = fma(bx, y0, pb);
+                pb = fma(by, y1, pb);
+                pb = fma(bz, y2, pb);
+            }
             yq += 3;
         }
         if (f & 4) {
             const double y0 = yq[0], y1 = yq[1], y2 = yq[2], y3 = yq[3], y4 = yq[4];
-            const Ang ga = ang_of(ax, ay, az), gb = ang_of(bx, by, bz);
+            const Ang ga = ang_of(ax, ay, az);
             pa = fma(ga.xy, y0, pa);
             pa = fma(ga.yz, y1, pa);
             pa = fma(ga.zx, y2, pa);
             pa = fma(ga.d3, y3, pa);
             pa = fma(ga.d4, y4, pa);
-            pb = fma(gb.xy, y0, pb);
-            pb = fma(gb.yz, y1, pb);
-            pb = fma(gb.zx, y2, pb);
-            pb = fma(gb.d3, y3, pb);
-            pb = fma(gb.d4, y4, pb);
+            if (TWO) {
+                const Ang gb = ang_of(bx, by, bz);
+                pb = fma(gb.xy, y0, pb);
+                pb = fma(gb.yz, y1, pb);
+                pb = fma(gb.zx, y2, pb);
+                pb = fma(gb.d3, y3, pb);
+                pb = fma(gb.d4, y4, pb);
+            }
             yq += 5;
         }
         acc_a += ea * pa;
-        acc_b += eb * pb;
+        if (TWO) acc_b += eb * pb;
         if (q + 1 == len) break;
         if (CODE == 3) {
             ea = ea * ea * ea;
-            eb = eb * eb * eb;
+            if (TWO) eb = eb * eb * eb;
         } else if (CODE == 2) {
-            const double sa = sqrt_chain(ea), sb = sqrt_chain(eb);
+            const double sa = sqrt_chain(ea);
             ea = (ea * ea) * sa;
-            eb = (eb * eb) * sb;
+            if (TWO) {
+                const double sb = sqrt_chain(eb);
+                eb = (eb * eb) * sb;
+            }
         } else if (CODE == 1) {
             ea = ea * ea;
-            eb = eb * eb;
+            if (TWO) eb = eb * eb;
         }
     }
 }
@@ -482,11 +491,12 @@ __device__ __forceinline__ void chain_dot2_pf(unsigned long long fl, int len, co
 // costs one exp per point; both points share the loads of y.  PF: y is in
 // device memory, and each group's loads issue together (TAIL: with the
 // batched s-only tail; the compacted table, where it measured slower, goes
-// without).
-template <bool PF = false, bool TAIL = true>
+// without).  TWO false (y in LDS): the first point only, out_b unset.
+template <bool PF = false, bool TAIL = true, bool TWO = true>
 __device__ __forceinline__ void basis_dot2(const KArgs &A, const double ra[3], const double rb[3],
                                            const double *y, double &out_a, double &out_b)
 {
+    static_assert(TWO || !PF, "one point only with y in LDS");
     double acc_a = 0.0, acc_b = 0.0;
     const auto *chains = cst(A.chains);
     for (int ch = 0; ch < A.n_chain; ++ch) {
@@ -495,7 +505,7 @@ __device__ __forceinline__ void basis_dot2(const KArgs &A, const double ra[3], c
         const double bx = rb[0] - D->R[0], by = rb[1] - D->R[1], bz = rb[2] - D->R[2];
         const double a2 = ax * ax + ay * ay + az * az, b2 = bx * bx + by * by + bz * bz;
         const double al0 = D->alpha0;
-        const double ea = exp(-al0 * a2), eb = exp(-al0 * b2);
+        const double ea = exp(-al0 * a2), eb = TWO ? exp(-al0 * b2) : 0.0;
         const unsigned long long fl = D->flags;
         const int len = D->len, code = D->code;
         const double *yq = y + D->mu0;
@@ -510,17 +520,17 @@ __device__ __forceinline__ void basis_dot2(const KArgs &A, const double ra[3], c
                 chain_dot2_pf<0, TAIL>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
         } else {
             if (code == 2)
-                chain_dot2<2>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+                chain_dot2<2, TWO>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
             else if (code == 1)
-                chain_dot2<1>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+                chain_dot2<1, TWO>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
             else if (code == 3)
-                chain_dot2<3>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+                chain_dot2<3, TWO>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
             else
-                chain_dot2<0>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+                chain_dot2<0, TWO>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
         }
     }
     out_a = acc_a;
-    out_b = acc_b;
+    if (TWO) out_b = acc_b;
 }
 
 __device__ __forceinline__ double rcp_nr(double a);
@@ -1190,6 +1200,60 @@ __device__ __forceinline__ double move_table_compact(const KArgs &A, double *lds
     return part;
 }
 
+// Heat-bath weights with one move per thread (M <= NT, Y in LDS): every
+// lane evaluates its own move m = threadIdx.x at one point, then, after a
+// barrier, each thread sums the weights of its chunk [c0, c1) as
+// move_table does, so the scan and the search see the same sums.  Small
+// systems: a wavefront holds all 12N moves, and one point per lane halves
+// the table's latency against one +/- pair per lane.
+template <bool CORR, bool MX>
+__device__ __forceinline__ double move_table_points(const KArgs &A, double *lds, const double *Rm, int c0, int c1,
+                                                    int *last, double *rho_g, double *k_g, double acc[3], bool diag)
+{
+    const Layout &L = A.L;
+    const double *pos = lds + L.pos, *Y = lds + L.Y, *Jo = lds + L.Jo;
+    double *T = lds + L.T;
+    const int m = threadIdx.x;
+    if (m < A.M) {
+        const int i = m / A.mpe, g = A.mpe == 12 ? (m / 6) & 1 : 0, d = m % 6, ax = d >> 1;
+        const double h = grid_spacing(A, g), sh = (d & 1) ? -h : h;
+        const double e[3] = {Rm[ax], Rm[3 + ax], Rm[6 + ax]};
+        double r[3], mp[3];
+        for (int c = 0; c < 3; ++c) {
+            const double x = pos[3 * i + c];
+            r[c] = x + sh * e[c];
+            mp[c] = x + (0.5 * sh) * e[c];
+        }
+        double k = A.inv_a2;   // single grid: p = 1
+        bool dr = false;
+        if (A.mpe == 12) {
+            const double pm = p_switch(A, mp);
+            k = g ? (1.0 - pm) * A.inv_ap2 : pm * A.inv_a2;
+            dr = !g && pm < kPDrop;
+        }
+        double rd, unused, ja, jb;
+        basis_dot2<false, true, false>(A, r, r, Y + i * A.Kp, rd, unused);
+        jastrow_point2<CORR, MX>(A, pos, i, r, r, ja, jb);
+        const double rho = rd * exp(ja - Jo[i]);
+        T[m] = dr ? 0.0 : 0.5 * k * (rho > 0.0 ? rho : 0.0);
+        if (diag) {
+            if (rho_g) rho_g[m] = rho;
+            if (k_g) k_g[m] = k;
+            acc[0] += k;
+            acc[1] += k * (rho - 1.0);
+            if (rho < 0.0) acc[2] += -0.5 * k * rho;
+        }
+    }
+    __syncthreads();
+    double part = 0.0;
+    for (int mm = c0; mm < c1; ++mm) {
+        const double t = T[mm];
+        part += t;
+        if (t > 0.0) *last = mm;
+    }
+    return part;
+}
+
 // Heat-bath weights of the moves m in [c0, c1) (S1-S6), c0 and c1 even:
 // each step evaluates the +/- pair (m, m + 1) along one axis of one grid of
 // one electron.  Returns the sum of the weights; with diag, stores rho and k
@@ -1201,6 +1265,8 @@ __device__ __forceinline__ double move_table(const KArgs &A, double *lds, const 
     if constexpr (YG) {
         // compaction pays when it saves a second round of pairs per thread
         if (!diag && A.M / 2 > A.nt) return move_table_compact<CORR, YG, MX>(A, lds, Rm, c0, c1, last);
+    } else {
+        if (A.M <= A.nt) return move_table_points<CORR, MX>(A, lds, Rm, c0, c1, last, rho_g, k_g, acc, diag);
     }
     const Layout &L = A.L;
     const double *pos = lds + L.pos, *Y = y_base<YG>(A, lds), *Jo = lds + L.Jo;
