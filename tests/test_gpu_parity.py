@@ -53,6 +53,11 @@ def _case(name):
         return s, 1 / 189, ap, rc, 0.000319
     if name == "hydrogenic":
         return inputs.hydrogenic(2.0), 0.15, 0.25, 0.4, 0.05
+    if name == "ne":
+        # 120 moves: two wavefronts per walker, one move per lane in the table
+        s = inputs.atom_screened(10, (11, 6, 0), 0.05, 2.5, name="ne_screened")
+        rc, ap, _ = spacing.spacing(10, 0.05)
+        return s, 0.05, ap, rc, 0.004
     raise KeyError(name)
 
 
@@ -64,7 +69,7 @@ def _pair(name, W, seed=3, rotate=1, tau=None, refresh=1):
     return s, gpu, orc
 
 
-@pytest.mark.parametrize("name,W", [("be", 16), ("tiny", 8), ("ar", 6), ("molecule", 3), ("xe", 2)])
+@pytest.mark.parametrize("name,W", [("be", 16), ("tiny", 8), ("ne", 8), ("ar", 6), ("molecule", 3), ("xe", 2)])
 @pytest.mark.parametrize("rotate", [0, 1])
 def test_eval_moves_matches_oracle(name, W, rotate):
     s, gpu, orc = _pair(name, W, rotate=rotate)
@@ -88,7 +93,7 @@ def test_eval_moves_matches_oracle(name, W, rotate):
     gpu.close()
 
 
-@pytest.mark.parametrize("name,W", [("be", 32), ("tiny", 16), ("ar", 8), ("molecule", 2)])
+@pytest.mark.parametrize("name,W", [("be", 32), ("tiny", 16), ("ne", 16), ("ar", 8), ("molecule", 2)])
 def test_one_generation_matches_oracle(name, W):
     s, gpu, orc = _pair(name, W)
     pos = inputs.initial_walkers(s, W, 11)
@@ -129,7 +134,8 @@ def test_reconfigure_matches_oracle_bit_exact():
 
 
 @pytest.mark.parametrize("name,W,n_gen,refresh", [("be", 64, 8, 1), ("tiny", 32, 6, 1), ("hydrogenic", 16, 5, 1),
-                                                   ("be", 64, 8, 3), ("tiny", 32, 6, 4), ("ar", 16, 5, 2)])
+                                                   ("be", 64, 8, 3), ("tiny", 32, 6, 4), ("ar", 16, 5, 2),
+                                                   ("ne", 32, 5, 1), ("ne", 32, 5, 3)])
 def test_run_matches_oracle(name, W, n_gen, refresh):
     """Whole projections: move counts and reconfiguration indices bit-exact,
     generation energies within the FP64 bound.  refresh > 1 carries the
