@@ -979,13 +979,61 @@ def cpu_baseline(system, a, ap, rc, tau, seed, pos, gen0, seconds, threads=None)
                       f"{moves} moves in {dt:.1f} s"}
 
 
-def run_workload(name, steps, warmup, want_cpu, cpu_seconds, precision=0, generic=0):
+def population_scan(name, walker_counts, steps, warmup, gens=20):
+    """Throughput of one workload (its system, spacing and tau) against the
+    number of walkers.  A generation ends with its slowest walker, and the
+    number of moves of a walker in a generation is Poisson-like, so with few
+    walkers per resident workgroup slot the end of the launch runs on a part
+    of the machine; the scan shows how much of the kernel's rate that costs.
+    Also reports the variance-to-mean ratio of the moves per walker and
+    generation at the workload's own walker count, and the correlation of a
+    walker's count with its parent's in the generation before (None where
+    every walker descends from one parent)."""
+    import torch
+    from paper_1909_01589_amd import inputs
+    from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_spacing
+    rows = []
+    for W in walker_counts:
+        _, r = run_workload(name, steps, warmup, False, 0.0, walkers=W)
+        rows.append(dict(walkers=W, value=r["value"], ms_per_step=r["ms_per_step"],
+                         kernel_ms=r["roofline"]["avg_launch_ms"], achieved=r["roofline"]["achieved"],
+                         frac=r["roofline"]["frac"], kernel=r["roofline"]["kernel"],
+                         moves_per_walker_gen=r["moves_per_walker_gen"]))
+        print(f"[population] {name} W={W}: {r['value'] / 1e6:.2f} M electron-moves/s, "
+              f"kernel {r['roofline']['avg_launch_ms']:.4f} ms, frac {r['roofline']['frac']:.3f}",
+              file=sys.stderr, flush=True)
+    cfg = inputs.get_config(name)
+    s = cfg.system
+    rc, ap, _ = lrdmc_spacing(s.z_max, cfg.a)
+    gpu = LRDMC(s, cfg.a, ap, rc, cfg.tau, cfg.walkers, seed=cfg.seed, rotate=cfg.rotate, refresh=cfg.refresh)
+    gpu.set_walkers(inputs.initial_walkers(s, cfg.walkers, cfg.seed), 0)
+    gpu.run(warmup)
+    disp, mx, corr, prev = [], [], [], None
+    for _ in range(gens):
+        gpu.project()
+        nm = gpu.get_walkers()["n_moves"].cpu().numpy().astype(float)
+        disp.append(nm.var() / nm.mean())
+        mx.append(nm.max() / nm.mean())
+        if prev is not None and prev.std() > 0:
+            corr.append(float(np.corrcoef(nm, prev)[0, 1]))
+        idx = gpu.branch()["idx"].cpu().numpy()
+        prev = nm[idx]   # the parent's count, per slot of the next generation
+    torch.cuda.synchronize()
+    gpu.close()
+    return {"population_scan": {"workload": name, "default_walkers": cfg.walkers, "steps": steps, "warmup": warmup,
+                                "rows": rows, "moves_var_over_mean": float(np.mean(disp)),
+                                "moves_max_over_mean": float(np.mean(mx)), "generations_sampled": gens,
+                                "parent_child_moves_corr": float(np.mean(corr)) if corr else None,
+                                "generations_with_distinct_parents": len(corr)}}
+
+
+def run_workload(name, steps, warmup, want_cpu, cpu_seconds, precision=0, generic=0, walkers=None):
     import torch
     from paper_1909_01589_amd import inputs, stats, workcount
     from paper_1909_01589_amd.lrdmc import (LRDMC, lrdmc_is_specialized, lrdmc_set_precision, lrdmc_set_timing,
                                             lrdmc_spacing, lrdmc_timing, lrdmc_use_generic)
 
-    cfg = inputs.get_config(name)
+    cfg = inputs.get_config(name, walkers=walkers) if walkers else inputs.get_config(name)
     s = cfg.system
     rc, ap, nc = lrdmc_spacing(s.z_max, cfg.a)
     W = cfg.walkers
@@ -1117,6 +1165,8 @@ def main():
                     help="only run the single/double-grid comparison for Ne and Ar with screened orbitals and exit")
     ap.add_argument("--zscan", action="store_true",
                     help="only run the single/double-grid cost scan over Z = 10, 18, 36, 54 and exit")
+    ap.add_argument("--population", type=int, nargs="+", default=None, metavar="W",
+                    help="throughput of --workload at these walker counts (JSON on stdout)")
     ap.add_argument("--ascan", action="store_true",
                     help="only run the spacing scan on helium for the three lattice schemes and exit")
     ap.add_argument("--tsigma", action="store_true",
@@ -1163,6 +1213,9 @@ def main():
         return
     if args.ascan:
         print(json.dumps(ascan()), flush=True)
+        return
+    if args.population:
+        print(json.dumps(population_scan(args.workload, args.population, args.steps, args.warmup)), flush=True)
         return
     if args.tsigma:
         print(json.dumps(tsigma_bench(seeds=args.seeds, first_seed=args.first_seed, gens=args.tsigma_gens,
