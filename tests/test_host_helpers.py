@@ -104,3 +104,69 @@ def test_table_s1_accelerations_quoted_by_the_bench_match_the_fixture():
         hit = [r for r in rows if names.get(int(r[0])) == atom and abs(r[2] - alpha) < 1e-9]
         assert len(hit) == 1, (atom, alpha)
         assert hit[0][3] == acc
+
+
+def test_fit_poly_closed_forms():
+    """_fit_poly (the E(a) models of the learned-Jastrow comparison): exact
+    polynomial data give their constant term with chi2 = 0; with no powers
+    the fit is the weighted mean with error 1 / sqrt(sum w); with powers
+    (2, 4) it is the fit of _fit_e0."""
+    a = np.array([0.06, 0.045, 0.035, 0.025, 0.0175, 0.0125])
+    sig = np.array([0.02, 0.01, 0.014, 0.012, 0.017, 0.0125])
+    E = -520.1 - 12.0 * a + 90.0 * a ** 2 - 700.0 * a ** 3
+    E0, s0, chi2, dof = bench._fit_poly(a, E, sig, (1, 2, 3))
+    assert E0 == pytest.approx(-520.1, abs=1e-9)
+    assert chi2 == pytest.approx(0.0, abs=1e-12)
+    assert dof == a.size - 4
+    y = np.array([1.0, 2.0, 4.0])
+    s = np.array([1.0, 2.0, 0.5])
+    w = 1.0 / s ** 2
+    m, sm, c2, d = bench._fit_poly(np.array([0.1, 0.2, 0.3]), y, s, ())
+    assert m == pytest.approx(np.sum(w * y) / np.sum(w), rel=1e-14)
+    assert sm == pytest.approx(1.0 / np.sqrt(np.sum(w)), rel=1e-14)
+    assert c2 == pytest.approx(np.sum(w * (y - m) ** 2) / 2, rel=1e-12)
+    assert d == 2
+    Eq = -520.4 + 300.0 * a ** 2 - 2.0e4 * a ** 4 + np.array([1, -1, 1, -1, 1, -1]) * sig
+    assert bench._fit_poly(a, Eq, sig, (2, 4))[:3] == pytest.approx(bench._fit_e0(a, Eq, sig), rel=1e-12)
+
+
+def test_tsigma_summary_hand_computed():
+    """tsigma_summarize on two seeds per form: time to 1 mHa = mean(c) mean(v)
+    / 1e-6; the ratio's 95 % interval from the delta method on log c and
+    log v (here only v scatters: se(v) = 1 at v = 4 for both forms, so the
+    half-width in log is 1.96 sqrt(2) / 4); the paired ratio of identical
+    per-seed ratios has no spread; the energy is the inverse-variance mean."""
+    def run(seed, c, v, E, sg):
+        return dict(seed=seed, c=c, v=v, E=E, sigma=sg, moves_per_s=1.0, ess_min=0.5)
+    runs = {"fp64": [run(0, 2.0, 3.0, 1.0, 1.0), run(1, 2.0, 5.0, 2.0, 1.0)],
+            "mixed": [run(0, 1.0, 3.0, 1.5, 1.0), run(1, 1.0, 5.0, 1.5, 1.0)]}
+    res = bench.tsigma_summarize(runs)
+    f = res["forms"]["fp64"]
+    assert f["time_to_1mHa_s"] == pytest.approx(2.0 * 4.0 / 1e-6, rel=1e-14)
+    assert f["v_se"] == pytest.approx(1.0, rel=1e-14)
+    assert f["E"] == pytest.approx(1.5, rel=1e-14)
+    assert f["E_sigma"] == pytest.approx(1.0 / np.sqrt(2.0), rel=1e-14)
+    assert f["E_scatter_chi2_dof"] == pytest.approx(0.5, rel=1e-14)
+    q = res["against_fp64"]["mixed"]
+    assert q["ratio"] == pytest.approx(2.0, rel=1e-14)
+    assert q["speed_ratio"] == pytest.approx(2.0, rel=1e-14)
+    assert q["variance_ratio"] == pytest.approx(1.0, rel=1e-14)
+    half = 1.96 * np.sqrt(2.0) / 4.0
+    assert q["ci95"] == pytest.approx([2.0 * np.exp(-half), 2.0 * np.exp(half)], rel=1e-12)
+    assert q["paired"]["ratio"] == pytest.approx(2.0, rel=1e-14)
+    assert q["paired"]["ci95"] == pytest.approx([2.0, 2.0], rel=1e-14)
+    assert q["dE"] == pytest.approx(0.0, abs=1e-14)
+
+
+def test_neural_summary_ratios_and_limits():
+    """neural_summarize: per-spacing time ratios Pade / neural, each form's
+    E0 from E0 + k a^2 (three spacings), and the difference of the limits."""
+    a = [0.3, 0.2, 0.1]
+    rows = [dict(form="pade", a=x, E=-2.9 + 0.5 * x * x, sigma=1e-3, t_1mHa_s=t) for x, t in zip(a, (30.0, 20.0, 10.0))]
+    rows += [dict(form="neural", a=x, E=-2.8 + 0.2 * x * x, sigma=1e-3, t_1mHa_s=t) for x, t in zip(a, (10.0, 10.0, 5.0))]
+    out = bench.neural_summarize(rows)
+    assert out["lrdmc"]["pade"]["fit"] == "E0 + k1 a^2"
+    assert out["lrdmc"]["pade"]["E0"] == pytest.approx(-2.9, abs=1e-12)
+    assert out["lrdmc"]["neural"]["E0"] == pytest.approx(-2.8, abs=1e-12)
+    assert out["E0_difference"] == pytest.approx(0.1, abs=1e-12)
+    assert out["time_to_1mHa_ratio_pade_over_neural"] == pytest.approx({"0.3": 3.0, "0.2": 2.0, "0.1": 2.0}, rel=1e-14)
