@@ -707,6 +707,51 @@ def mixed_bench(walkers=16384, gens=1200, seed=0):
     return {"mixed_precision": out}
 
 
+def mixed_molecule(gens=400, equil=100, vmc_steps=800, step=0.3, seed=0):
+    """FP64 against the mixed-precision move table on the benchmark molecule
+    (16384 walkers, a = 1/28): both projections start from the same
+    Metropolis sample of |Psi|^2 with the same random keys, run `equil`
+    untimed and `gens` timed generations; reported per table the energy with
+    its reblocked error, the wall rate and the smallest effective sample size,
+    and the energy difference.  The random orbitals make these energies a
+    property of this synthetic trial function only, not of a physical
+    system."""
+    import torch
+    from paper_1909_01589_amd import inputs, stats
+    from paper_1909_01589_amd.lrdmc import LRDMC, lrdmc_set_precision, lrdmc_spacing
+    cfg = inputs.get_config("molecule")
+    s, W = cfg.system, cfg.walkers
+    rc, ap, _ = lrdmc_spacing(s.z_max, cfg.a)
+    g = LRDMC(s, cfg.a, ap, rc, cfg.tau, W, seed=cfg.seed, rotate=cfg.rotate, refresh=cfg.refresh)
+    g.set_walkers(inputs.initial_walkers(s, W, seed), 0)
+    g.vmc(vmc_steps, step)
+    pos = g.get_walkers()["pos"].clone()
+    g.close()
+    rows = {}
+    for p in (0, 1):
+        g = LRDMC(s, cfg.a, ap, rc, cfg.tau, W, seed=cfg.seed, rotate=cfg.rotate, refresh=cfg.refresh)
+        lrdmc_set_precision(g.ctx, p)
+        g.set_walkers(pos, 0)
+        g.run(equil)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rec = g.run(gens)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        E, sig = stats.estimate(rec["log_wbar"].cpu().numpy(), rec["ebar"].cpu().numpy(), p=None)
+        rows["fp64" if p == 0 else "mixed"] = dict(E=E, sigma=sig, wall_s=wall,
+                                                   moves_per_s=float(rec["n_moves"].sum()) / wall,
+                                                   ess_min=float(rec["ess"].min()) / W)
+        g.close()
+        print(f"[mixed molecule] precision={p}: E={E:.4f} +- {sig:.4f}, {wall:.1f} s", file=sys.stderr, flush=True)
+    f, m = rows["fp64"], rows["mixed"]
+    return {"mixed_molecule": dict(walkers=W, a=cfg.a, a_prime=ap, tau=cfg.tau, equilibration_generations=equil,
+                                   generations=gens, vmc_steps=vmc_steps, runs=rows,
+                                   energy_difference=m["E"] - f["E"],
+                                   energy_difference_sigma=float(np.hypot(f["sigma"], m["sigma"])),
+                                   speed_ratio=f["wall_s"] / m["wall_s"])}
+
+
 def tsigma_bench(seeds=8, walkers=16384, a=0.035, gens=1000, moves_per_electron=8.0, t_equil=2.0, seed0=0,
                  rounds=8, train_steps=60, lr=1e-3, train_walkers=131072, step=0.25, first_seed=0, runs_out=None):
     """Time to sigma(E) = 1 mHa of four forms of the projection on the same
@@ -1159,6 +1204,8 @@ def main():
                     help="fit the per-run lines of --neural --runs-out files (no GPU) and exit")
     ap.add_argument("--sweep", action="store_true",
                     help="only time every configured workload (Be-like, Ar-like, Z-sweep, molecule) and exit")
+    ap.add_argument("--mixed-molecule", action="store_true",
+                    help="FP64 against the mixed-precision table on the benchmark molecule: energies (JSON on stdout)")
     ap.add_argument("--mixed", action="store_true",
                     help="FP64 against the mixed-precision move table: throughput, energies, time to 1 mHa")
     ap.add_argument("--zscan-phys", action="store_true",
@@ -1229,6 +1276,9 @@ def main():
         return
     if args.mixed:
         print(json.dumps(mixed_bench()), flush=True)
+        return
+    if args.mixed_molecule:
+        print(json.dumps(mixed_molecule()), flush=True)
         return
     if args.zscan_phys:
         print(json.dumps(zscan_phys()), flush=True)
