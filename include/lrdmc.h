@@ -192,7 +192,7 @@ int lrdmc_get_walkers(lrdmc_ctx *ctx, double *pos, double *log_w, double *e_loc,
  * walker slot, res[s] (device [W]) = max |(A Ainv - I)_ik| over both spins,
  * with A recomputed from the walker's current positions and Ainv the inverse
  * stored in its state, carried by rank-one updates since the last refresh
- * (the survey's check of ||A Ainv - I|| after the updates).  After a
+ * (a residual far above rounding means the updates have drifted).  After a
  * reconfiguration slot s reports the walker it selected.  Synchronizes the
  * stream.  Errors: LRDMC_EINVAL (NULL; refresh <= 1 or no projection since the
  * walkers were set, so no state is stored), LRDMC_EDEVICE. */
@@ -353,7 +353,7 @@ int32_t lrdmc_is_specialized(const lrdmc_ctx *ctx);
 
 /* Arithmetic of the move table for later projections and evaluations.
  * mode 0 (default): FP64 throughout.  mode 1 (mixed precision): in the
- * ratios Psi(x')/Psi(x) of the table (S5 of the projection), the Jastrow pair
+ * ratios Psi(x')/Psi(x) of the table, the Jastrow pair
  * terms take 1/r and 1/(1/r + b) from the FP32 hardware estimates (relative
  * error about 2^-22 each) while distances, sums and everything else stay
  * FP64; the local energy, the weights, the Sherman-Morrison updates and the

@@ -29,7 +29,7 @@
  *   "Application to large systems": R_c over the heaviest nuclei only.
  * The rest (stencil, regularized potential, fixed-node rule, continuous-time
  * projection, reconfiguration) is the standard LRDMC the paper cites
- * (Casula, Filippi & Sorella 2005), read as listed in the design notes.
+ * (Casula, Filippi & Sorella 2005).
  */
 #include <math.h>
 #include <stdint.h>

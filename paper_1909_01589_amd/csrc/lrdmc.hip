@@ -1254,7 +1254,8 @@ __device__ __forceinline__ double move_table_points(const KArgs &A, double *lds,
     return part;
 }
 
-// Heat-bath weights of the moves m in [c0, c1) (S1-S6), c0 and c1 even:
+// Heat-bath weights (Eq. (1) with the switch of Eq. (3)) of the moves m in
+// [c0, c1), c0 and c1 even:
 // each step evaluates the +/- pair (m, m + 1) along one axis of one grid of
 // one electron.  Returns the sum of the weights; with diag, stores rho and k
 // and accumulates sum k, L^a and V_sf.
@@ -1359,8 +1360,8 @@ __device__ __forceinline__ double seq_dot(const double *x, const double *y, int 
     return s;
 }
 
-// Update of the walker state after electron k moved from rold to rnew (S8),
-// in three workgroup-wide phases separated by barriers:
+// Update of the walker state after electron k moved from rold to rnew, in
+// three workgroup-wide phases separated by barriers:
 //  1. basis block at r_new; copies of row k of Y and column k of Ainv;
 //     dq = dphi_i . Ainv[:, k] of the other electrons of k's spin; the pair
 //     terms of every other electron i with k (new minus old) into its Jastrow

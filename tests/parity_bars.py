@@ -5,7 +5,7 @@ Indices (moves per generation, heat-bath choices, resampling indices) must be
 bit-exact, except where the oracle's decision margin (its relative distance
 of the threshold to the nearer end of the chosen cumulative interval, or of
 the holding time to the time left) is below TIE: there the summation order
-decides, and the survey's tie rule (C11) accepts either index.  Such ties
+decides, and either index is accepted.  Such ties
 are counted and reported; the trajectories that follow a tie are not
 compared.
 
@@ -20,7 +20,7 @@ import numpy as np
 TIE = 1e-12
 OBSERVED: dict = {}
 
-# FP64 bars (design notes, tolerances).  Generation records (ebar, log wbar):
+# FP64 bars.  Generation records (ebar, log wbar):
 # the 1e-10 Ha target plus about 900 eps |E| for the synthetic atoms whose
 # energies reach thousands of Ha (cancellation in E_L of tight Gaussians).
 # Per-walker E_L (and sum_i lap_i Psi/Psi) relative to 1 + |E_L| (+ |lap|),

@@ -9,7 +9,7 @@ nuclei, four heavy) on whole smaller populations.
 
 Bars: move counts and resampling indices bit-exact up to ties (oracle margin
 below 1e-12, counted); positions 1e-11 bohr; per-walker E_L and log w and the
-generation record as in the design notes; the largest differences seen are
+generation record as in parity_bars; the largest differences seen are
 recorded for the session summary."""
 import numpy as np
 import pytest

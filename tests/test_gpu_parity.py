@@ -1,6 +1,6 @@
 """GPU parity: the HIP projection against the CPU oracle, through the C ABI.
 
-Bars (derived in the design notes):
+Bars:
 * move and reconfiguration indices: bit-exact, except at ties, where the
   oracle's decision margin is below 1e-12 (counted and reported; the
   trajectory after a tie is not compared);

@@ -1,5 +1,5 @@
 """Oracle pins: the energy estimator with correcting factors and its
-blocking error (the survey's reading C7; the paper is silent on both).
+blocking error (the paper states neither).
 
 Correcting factors G_n = prod_{k=0}^{p} wbar_{n-k} (p + 1 factors, the
 generation's own mean weight included), E_p = sum_n G_n ebar_n / sum_n G_n

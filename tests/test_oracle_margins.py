@@ -1,5 +1,5 @@
-"""Oracle pins: the decision margins that judge index parity (the survey's
-tie rule for the heat bath and the resampling, C11).
+"""Oracle pins: the decision margins that judge index parity (the tie rule
+for the heat bath and the resampling).
 
 The oracle reports, for every integer decision, how far the cumulative sums
 would have to move, relative to their total, before the decision changes.  A
