@@ -156,7 +156,9 @@ struct ChainDesc {
     int len;                     // groups (at most 21)
     int code;                    // 1, 2, 3: beta = 2, 2.5, 3; 0: single group
     int mu0;                     // first basis function
-    int pad[3];
+    int n_spd;                   // leading groups with s, p and d shells
+    int n_sp;                    // end of the run of s, p groups that follows
+    int tail0;                   // first group of the trailing run of two or more s-only groups (len: none)
 };
 static_assert(sizeof(ChainDesc) == 64, "chain descriptor size");
 
@@ -437,19 +439,38 @@ __device__ __forceinline__ void chain_step(double &ea, double &eb)
 // (TAIL) a trailing run of at least two s-only groups loads four values at
 // a time (one wait per block instead of one per shell).  Same arithmetic,
 // in the same order, as chain_dot2.
-template <int CODE, bool TAIL>
-__device__ __forceinline__ void chain_dot2_pf(unsigned long long fl, int len, const double *yq, double ax,
-                                              double ay, double az, double bx, double by, double bz, double ea,
-                                              double eb, double &acc_a, double &acc_b)
+template <int CODE, bool TAIL, typename DescPtr>
+__device__ __forceinline__ void chain_dot2_pf(DescPtr D, const double *yq, double ax, double ay,
+                                              double az, double bx, double by, double bz, double ea, double eb,
+                                              double &acc_a, double &acc_b)
 {
     const Ang ga = ang_of(ax, ay, az), gb = ang_of(bx, by, bz);
+    const unsigned long long fl = D->flags;
+    const int len = D->len;
     // first group of the trailing s-only run
-    int q1 = len;
-    if (TAIL) {
-        while (q1 > 0 && ((int)(fl >> (3 * (q1 - 1))) & 7) == 1) --q1;
-        if (len - q1 < 2) q1 = len;
+    const int q1 = TAIL ? D->tail0 : len;
+    // An even-tempered chain starts with its groups of s, p and d shells,
+    // then those of s and p: loops over those runs need no branch on the
+    // flags, and the loads of a group are not behind one.
+    const int n7 = min(D->n_spd, q1), n3 = min(D->n_sp, q1);
+    int q = 0;
+    for (; q < n7; ++q) {
+        double pa, pb;
+        yq += group_dot2<7>(yq, ga, gb, pa, pb);
+        acc_a += ea * pa;
+        acc_b += eb * pb;
+        if (q + 1 == len) return;
+        chain_step<CODE>(ea, eb);
     }
-    for (int q = 0; q < q1; ++q) {
+    for (; q < n3; ++q) {
+        double pa, pb;
+        yq += group_dot2<3>(yq, ga, gb, pa, pb);
+        acc_a += ea * pa;
+        acc_b += eb * pb;
+        if (q + 1 == len) return;
+        chain_step<CODE>(ea, eb);
+    }
+    for (; q < q1; ++q) {
         const int f = (int)(fl >> (3 * q)) & 7;
         double pa = 0.0, pb = 0.0;
         switch (f) {
@@ -511,13 +532,13 @@ __device__ __forceinline__ void basis_dot2(const KArgs &A, const double ra[3], c
         const double *yq = y + D->mu0;
         if constexpr (PF) {
             if (code == 2)
-                chain_dot2_pf<2, TAIL>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+                chain_dot2_pf<2, TAIL>(D, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
             else if (code == 1)
-                chain_dot2_pf<1, TAIL>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+                chain_dot2_pf<1, TAIL>(D, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
             else if (code == 3)
-                chain_dot2_pf<3, TAIL>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+                chain_dot2_pf<3, TAIL>(D, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
             else
-                chain_dot2_pf<0, TAIL>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+                chain_dot2_pf<0, TAIL>(D, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
         } else {
             if (code == 2)
                 chain_dot2<2, TWO>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
@@ -2896,6 +2917,16 @@ int lrdmc_create(const lrdmc_system *sys, const lrdmc_params *prm, int32_t n_wal
             D.len = (int)(e - g);
             D.code = code;
             D.mu0 = grp_mu[g];
+            auto shells = [&](int q) { return (int)(D.flags >> (3 * q)) & 7; };
+            int t = D.len;
+            while (t > 0 && shells(t - 1) == 1) --t;
+            D.tail0 = D.len - t >= 2 ? t : D.len;
+            int a7 = 0;
+            while (a7 < D.len && shells(a7) == 7) ++a7;
+            int a3 = a7;
+            while (a3 < D.len && shells(a3) == 3) ++a3;
+            D.n_spd = a7;
+            D.n_sp = a3;
             chains.push_back(D);
             g = e;
         }
