@@ -330,15 +330,109 @@ __device__ __forceinline__ double shell_dot(const Ang &g, bool s, bool p, bool d
     return t;
 }
 
-// One chain of basis_dot2 with its step code fixed at compile time
-// (e^2.5 = e^2 sqrt(e)); the chain has no branches on the data.  TWO false:
-// the first point only (the b results are not formed).
-template <int CODE, bool TWO = true>
-__device__ __forceinline__ void chain_dot2(unsigned long long fl, int len, const double *yq, double ax,
-                                           double ay, double az, double bx, double by, double bz, double ea,
-                                           double eb, double &acc_a, double &acc_b)
+// One group of chain_dot2 with its shells F fixed at compile time: the sums
+// of shell_dot, shell by shell, as the generic loop of chain_dot2 forms them.
+template <int F, bool TWO>
+__device__ __forceinline__ const double *group_lds(const double *yq, double ax, double ay, double az, double bx,
+                                                   double by, double bz, double &pa, double &pb)
 {
-    for (int q = 0; q < len; ++q) {
+    pa = 0.0;
+    pb = 0.0;
+    if (F & 1) {
+        pa = yq[0];
+        if (TWO) pb = pa;
+        yq += 1;
+    }
+    if (F & 2) {
+        const double y0 = yq[0], y1 = yq[1], y2 = yq[2];
+        pa = fma(ax, y0, pa);
+        pa = fma(ay, y1, pa);
+        pa = fma(az, y2, pa);
+        if (TWO) {
+            pb = fma(bx, y0, pb);
+            pb = fma(by, y1, pb);
+            pb = fma(bz, y2, pb);
+        }
+        yq += 3;
+    }
+    if (F & 4) {
+        const double y0 = yq[0], y1 = yq[1], y2 = yq[2], y3 = yq[3], y4 = yq[4];
+        const Ang ga = ang_of(ax, ay, az);
+        pa = fma(ga.xy, y0, pa);
+        pa = fma(ga.yz, y1, pa);
+        pa = fma(ga.zx, y2, pa);
+        pa = fma(ga.d3, y3, pa);
+        pa = fma(ga.d4, y4, pa);
+        if (TWO) {
+            const Ang gb = ang_of(bx, by, bz);
+            pb = fma(gb.xy, y0, pb);
+            pb = fma(gb.yz, y1, pb);
+            pb = fma(gb.zx, y2, pb);
+            pb = fma(gb.d3, y3, pb);
+            pb = fma(gb.d4, y4, pb);
+        }
+        yq += 5;
+    }
+    return yq;
+}
+
+// Exponential of the next group of a chain from the current one (TWO false:
+// the first point only).
+template <int CODE, bool TWO>
+__device__ __forceinline__ void chain_step(double &ea, double &eb)
+{
+    if (CODE == 3) {
+        ea = ea * ea * ea;
+        if (TWO) eb = eb * eb * eb;
+    } else if (CODE == 2) {
+        const double sa = sqrt_chain(ea), sb = TWO ? sqrt_chain(eb) : 0.0;
+        ea = (ea * ea) * sa;
+        if (TWO) eb = (eb * eb) * sb;
+    } else if (CODE == 1) {
+        ea = ea * ea;
+        if (TWO) eb = eb * eb;
+    }
+}
+
+// One chain of basis_dot2 with its step code fixed at compile time
+// (e^2.5 = e^2 sqrt(e)); the chain has no branches on the data.  The runs
+// of s,p,d groups, s,p groups and trailing s-only groups that the host found
+// in the chain go through loops with the shells fixed; the rest tests each
+// group's flags.  TWO false: the first point only (the b results are not
+// formed).
+template <int CODE, bool TWO, typename DescPtr>
+__device__ __forceinline__ void chain_dot2(DescPtr D, const double *yq, double ax, double ay, double az,
+                                           double bx, double by, double bz, double ea, double eb, double &acc_a,
+                                           double &acc_b)
+{
+    const unsigned long long fl = D->flags;
+    const int len = D->len, n7 = D->n_spd, n3 = D->n_sp, n1 = D->tail0 == n3 ? len : n3;
+    int q0 = 0;
+    for (; q0 < n7; ++q0) {
+        double pa, pb;
+        yq = group_lds<7, TWO>(yq, ax, ay, az, bx, by, bz, pa, pb);
+        acc_a += ea * pa;
+        if (TWO) acc_b += eb * pb;
+        if (q0 + 1 == len) return;
+        chain_step<CODE, TWO>(ea, eb);
+    }
+    for (; q0 < n3; ++q0) {
+        double pa, pb;
+        yq = group_lds<3, TWO>(yq, ax, ay, az, bx, by, bz, pa, pb);
+        acc_a += ea * pa;
+        if (TWO) acc_b += eb * pb;
+        if (q0 + 1 == len) return;
+        chain_step<CODE, TWO>(ea, eb);
+    }
+    for (; q0 < n1; ++q0) {
+        double pa, pb;
+        yq = group_lds<1, TWO>(yq, ax, ay, az, bx, by, bz, pa, pb);
+        acc_a += ea * pa;
+        if (TWO) acc_b += eb * pb;
+        if (q0 + 1 == len) return;
+        chain_step<CODE, TWO>(ea, eb);
+    }
+    for (int q = q0; q < len; ++q) {
         const int f = (int)(fl >> (3 * q)) & 7;
         // shell_dot's sums, shell by shell as the loads arrive
         double pa = 0.0, pb = 0.0;
@@ -380,20 +474,7 @@ __device__ __forceinline__ void chain_dot2(unsigned long long fl, int len, const
         acc_a += ea * pa;
         if (TWO) acc_b += eb * pb;
         if (q + 1 == len) break;
-        if (CODE == 3) {
-            ea = ea * ea * ea;
-            if (TWO) eb = eb * eb * eb;
-        } else if (CODE == 2) {
-            const double sa = sqrt_chain(ea);
-            ea = (ea * ea) * sa;
-            if (TWO) {
-                const double sb = sqrt_chain(eb);
-                eb = (eb * eb) * sb;
-            }
-        } else if (CODE == 1) {
-            ea = ea * ea;
-            if (TWO) eb = eb * eb;
-        }
+        chain_step<CODE, TWO>(ea, eb);
     }
 }
 
@@ -415,23 +496,6 @@ __device__ __forceinline__ int group_dot2(const double *yq, const Ang &ga, const
     pa = shell_dot(ga, F & 1, F & 2, F & 4, v);
     pb = shell_dot(gb, F & 1, F & 2, F & 4, v);
     return od + ((F & 4) ? 5 : 0);
-}
-
-// Exponential of the next group of a chain from the current one.
-template <int CODE>
-__device__ __forceinline__ void chain_step(double &ea, double &eb)
-{
-    if (CODE == 3) {
-        ea = ea * ea * ea;
-        eb = eb * eb * eb;
-    } else if (CODE == 2) {
-        const double sa = sqrt_chain(ea), sb = sqrt_chain(eb);
-        ea = (ea * ea) * sa;
-        eb = (eb * eb) * sb;
-    } else if (CODE == 1) {
-        ea = ea * ea;
-        eb = eb * eb;
-    }
 }
 
 // chain_dot2 with y in device memory: each group's loads issue together at
@@ -460,7 +524,7 @@ __device__ __forceinline__ void chain_dot2_pf(DescPtr D, const double *yq, doubl
         acc_a += ea * pa;
         acc_b += eb * pb;
         if (q + 1 == len) return;
-        chain_step<CODE>(ea, eb);
+        chain_step<CODE, true>(ea, eb);
     }
     for (; q < n3; ++q) {
         double pa, pb;
@@ -468,7 +532,7 @@ __device__ __forceinline__ void chain_dot2_pf(DescPtr D, const double *yq, doubl
         acc_a += ea * pa;
         acc_b += eb * pb;
         if (q + 1 == len) return;
-        chain_step<CODE>(ea, eb);
+        chain_step<CODE, true>(ea, eb);
     }
     for (; q < q1; ++q) {
         const int f = (int)(fl >> (3 * q)) & 7;
@@ -486,7 +550,7 @@ __device__ __forceinline__ void chain_dot2_pf(DescPtr D, const double *yq, doubl
         acc_a += ea * pa;
         acc_b += eb * pb;
         if (q + 1 == len) return;
-        chain_step<CODE>(ea, eb);
+        chain_step<CODE, true>(ea, eb);
     }
     for (int q = q1; q < len; q += 4) {
         const int nb = min(4, len - q);
@@ -499,7 +563,7 @@ __device__ __forceinline__ void chain_dot2_pf(DescPtr D, const double *yq, doubl
             if (j < nb) {
                 acc_a += ea * v[j];
                 acc_b += eb * v[j];
-                if (q + j + 1 < len) chain_step<CODE>(ea, eb);
+                if (q + j + 1 < len) chain_step<CODE, true>(ea, eb);
             }
         }
     }
@@ -527,8 +591,7 @@ __device__ __forceinline__ void basis_dot2(const KArgs &A, const double ra[3], c
         const double a2 = ax * ax + ay * ay + az * az, b2 = bx * bx + by * by + bz * bz;
         const double al0 = D->alpha0;
         const double ea = exp(-al0 * a2), eb = TWO ? exp(-al0 * b2) : 0.0;
-        const unsigned long long fl = D->flags;
-        const int len = D->len, code = D->code;
+        const int code = D->code;
         const double *yq = y + D->mu0;
         if constexpr (PF) {
             if (code == 2)
@@ -541,13 +604,13 @@ __device__ __forceinline__ void basis_dot2(const KArgs &A, const double ra[3], c
                 chain_dot2_pf<0, TAIL>(D, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
         } else {
             if (code == 2)
-                chain_dot2<2, TWO>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+                chain_dot2<2, TWO>(D, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
             else if (code == 1)
-                chain_dot2<1, TWO>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+                chain_dot2<1, TWO>(D, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
             else if (code == 3)
-                chain_dot2<3, TWO>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+                chain_dot2<3, TWO>(D, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
             else
-                chain_dot2<0, TWO>(fl, len, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
+                chain_dot2<0, TWO>(D, yq, ax, ay, az, bx, by, bz, ea, eb, acc_a, acc_b);
         }
     }
     out_a = acc_a;
