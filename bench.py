@@ -1052,7 +1052,8 @@ def population_scan(name, walker_counts, steps, warmup, gens=20):
     rc, ap, _ = lrdmc_spacing(s.z_max, cfg.a)
     gpu = LRDMC(s, cfg.a, ap, rc, cfg.tau, cfg.walkers, seed=cfg.seed, rotate=cfg.rotate, refresh=cfg.refresh)
     gpu.set_walkers(inputs.initial_walkers(s, cfg.walkers, cfg.seed), 0)
-    gpu.run(warmup)
+    if warmup:
+        gpu.run(warmup)
     disp, mx, corr, prev = [], [], [], None
     for _ in range(gens):
         gpu.project()
