@@ -170,3 +170,18 @@ def test_neural_summary_ratios_and_limits():
     assert out["lrdmc"]["neural"]["E0"] == pytest.approx(-2.8, abs=1e-12)
     assert out["E0_difference"] == pytest.approx(0.1, abs=1e-12)
     assert out["time_to_1mHa_ratio_pade_over_neural"] == pytest.approx({"0.3": 3.0, "0.2": 2.0, "0.1": 2.0}, rel=1e-14)
+
+
+def test_traffic_record_follows_the_source_hash(monkeypatch):
+    """The bench line's HBM traffic comes from the committed counter record
+    only while the kernel sources hash to the recorded value; any other
+    hash gives None (the counters no longer describe the kernel)."""
+    import re
+    text = open(bench.os.path.join(bench.ROOT, "profiles", "traffic_project_kernel.md")).read()
+    recorded = re.search(r"^source_sha256 = ([0-9a-f]{64})$", text, re.M).group(1)
+    mol = float(re.search(r"^molecule bytes_per_launch = ([0-9.eE+]+)$", text, re.M).group(1))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: recorded)
+    assert bench._traffic_record("molecule") == mol > 0
+    assert bench._traffic_record("no_such_workload") is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 64)
+    assert bench._traffic_record("molecule") is None
